@@ -1,0 +1,112 @@
+/*
+ * Plain FP64 CPU oracle for the parabolic relaxation model II of the
+ * isothermal Navier-Stokes-Korteweg equations (Hitz, Keim, Munz, Rohde,
+ * "A Parabolic Relaxation Model for the Navier-Stokes-Korteweg Equations").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the checker that the GPU path is
+ * compared against.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it.  It shares no code, header, table or
+ * generator with the HIP library; the two are written independently.
+ *
+ * Every function follows a passage of the paper (cited by section and
+ * equation) and is written for a reader who checks it against the paper by
+ * eye: straight loops, no blocking, no fusion.
+ *
+ * State layout shared with the caller (not with the GPU code): U[var][elem][node]
+ *   var  = 0 rho, 1..dim momentum rho*v_d, dim+1 relaxation variable c
+ *   elem = ex + nel0*(ey + nel1*ez)       (x fastest)
+ *   node = i + (N+1)*(j + (N+1)*k)        (xi_1 fastest)
+ */
+#ifndef NSK_ORACLE_H
+#define NSK_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------- 1D basis on Gauss-Legendre nodes (Sec. 3.1) -------------- */
+#define OR_NMAX 12
+typedef struct {
+  int N;                         /* polynomial degree                            */
+  double xi[OR_NMAX + 1];        /* Gauss-Legendre nodes on [-1,1], ascending   */
+  double w[OR_NMAX + 1];         /* quadrature weights                           */
+  double D[OR_NMAX + 1][OR_NMAX + 1];    /* D[i][j] = l_j'(xi_i)                 */
+  double Dhat[OR_NMAX + 1][OR_NMAX + 1]; /* weak-form operator w_j/w_i * D[j][i] */
+  double Lm[OR_NMAX + 1];        /* l_j(-1)                                      */
+  double Lp[OR_NMAX + 1];        /* l_j(+1)                                      */
+} or_basis;
+
+int or_make_basis(int N, or_basis* b);
+
+/* ---------------- Van-der-Waals thermodynamics (Sec. 2.1) ------------------ */
+double or_W(double T, double rho);      /* Helmholtz free energy density         */
+double or_dW(double T, double rho);     /* chemical potential W'(rho)            */
+double or_p(double T, double rho);      /* pressure rho W' - W                   */
+double or_dp(double T, double rho);     /* p'(rho) = rho W''(rho)                */
+double or_d2W(double T, double rho);    /* W''(rho)                              */
+/* Maxwell construction: equal pressure and equal chemical potential. */
+int or_maxwell(double T, double* rho_v, double* rho_l, double* p_sat, double* mu_sat);
+/* Spinodal densities: the two zeros of p'(rho). */
+int or_spinodal(double T, double* rho_sv, double* rho_sl);
+/* Integral of sqrt(2 (W - mu_sat rho + p_sat)) over [rho_v, rho_l]; the planar
+ * gradient-theory surface tension is sqrt(kappa) times this number. */
+double or_surface_integral(double T);
+/* Young-Laplace initial densities for a spherical droplet (Sec. 4.3.1). */
+int or_young_laplace(double T, double sigma, double r, double* rho_l, double* rho_v);
+
+/* ---------------- low-storage Runge-Kutta (Sec. 3.1) ----------------------- */
+/* Carpenter-Kennedy five-stage fourth-order 2N-storage scheme. */
+void or_lsrk45(double A[5], double B[5], double C[5]);
+/* Stability polynomial R(z) = sum_k g[k] z^k of the scheme (k = 0..5). */
+void or_lsrk_stability_poly(double g[6]);
+/* Largest x such that |R(-y)| <= 1 for all y in [0, x] (bisection). */
+double or_lsrk_real_limit(void);
+
+/* ---------------- DGSEM operator for relaxation model II ------------------- */
+typedef struct {
+  int dim;                 /* 1, 2 or 3                                       */
+  int N;                   /* polynomial degree                               */
+  int nel[3];              /* elements per direction (unused dims: 1)         */
+  const double* xb[3];     /* breakpoints per direction, nel[d]+1 values      */
+  double T;                /* temperature                                     */
+  double eps;              /* viscosity 1/Re                                  */
+  double kappa;            /* eps^2 gamma: coefficient of the Laplacian of c  */
+  double alpha, beta;      /* relaxation parameters                           */
+  int diss_c;              /* 1: Rusanov dissipation also on c                */
+} or_prob;
+
+/* Optional forcing added to the right-hand side at time t (manufactured
+ * solutions).  F has the layout of U. */
+typedef void (*or_forcing_fn)(double t, double* F, void* user);
+
+long or_nelem(const or_prob* P);
+int or_nnode(const or_prob* P);
+
+/* Weak-form DGSEM right-hand side R = dU/dt (eqs. for the weak form and the
+ * semi-discrete scheme of Sec. 3.1, BR1 lifting of the primitives).
+ * Q (optional, may be NULL) receives the lifted gradients, layout
+ * Q[d][k][elem][node] with k over (v_1..v_dim, c).  Returns 0 on success. */
+int or_rhs_weak(const or_prob* P, const double* U, double* R, double* Q);
+/* The same semi-discretisation written in strong form (independent code). */
+int or_rhs_strong(const or_prob* P, const double* U, double* R);
+
+/* LSRK4(5) integration in place: nsteps steps of size dt, from time t0. */
+int or_run(const or_prob* P, double* U, double dt, int nsteps, double t0,
+           or_forcing_fn f, void* user);
+
+/* Time step rule: CFL * min(convective, viscous, relaxation-source) bound. */
+double or_dt(const or_prob* P, const double* U, double cfl);
+
+/* Diagnostics: out[0..nvar-1] = integral of each conserved variable,
+ * out[7] kinetic energy, out[8] total energy E^alpha, out[9] L2 norm of rho-c,
+ * out[10] rho min, out[11] rho max, out[12] max wave speed, out[13] number of
+ * non-finite values.  out must hold 16 doubles. */
+int or_diagnostics(const or_prob* P, const double* U, double* out);
+
+/* Nodal coordinates (for tests): X[d][elem][node]. */
+int or_node_coords(const or_prob* P, double* X);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
