@@ -1,0 +1,227 @@
+"""Benchmark: DOF-stage updates per second of the explicit DGSEM right-hand
+side plus low-storage Runge-Kutta update for relaxation model II, on one GPU.
+
+A step is one full five-stage Runge-Kutta step over the whole mesh (lifting,
+volume and surface integrals, source and update in every stage).  The default
+workload is the 3D head-on droplet collision: periodic box [0,2]x[0,1]^2,
+96x48x48 elements, N = 4 (27,648,000 nodes, 5 variables), alpha = 1000,
+beta = 1e-3, eps = 1e-3, kappa = 1e-5, We = 100, FP64.  Inputs are generated
+once on the host and are resident in HBM before the timed region starts.
+
+Prints ONE JSON line.  Fields beyond the common contract:
+  roofline      dominant kernel (right-hand side + stage update): algorithmic
+                bytes per launch / its mean duration from HIP events recorded
+                on the bound stream during the timed steps, against 8 TB/s
+  cpu_baseline  the CPU oracle timed on a bounded sample of the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+REPO = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, REPO)
+
+METRIC = "DOF-stage updates/s (DG RHS+RK) plain FP64 vs closure/mixed at fixed L2 error"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (builder kwargs, physics)
+    "3d-collision": dict(dim=3, nel=(96, 48, 48), N=4, lo=(0.0, 0.0, 0.0), hi=(2.0, 1.0, 1.0), We=100.0,
+                         alpha=1000.0),
+    "2d-droplets": dict(dim=2, nel=(96, 96), N=4, lo=(0.0, 0.0), hi=(1.0, 1.0), alpha=2000.0),
+}
+
+
+def bytes_per_node(dim: int, stage_first: bool, mixed: bool) -> dict:
+    """Algorithmic HBM bytes per node of each kernel of one stage.
+    lift: read U (nvar words), write G (tau + grad c: dim(dim+1)/2 + dim).
+    rhs : read U and G, read the register dU (not in the first stage, whose
+          coefficient A is zero), write U_new and dU."""
+    nvar = dim + 2
+    ng = dim * (dim + 1) // 2 + dim
+    gw = 4 if mixed else 8
+    lift = 8 * nvar + gw * ng
+    rhs = 8 * nvar + gw * ng + (0 if stage_first else 8 * nvar) + 16 * nvar
+    return {"lift": lift, "rhs": rhs}
+
+
+def build_state(name: str):
+    from paper_1912_12059_amd import inputs as I
+
+    w = WORKLOADS[name]
+    if w["dim"] == 3:
+        return I.collision_3d(nel=w["nel"], N=w["N"], We=w["We"], lo=w["lo"], hi=w["hi"])
+    return I.droplets_2d(nel=w["nel"][0], N=w["N"])
+
+
+def sample_block(U, nel, block):
+    """Elements of the sub-box [x0, x0+bx) x [y0, y0+by) x [z0, z0+bz) of a
+    state U[var][elem][node] (x-fastest element order), as a new state."""
+    import numpy as np
+
+    dim = len(nel)
+    rng = [np.arange(b0, b0 + nb) for b0, nb in block]
+    if dim == 3:
+        ez, ey, ex = np.meshgrid(rng[2], rng[1], rng[0], indexing="ij")
+        idx = (ex + nel[0] * (ey + nel[1] * ez)).reshape(-1)
+    else:
+        ey, ex = np.meshgrid(rng[1], rng[0], indexing="ij")
+        idx = (ex + nel[0] * ey).reshape(-1)
+    return np.ascontiguousarray(U[:, idx, :])
+
+
+def cpu_baseline(name: str, sample, sub, budget_s: float = 20.0):
+    """Time the CPU oracle (as it stands) on a bounded sample: a block of
+    elements cut out of the same initial state, treated as a periodic box with
+    the same element size, degree and physics; full LSRK4(5) steps; rate in
+    DOF-stage updates per second."""
+    from oracle import oracle as O
+
+    w = WORKLOADS[name]
+    dim = w["dim"]
+    h = [(w["hi"][d] - w["lo"][d]) / w["nel"][d] for d in range(dim)]
+    nel3 = tuple(sub) + (1,) * (3 - dim)
+    hi3 = tuple(sub[d] * h[d] for d in range(dim)) + (1.0,) * (3 - dim)
+    P = O.Problem(dim=dim, N=w["N"], nel=nel3, lo=(0, 0, 0), hi=hi3, alpha=w["alpha"], beta=1e-3, eps=1e-3,
+                  kappa=1e-5)
+    dt = O.dt(P, sample, 0.5)
+    t0 = time.perf_counter()
+    O.run(P, sample, dt, 1)
+    first = time.perf_counter() - t0
+    steps = int(min(20, max(1, budget_s // max(first, 1e-3))))
+    t0 = time.perf_counter()
+    O.run(P, sample, dt, steps)
+    el = time.perf_counter() - t0
+    dofs = sample.shape[1] * sample.shape[2]
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": dofs * 5 * steps / el,
+        "unit": "DOF-stage/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{'x'.join(map(str, sub))}-element block of the same initial state (periodic, same "
+                  f"element size, N={w['N']} and physics), {steps} LSRK4(5) steps in {el:.1f} s",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--workload", default="3d-collision", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", default="auto", help="auto (autotuner) or 'variant,remap', e.g. 0,1")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1912_12059_amd import nsk
+
+    w = WORKLOADS[args.workload]
+    mixed = args.precision == "mixed"
+    print(f"[bench] building {args.workload} state", file=sys.stderr, flush=True)
+    m, U = build_state(args.workload)
+    s = nsk.Solver(dim=m.dim, N=m.N, nel=tuple(m.nel), lo=tuple(m.lo), hi=tuple(m.hi), alpha=w["alpha"],
+                   beta=1e-3, eps=1e-3, kappa=1e-5, precision=1 if mixed else 0)
+    s.set_state(torch.from_numpy(U.reshape(-1)))
+    if m.dim == 3:
+        sub = (16, 16, 16)
+        block = ((24, 16), (16, 16), (16, 16))  # around the first droplet's interface
+    else:
+        sub = (32, 32)
+        block = ((16, 32), (32, 32))
+    sample = None if args.no_cpu_baseline else sample_block(U, m.nel, block)
+    del U
+    dt = s.dt_estimate(0.5)
+    if args.tile == "auto":
+        variant, remap, tune_ms = nsk.nsk_autotune(s.ctx, 3)
+    else:
+        variant, remap = (int(x) for x in args.tile.split(","))
+        nsk.nsk_set_tile(s.ctx, variant, remap)
+        tune_ms = None
+    print(f"[bench] tile variant={variant} xcd_remap={remap} tune_ms={tune_ms}", file=sys.stderr, flush=True)
+    print(f"[bench] dt={dt:.4e}, warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    s.rk_step(dt, args.warmup)
+    torch.cuda.synchronize()
+    nsk.nsk_timing_enable(s.ctx, 1)
+    dev = torch.device("cuda:0")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s.stream)
+    t0 = time.perf_counter()
+    s.rk_step(dt, args.steps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    ms_lift, ms_rhs, nst = nsk.nsk_timing_read(s.ctx)
+    nsk.nsk_timing_enable(s.ctx, 0)
+    diag = s.diagnostics()
+    dofs = m.nelem * m.nnode
+    rate = dofs * 5 * args.steps / (ms * 1e-3)
+    bp_first = bytes_per_node(m.dim, True, mixed)
+    bp = bytes_per_node(m.dim, False, mixed)
+    # average algorithmic bytes per launch of the rhs kernel over the 5 stages
+    rhs_bytes = dofs * (bp_first["rhs"] + 4 * bp["rhs"]) / 5.0
+    lift_bytes = dofs * bp["lift"]
+    avg_rhs_ms = ms_rhs / max(nst, 1)
+    avg_lift_ms = ms_lift / max(nst, 1)
+    achieved = rhs_bytes / (avg_rhs_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": rate,
+        "unit": "DOF-stage/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if not mixed else "f64-state/f32-flux",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload} {'x'.join(map(str, m.nel))} N={m.N} alpha={w['alpha']:g} beta=1e-3 "
+                        f"eps=1e-3 kappa=1e-5" + (f" We={w['We']:g}" if "We" in w else ""),
+            "dofs": dofs,
+            "nvar": m.nvar,
+            "precision": args.precision,
+            "dt": dt,
+            "tile": {"variant": variant, "xcd_remap": remap, "autotune_ms": tune_ms},
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "rhs_kernel (volume+surface+source+RK stage)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_ms": avg_rhs_ms,
+            "lift_avg_ms": avg_lift_ms,
+            "lift_achieved_GBs": lift_bytes / (avg_lift_ms * 1e-3) / 1e9 if avg_lift_ms > 0 else None,
+            "stage_bytes_per_node": (bp["lift"] + bp["rhs"]),
+            "stage_GBs": dofs * (bp["lift"] + bp["rhs"]) / ((avg_rhs_ms + avg_lift_ms) * 1e-3) / 1e9,
+        },
+        "diag_after": {"mass_rho": diag["mass"][0], "e_total": diag["e_total"], "status": diag["status"]},
+        "wall_s": wall,
+    }
+    s.close()
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.workload, sample, sub)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,651 @@
+// libnsk host side: the C ABI declared in include/nsk.h.
+//
+// Builds the 1D Gauss-Legendre basis and the geometry on the host, lays out
+// the caller-provided workspace, and enqueues the kernels of dg_kernels.hpp on
+// the bound stream.  No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/nsk.h"
+#include "dg_kernels.hpp"
+
+using namespace nsk;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// 1D basis (Sec. 3.1): nodes are the roots of P_{N+1}; for Gauss nodes the
+// derivative matrix has the closed form
+//   D_ij = P'(x_i) / (P'(x_j) (x_i - x_j))  (i != j),   D_ii = x_i / (1 - x_i^2)
+// and the weights are 2 / ((1 - x_i^2) P'(x_i)^2).
+// ---------------------------------------------------------------------------
+struct Basis1D {
+  int np;
+  double x[kMaxNP], w[kMaxNP], D[kMaxNP][kMaxNP], Dhat[kMaxNP][kMaxNP], Lm[kMaxNP], Lp[kMaxNP];
+};
+
+void legendre_eval(int n, long double x, long double& P, long double& dP) {
+  // upward recurrence for P_k and P_k' together
+  long double pm = 1.0L, p = x, dpm = 0.0L, dp = 1.0L;
+  if (n == 0) { P = 1.0L; dP = 0.0L; return; }
+  for (int k = 1; k < n; ++k) {
+    long double pn = ((2 * k + 1) * x * p - k * pm) / (k + 1);
+    long double dpn = dpm + (2 * k + 1) * p;  // P'_{k+1} = P'_{k-1} + (2k+1) P_k
+    pm = p; p = pn;
+    dpm = dp; dp = dpn;
+  }
+  P = p;
+  dP = dp;
+}
+
+void make_basis(int N, Basis1D& b) {
+  const int n = N + 1;
+  b.np = n;
+  long double x[kMaxNP], dPx[kMaxNP];
+  for (int i = 0; i < n; ++i) {
+    // ascending roots; initial guess from the asymptotic formula
+    long double z = std::cos(3.141592653589793238462643383279L * (n - i - 0.25L) / (n + 0.5L));
+    for (int it = 0; it < 60; ++it) {
+      long double P, dP;
+      legendre_eval(n, z, P, dP);
+      long double step = P / dP;
+      z -= step;
+      if (std::fabs((double)step) < 1e-20) break;
+    }
+    long double P, dP;
+    legendre_eval(n, z, P, dP);
+    x[i] = z;
+    dPx[i] = dP;
+  }
+  for (int i = 0; i < n; ++i) {
+    b.x[i] = (double)x[i];
+    b.w[i] = (double)(2.0L / ((1.0L - x[i] * x[i]) * dPx[i] * dPx[i]));
+  }
+  long double D[kMaxNP][kMaxNP];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      D[i][j] = (i == j) ? x[i] / (1.0L - x[i] * x[i]) : dPx[i] / (dPx[j] * (x[i] - x[j]));
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      b.D[i][j] = (double)D[i][j];
+      long double wi = 2.0L / ((1.0L - x[i] * x[i]) * dPx[i] * dPx[i]);
+      long double wj = 2.0L / ((1.0L - x[j] * x[j]) * dPx[j] * dPx[j]);
+      b.Dhat[i][j] = (double)(wj / wi * D[j][i]);
+    }
+  // Lagrange polynomials at the ends: l_j(s) = P(s) / (P'(x_j) (s - x_j))
+  for (int j = 0; j < n; ++j) {
+    long double Pp, dPp, Pm, dPm;
+    legendre_eval(n, 1.0L, Pp, dPp);
+    legendre_eval(n, -1.0L, Pm, dPm);
+    b.Lp[j] = (double)(Pp / (dPx[j] * (1.0L - x[j])));
+    b.Lm[j] = (double)(Pm / (dPx[j] * (-1.0L - x[j])));
+  }
+}
+
+// Carpenter-Kennedy 2N-storage RK4(5) (the five-stage fourth-order
+// low-storage scheme of Sec. 3.1).
+const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                        -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                        1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                        2277821191437.0 / 14882151754819.0};
+
+// Negative-real-axis stability limit: apply one step to y' = -x y and find
+// the first x where the amplification exceeds one.
+double rk_amplification(double x) {
+  double y = 1.0, k = 0.0;
+  for (int s = 0; s < 5; ++s) {
+    k = kRkA[s] * k + (-x) * y;
+    y += kRkB[s] * k;
+  }
+  return std::fabs(y);
+}
+
+double rk_real_limit() {
+  double lo = 0.0;
+  while (rk_amplification(lo + 0.01) <= 1.0) lo += 0.01;
+  double hi = lo + 0.01;
+  for (int it = 0; it < 100; ++it) {
+    double m = 0.5 * (lo + hi);
+    (rk_amplification(m) <= 1.0 ? lo : hi) = m;
+  }
+  return lo;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct nsk_ctx {
+  nsk_mesh mesh;
+  nsk_params par;
+  int dim = 0, N = 0, np = 0, nn = 0, nvar = 0, ng = 0;
+  int nel[3] = {1, 1, 1};
+  long long E = 0, S = 0;
+  std::vector<double> h2[3];  // 2/h per element index
+  Basis1D basis;
+  double zR = 0.0;
+  double rho_lo64 = 0.0, rho_hi64 = 0.0;
+  // workspace layout (byte offsets)
+  size_t off_U2 = 0, off_G = 0, off_h2[3] = {0, 0, 0}, off_wq = 0, off_part = 0, off_out = 0, ws_bytes = 0;
+  int diag_blocks = 0;
+  int tile = 0;      // elements-per-workgroup variant (0 or 1)
+  int nxcd = 8;      // XCDs the block order is spread over (1 = hardware order)
+  // bound memory
+  bool bound = false;
+  double* U = nullptr;
+  double* dU = nullptr;
+  char* work = nullptr;
+  hipStream_t stream = nullptr;
+  int cur = 0;  // 0: state in U, 1: state in the workspace copy
+  // optional kernel timing
+  std::vector<hipEvent_t> events;  // 3 per timed stage
+  int timed = 0;                   // stages recorded since the last read
+};
+
+namespace {
+
+int check_params(const nsk_params* p) {
+  if (!p) return NSK_EINVAL;
+  if (!(p->T > 0.0 && p->T < 1.0)) return NSK_EINVAL;
+  if (!(p->alpha > 0.0) || !(p->beta > 0.0) || !(p->eps >= 0.0) || !(p->kappa >= 0.0)) return NSK_EINVAL;
+  if (p->flux != 0 || p->closure != 0) return NSK_EINVAL;
+  if (p->precision != 0 && p->precision != 1) return NSK_EINVAL;
+  if (p->diss_c != 0 && p->diss_c != 1) return NSK_EINVAL;
+  return NSK_OK;
+}
+
+// spinodal band of the reduced Van-der-Waals isotherm, widened by 0.05:
+// the mixed-precision path evaluates the EoS in FP64 inside it
+void spinodal_band(double T, double& lo, double& hi) {
+  auto dp = [T](double r) { return 24.0 * T / ((3.0 - r) * (3.0 - r)) - 6.0 * r; };
+  auto root = [&](double a, double b) {
+    bool sa = dp(a) < 0;
+    for (int i = 0; i < 200; ++i) {
+      double m = 0.5 * (a + b);
+      ((dp(m) < 0) == sa ? a : b) = m;
+    }
+    return 0.5 * (a + b);
+  };
+  lo = root(1e-6, 1.0) - 0.05;
+  hi = root(1.0, 3.0 - 1e-9) + 0.05;
+}
+
+BasisArgs basis_args(const nsk_ctx* c) {
+  BasisArgs b;
+  std::memset(&b, 0, sizeof(b));
+  for (int i = 0; i < c->np; ++i) {
+    for (int j = 0; j < c->np; ++j) b.Dhat[i][j] = c->basis.Dhat[i][j];
+    b.Lm[i] = c->basis.Lm[i];
+    b.Lp[i] = c->basis.Lp[i];
+    b.invw[i] = 1.0 / c->basis.w[i];
+  }
+  return b;
+}
+
+MeshArgs mesh_args(const nsk_ctx* c) {
+  MeshArgs m;
+  for (int d = 0; d < 3; ++d) {
+    m.h2[d] = reinterpret_cast<const double*>(c->work + c->off_h2[d]);
+    m.nel[d] = c->nel[d];
+  }
+  m.E = (int)c->E;
+  m.S = c->S;
+  m.nxcd = c->nxcd;
+  return m;
+}
+
+PhysArgs phys_args(const nsk_ctx* c) {
+  PhysArgs p;
+  p.T = c->par.T;
+  p.eps = c->par.eps;
+  p.kappa = c->par.kappa;
+  p.alpha = c->par.alpha;
+  p.beta = c->par.beta;
+  p.kb = c->par.kappa / c->par.beta;
+  p.ab = c->par.alpha / c->par.beta;
+  p.diss_c = c->par.diss_c;
+  p.rho_lo64 = c->rho_lo64;
+  p.rho_hi64 = c->rho_hi64;
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// Launch dispatch over (dim, N, precision)
+// ---------------------------------------------------------------------------
+// events of the next timed stage, or nullptr when timing is off or full
+hipEvent_t* stage_events(nsk_ctx* c, const StageArgs& st) {
+  if (st.mode != 1 || c->events.empty() || 3 * (size_t)(c->timed + 1) > c->events.size()) return nullptr;
+  return &c->events[3 * (size_t)c->timed++];
+}
+
+// Elements per workgroup: variant 0 fills about 256 threads, variant 1
+// doubles it where the LDS of the right-hand-side kernel stays within 64 KB.
+template <int DIM, int NP>
+struct Epb {
+  using Sh = Shape<DIM, NP>;
+  static constexpr int A = cmax(1, 256 / cmax(Sh::NN, 2 * DIM * Sh::NF));
+  template <typename R>
+  static constexpr int rhs_lds(int epb) {
+    return (int)sizeof(R) * epb * ((Sh::NVAR + Sh::NG) * Sh::NN + Sh::NVAR * Sh::NN + DIM * 2 * Sh::NVAR * Sh::NF) +
+           (sizeof(R) == 4 ? 8 * epb * Sh::NN : 8) + 1024;
+  }
+  static constexpr bool B_OK = rhs_lds<double>(2 * A) <= 65536;
+  static constexpr int B = B_OK ? 2 * A : A;
+};
+
+template <int DIM, int NP, int EPB, typename R, typename GT>
+int launch_stage_e(nsk_ctx* c, const double* Uin, double* Uout, double* dU, const StageArgs& st) {
+  using Tl = Tile<DIM, NP, EPB>;
+  const BasisArgs b = basis_args(c);
+  const MeshArgs m = mesh_args(c);
+  const PhysArgs p = phys_args(c);
+  GT* G = reinterpret_cast<GT*>(c->work + c->off_G);
+  const unsigned blocks = (unsigned)((c->E + EPB - 1) / EPB);
+  hipEvent_t* ev = stage_events(c, st);
+  if (ev) (void)hipEventRecord(ev[0], c->stream);
+  hipLaunchKernelGGL((lift_kernel<DIM, NP, EPB, R, GT>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream, Uin, G, b, m,
+                     p);
+  if (ev) (void)hipEventRecord(ev[1], c->stream);
+  hipLaunchKernelGGL((rhs_kernel<DIM, NP, EPB, R, GT>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream, Uin, G, Uout,
+                     dU, b, m, p, st);
+  if (ev) (void)hipEventRecord(ev[2], c->stream);
+  return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
+}
+
+template <int DIM, int NP, typename R, typename GT>
+int launch_stage_t(nsk_ctx* c, const double* Uin, double* Uout, double* dU, const StageArgs& st) {
+  if (c->tile == 1 && Epb<DIM, NP>::B_OK)
+    return launch_stage_e<DIM, NP, Epb<DIM, NP>::B, R, GT>(c, Uin, Uout, dU, st);
+  return launch_stage_e<DIM, NP, Epb<DIM, NP>::A, R, GT>(c, Uin, Uout, dU, st);
+}
+
+template <int DIM, int NP, typename GT>
+int launch_diag_t(nsk_ctx* c, const double* Uin) {
+  constexpr int EPB = Epb<DIM, NP>::A;
+  using Tl = Tile<DIM, NP, EPB>;
+  const BasisArgs b = basis_args(c);
+  const MeshArgs m = mesh_args(c);
+  const PhysArgs p = phys_args(c);
+  GT* G = reinterpret_cast<GT*>(c->work + c->off_G);
+  const unsigned blocks = (unsigned)((c->E + EPB - 1) / EPB);
+  using R = GT;
+  hipLaunchKernelGGL((lift_kernel<DIM, NP, EPB, R, GT>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream, Uin, G, b, m,
+                     p);
+  double* part = reinterpret_cast<double*>(c->work + c->off_part);
+  double* out = reinterpret_cast<double*>(c->work + c->off_out);
+  const double* wq = reinterpret_cast<const double*>(c->work + c->off_wq);
+  hipLaunchKernelGGL((diag_partial_kernel<DIM, NP, GT>), dim3(c->diag_blocks), dim3(kDiagThreads), 0, c->stream, Uin,
+                     G, part, wq, m, p);
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(kDiagThreads), 0, c->stream, part, c->diag_blocks, out);
+  return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
+}
+
+template <int DIM, int NP>
+int dispatch_prec(nsk_ctx* c, int what, const double* Uin, double* Uout, double* dU, const StageArgs& st) {
+  if (c->par.precision == 0) {
+    if (what == 0) return launch_stage_t<DIM, NP, double, double>(c, Uin, Uout, dU, st);
+    return launch_diag_t<DIM, NP, double>(c, Uin);
+  }
+  if (what == 0) return launch_stage_t<DIM, NP, float, float>(c, Uin, Uout, dU, st);
+  return launch_diag_t<DIM, NP, float>(c, Uin);
+}
+
+template <int DIM>
+int dispatch_np(nsk_ctx* c, int what, const double* Uin, double* Uout, double* dU, const StageArgs& st) {
+  switch (c->np) {
+    case 2: return dispatch_prec<DIM, 2>(c, what, Uin, Uout, dU, st);
+    case 3: return dispatch_prec<DIM, 3>(c, what, Uin, Uout, dU, st);
+    case 4: return dispatch_prec<DIM, 4>(c, what, Uin, Uout, dU, st);
+    case 5: return dispatch_prec<DIM, 5>(c, what, Uin, Uout, dU, st);
+    case 6: return dispatch_prec<DIM, 6>(c, what, Uin, Uout, dU, st);
+    case 7:
+      if constexpr (DIM < 3) return dispatch_prec<DIM, 7>(c, what, Uin, Uout, dU, st);
+      break;
+  }
+  return NSK_EUNSUPPORTED;
+}
+
+// what = 0: one stage (lift + rhs), what = 1: diagnostics
+int dispatch(nsk_ctx* c, int what, const double* Uin, double* Uout, double* dU, const StageArgs& st) {
+  switch (c->dim) {
+    case 1: return dispatch_np<1>(c, what, Uin, Uout, dU, st);
+    case 2: return dispatch_np<2>(c, what, Uin, Uout, dU, st);
+    case 3: return dispatch_np<3>(c, what, Uin, Uout, dU, st);
+  }
+  return NSK_EUNSUPPORTED;
+}
+
+double* state_buf(nsk_ctx* c, int which) {
+  return which == 0 ? c->U : reinterpret_cast<double*>(c->work + c->off_U2);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nsk_strerror(int code) {
+  switch (code) {
+    case NSK_OK: return "ok";
+    case NSK_EINVAL: return "invalid mesh, parameters or argument";
+    case NSK_ENONPHYS: return "non-physical state (non-finite value or density outside (0,3))";
+    case NSK_EHIP: return "HIP runtime error";
+    case NSK_EUNBOUND: return "device memory not bound";
+    case NSK_EUNSUPPORTED: return "unsupported dimension/degree";
+  }
+  return "unknown error";
+}
+
+int nsk_create(const nsk_mesh* mesh, const nsk_params* params, nsk_ctx** out) {
+  if (!mesh || !out) return NSK_EINVAL;
+  *out = nullptr;
+  if (mesh->dim < 1 || mesh->dim > 3 || mesh->N < 1 || mesh->N > kMaxNP - 1) return NSK_EINVAL;
+  if (mesh->dim == 3 && mesh->N > 5) return NSK_EUNSUPPORTED;  // LDS of one 3D element above 64 KB
+  int rc = check_params(params);
+  if (rc) return rc;
+  nsk_ctx* c = new (std::nothrow) nsk_ctx();
+  if (!c) return NSK_EINVAL;
+  c->mesh = *mesh;
+  c->par = *params;
+  c->dim = mesh->dim;
+  c->N = mesh->N;
+  c->np = mesh->N + 1;
+  c->nn = 1;
+  for (int d = 0; d < c->dim; ++d) c->nn *= c->np;
+  c->nvar = c->dim + 2;
+  c->ng = c->dim * (c->dim + 1) / 2 + c->dim;
+  c->E = 1;
+  for (int d = 0; d < 3; ++d) {
+    c->mesh.xbreaks[d] = nullptr;  // not kept: copied into h2 below
+    if (d >= c->dim) {
+      c->nel[d] = 1;
+      c->h2[d].assign(1, 1.0);
+      continue;
+    }
+    if (mesh->nel[d] < 1 || mesh->nel[d] > (1 << 20)) { delete c; return NSK_EINVAL; }
+    c->nel[d] = mesh->nel[d];
+    c->E *= c->nel[d];
+    c->h2[d].resize(c->nel[d]);
+    for (int k = 0; k < c->nel[d]; ++k) {
+      double a, b;
+      if (mesh->xbreaks[d]) {
+        a = mesh->xbreaks[d][k];
+        b = mesh->xbreaks[d][k + 1];
+      } else {
+        const double L = mesh->hi[d] - mesh->lo[d];
+        a = mesh->lo[d] + L * k / c->nel[d];
+        b = mesh->lo[d] + L * (k + 1) / c->nel[d];
+      }
+      if (!(b > a) || !std::isfinite(a) || !std::isfinite(b)) { delete c; return NSK_EINVAL; }
+      c->h2[d][k] = 2.0 / (b - a);
+    }
+  }
+  c->S = c->E * c->nn;
+  if (c->E > (1LL << 30) || c->S * (c->nvar > c->ng ? c->nvar : c->ng) > (1LL << 40)) { delete c; return NSK_EINVAL; }
+  make_basis(c->N, c->basis);
+  c->zR = rk_real_limit();
+  spinodal_band(c->par.T, c->rho_lo64, c->rho_hi64);
+
+  // workspace layout
+  const size_t gsz = c->par.precision == 0 ? sizeof(double) : sizeof(float);
+  size_t off = 0;
+  c->off_U2 = off;
+  off = align256(off + sizeof(double) * (size_t)c->nvar * c->S);
+  c->off_G = off;
+  off = align256(off + gsz * (size_t)c->ng * c->S);
+  for (int d = 0; d < 3; ++d) {
+    c->off_h2[d] = off;
+    off = align256(off + sizeof(double) * c->h2[d].size());
+  }
+  c->off_wq = off;
+  off = align256(off + sizeof(double) * kMaxNP);
+  long long blk = (c->E + kDiagThreads - 1) / kDiagThreads;
+  c->diag_blocks = (int)(blk < 1024 ? blk : 1024);
+  c->off_part = off;
+  off = align256(off + sizeof(double) * kDiagSlots * (size_t)c->diag_blocks);
+  c->off_out = off;
+  off = align256(off + sizeof(double) * 16);
+  c->ws_bytes = off;
+  *out = c;
+  return NSK_OK;
+}
+
+void nsk_destroy(nsk_ctx* c) {
+  if (!c) return;
+  if (c->bound) (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  delete c;
+}
+
+int nsk_timing_enable(nsk_ctx* c, int enable) {
+  if (!c) return NSK_EINVAL;
+  if (c->bound) (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  c->events.clear();
+  c->timed = 0;
+  if (!enable) return NSK_OK;
+  const int n = 3 * 4096;
+  c->events.resize(n);
+  for (int i = 0; i < n; ++i)
+    if (hipEventCreate(&c->events[i]) != hipSuccess) {
+      c->events.resize(i);
+      nsk_timing_enable(c, 0);
+      return NSK_EHIP;
+    }
+  return NSK_OK;
+}
+
+int nsk_timing_read(nsk_ctx* c, double out[3]) {
+  if (!c || !out) return NSK_EINVAL;
+  out[0] = out[1] = out[2] = 0.0;
+  if (c->timed == 0) return NSK_OK;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return NSK_EHIP;
+  for (int k = 0; k < c->timed; ++k) {
+    float a = 0.f, b = 0.f;
+    if (hipEventElapsedTime(&a, c->events[3 * k], c->events[3 * k + 1]) != hipSuccess) return NSK_EHIP;
+    if (hipEventElapsedTime(&b, c->events[3 * k + 1], c->events[3 * k + 2]) != hipSuccess) return NSK_EHIP;
+    out[0] += a;
+    out[1] += b;
+  }
+  out[2] = c->timed;
+  c->timed = 0;
+  return NSK_OK;
+}
+
+size_t nsk_state_size(const nsk_ctx* c) { return c ? (size_t)c->nvar * c->S : 0; }
+
+size_t nsk_workspace_bytes(const nsk_ctx* c) { return c ? c->ws_bytes : 0; }
+
+int nsk_bind(nsk_ctx* c, double* d_U, double* d_dU, void* d_work, void* hip_stream) {
+  if (!c || !d_U || !d_dU || !d_work) return NSK_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(d_work) & 255) != 0) return NSK_EINVAL;
+  c->U = d_U;
+  c->dU = d_dU;
+  c->work = static_cast<char*>(d_work);
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->cur = 0;
+  for (int d = 0; d < 3; ++d)
+    if (hipMemcpyAsync(c->work + c->off_h2[d], c->h2[d].data(), sizeof(double) * c->h2[d].size(),
+                       hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      return NSK_EHIP;
+  double wq[kMaxNP] = {0};
+  for (int i = 0; i < c->np; ++i) wq[i] = c->basis.w[i];
+  if (hipMemcpyAsync(c->work + c->off_wq, wq, sizeof(wq), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    return NSK_EHIP;
+  if (hipMemsetAsync(c->dU, 0, sizeof(double) * nsk_state_size(c), c->stream) != hipSuccess) return NSK_EHIP;
+  // the host arrays above are stack/heap memory owned here: wait for the copies
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return NSK_EHIP;
+  c->bound = true;
+  return NSK_OK;
+}
+
+int nsk_set_state(nsk_ctx* c, const double* d_src) {
+  if (!c || !d_src) return NSK_EINVAL;
+  if (!c->bound) return NSK_EUNBOUND;
+  c->cur = 0;
+  if (d_src == c->U) return NSK_OK;
+  return hipMemcpyAsync(c->U, d_src, sizeof(double) * nsk_state_size(c), hipMemcpyDeviceToDevice, c->stream) ==
+                 hipSuccess
+             ? NSK_OK
+             : NSK_EHIP;
+}
+
+int nsk_get_state(nsk_ctx* c, double* d_dst) {
+  if (!c || !d_dst) return NSK_EINVAL;
+  if (!c->bound) return NSK_EUNBOUND;
+  const double* src = state_buf(c, c->cur);
+  if (src == d_dst) return NSK_OK;
+  return hipMemcpyAsync(d_dst, src, sizeof(double) * nsk_state_size(c), hipMemcpyDeviceToDevice, c->stream) ==
+                 hipSuccess
+             ? NSK_OK
+             : NSK_EHIP;
+}
+
+int nsk_rhs(nsk_ctx* c, const double* d_U, double* d_R, double t) {
+  (void)t;
+  if (!c || !d_U || !d_R || d_U == d_R) return NSK_EINVAL;
+  if (!c->bound) return NSK_EUNBOUND;
+  StageArgs st{0.0, 0.0, 0.0, 0};
+  return dispatch(c, 0, d_U, d_R, nullptr, st);
+}
+
+int nsk_rk_step(nsk_ctx* c, double dt, int nsteps) {
+  if (!c || nsteps < 0 || !(dt > 0.0) || !std::isfinite(dt)) return NSK_EINVAL;
+  if (!c->bound) return NSK_EUNBOUND;
+  for (int step = 0; step < nsteps; ++step) {
+    for (int s = 0; s < 5; ++s) {
+      StageArgs st{kRkA[s], kRkB[s], dt, 1};
+      int rc = dispatch(c, 0, state_buf(c, c->cur), state_buf(c, 1 - c->cur), c->dU, st);
+      if (rc) return rc;
+      c->cur = 1 - c->cur;
+    }
+  }
+  if (c->cur == 1) {
+    if (hipMemcpyAsync(c->U, state_buf(c, 1), sizeof(double) * nsk_state_size(c), hipMemcpyDeviceToDevice,
+                       c->stream) != hipSuccess)
+      return NSK_EHIP;
+    c->cur = 0;
+  }
+  return NSK_OK;
+}
+
+static int run_diag(nsk_ctx* c, double* h) {
+  StageArgs st{0.0, 0.0, 0.0, 0};
+  int rc = dispatch(c, 1, state_buf(c, c->cur), nullptr, nullptr, st);
+  if (rc) return rc;
+  if (hipMemcpyAsync(h, c->work + c->off_out, sizeof(double) * kDiagSlots, hipMemcpyDeviceToHost, c->stream) !=
+      hipSuccess)
+    return NSK_EHIP;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return NSK_EHIP;
+  return NSK_OK;
+}
+
+int nsk_diagnostics(nsk_ctx* c, nsk_diag* o) {
+  if (!c || !o) return NSK_EINVAL;
+  if (!c->bound) return NSK_EUNBOUND;
+  double h[kDiagSlots];
+  int rc = run_diag(c, h);
+  if (rc) return rc;
+  std::memset(o, 0, sizeof(*o));
+  for (int v = 0; v < c->nvar; ++v) o->mass[v] = h[v];
+  o->e_kin = h[5];
+  o->e_total = h[6];
+  o->l2_rho_minus_c = std::sqrt(h[7]);
+  o->rho_min = h[8];
+  o->rho_max = h[9];
+  o->max_wavespeed = h[10];
+  o->nonfinite = (long long)h[11];
+  const bool bad = o->nonfinite > 0 || !(o->rho_min > 0.0) || !(o->rho_max < 3.0);
+  o->status = bad ? NSK_ENONPHYS : NSK_OK;
+  return o->status;
+}
+
+int nsk_dt_estimate(nsk_ctx* c, double cfl, double* dt_out) {
+  if (!c || !dt_out || !(cfl > 0.0)) return NSK_EINVAL;
+  if (!c->bound) return NSK_EUNBOUND;
+  double h[kDiagSlots];
+  int rc = run_diag(c, h);
+  if (rc) return rc;
+  if (h[11] > 0.0) return NSK_ENONPHYS;
+  const double N2 = 2.0 * c->N + 1.0;
+  const double lam_c = h[12];
+  double lam_v = 0.0;
+  const double lv = std::fmax(c->par.eps, c->par.kappa / c->par.beta);
+  // viscous bound: max over elements of sum_d lv / h_d^2 (widths are per
+  // direction index, so the maximum is the sum of the per-direction maxima)
+  for (int d = 0; d < c->dim; ++d) {
+    double m = 0.0;
+    for (double x : c->h2[d]) m = std::fmax(m, 0.25 * x * x);
+    lam_v += lv * m;
+  }
+  double dt = INFINITY;
+  if (lam_c > 0.0) dt = std::fmin(dt, 1.0 / (N2 * lam_c));
+  if (lam_v > 0.0) dt = std::fmin(dt, 1.0 / (N2 * N2 * lam_v));
+  dt = std::fmin(dt, c->zR * c->par.beta / c->par.alpha);
+  *dt_out = cfl * dt;
+  return NSK_OK;
+}
+
+int nsk_set_tile(nsk_ctx* c, int variant, int xcd_remap) {
+  if (!c || (variant != 0 && variant != 1) || (xcd_remap != 0 && xcd_remap != 1)) return NSK_EINVAL;
+  c->tile = variant;
+  c->nxcd = xcd_remap ? 8 : 1;
+  return NSK_OK;
+}
+
+int nsk_autotune(nsk_ctx* c, int reps, int* variant_out, int* remap_out, double* ms_out) {
+  if (!c || reps < 1) return NSK_EINVAL;
+  if (!c->bound) return NSK_EUNBOUND;
+  if (c->cur != 0) return NSK_EINVAL;  // the scratch state buffer must be free
+  const int keep_tile = c->tile, keep_nxcd = c->nxcd;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return NSK_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return NSK_EHIP; }
+  StageArgs st{0.0, 0.0, 0.0, 0};
+  double best = INFINITY;
+  int bv = keep_tile, br = keep_nxcd > 1;
+  int rc = NSK_OK;
+  for (int k = 0; k < 4 && rc == NSK_OK; ++k) {
+    c->tile = k >> 1;
+    c->nxcd = (k & 1) ? 8 : 1;
+    // right-hand side of the bound state written into the scratch state buffer
+    rc = dispatch(c, 0, c->U, state_buf(c, 1), nullptr, st);
+    if (rc) break;
+    if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = NSK_EHIP; break; }
+    for (int r = 0; r < reps && rc == NSK_OK; ++r) rc = dispatch(c, 0, c->U, state_buf(c, 1), nullptr, st);
+    if (rc) break;
+    float ms = 0.f;
+    if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = NSK_EHIP;
+      break;
+    }
+    const double per = ms / reps;
+    if (ms_out) ms_out[k] = per;
+    if (per < best) { best = per; bv = k >> 1; br = k & 1; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->tile = rc == NSK_OK ? bv : keep_tile;
+  c->nxcd = rc == NSK_OK ? (br ? 8 : 1) : keep_nxcd;
+  if (variant_out) *variant_out = c->tile;
+  if (remap_out) *remap_out = c->nxcd > 1;
+  return rc;
+}
+
+int nsk_set_params(nsk_ctx* c, const nsk_params* p) {
+  if (!c) return NSK_EINVAL;
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (p->precision != c->par.precision) return NSK_EINVAL;  // workspace layout depends on it
+  c->par = *p;
+  spinodal_band(c->par.T, c->rho_lo64, c->rho_hi64);
+  return NSK_OK;
+}
+
+}  // extern "C"

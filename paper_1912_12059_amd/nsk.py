@@ -1,0 +1,321 @@
+"""Python binding of libnsk (include/nsk.h): argument marshalling only.
+
+Every function here forwards to the C entry point of the same name.  All
+arithmetic of the method runs in the HIP kernels of ``csrc/``; PyTorch only
+provides device memory and the stream.  Importing this module fails loudly when
+the compiled library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnsk.so")
+
+NSK_OK = 0
+NSK_EINVAL = -1
+NSK_ENONPHYS = -2
+NSK_EHIP = -3
+NSK_EUNBOUND = -4
+NSK_EUNSUPPORTED = -5
+
+
+class NskError(RuntimeError):
+    def __init__(self, fn: str, code: int):
+        super().__init__(f"{fn} failed: {nsk_strerror(code)} ({code})")
+        self.code = code
+
+
+class nsk_mesh(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int),
+        ("N", C.c_int),
+        ("nel", C.c_int * 3),
+        ("lo", C.c_double * 3),
+        ("hi", C.c_double * 3),
+        ("xbreaks", C.POINTER(C.c_double) * 3),
+    ]
+
+
+class nsk_params(C.Structure):
+    _fields_ = [
+        ("T", C.c_double),
+        ("eps", C.c_double),
+        ("kappa", C.c_double),
+        ("alpha", C.c_double),
+        ("beta", C.c_double),
+        ("flux", C.c_int),
+        ("diss_c", C.c_int),
+        ("precision", C.c_int),
+        ("closure", C.c_int),
+    ]
+
+
+class nsk_diag(C.Structure):
+    _fields_ = [
+        ("mass", C.c_double * 5),
+        ("e_kin", C.c_double),
+        ("e_total", C.c_double),
+        ("l2_rho_minus_c", C.c_double),
+        ("rho_min", C.c_double),
+        ("rho_max", C.c_double),
+        ("max_wavespeed", C.c_double),
+        ("nonfinite", C.c_longlong),
+        ("status", C.c_int),
+    ]
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libnsk.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        vp, dp = C.c_void_p, C.POINTER(C.c_double)
+        L.nsk_create.argtypes = [C.POINTER(nsk_mesh), C.POINTER(nsk_params), C.POINTER(vp)]
+        L.nsk_destroy.argtypes = [vp]
+        L.nsk_destroy.restype = None
+        L.nsk_state_size.argtypes = [vp]
+        L.nsk_state_size.restype = C.c_size_t
+        L.nsk_workspace_bytes.argtypes = [vp]
+        L.nsk_workspace_bytes.restype = C.c_size_t
+        L.nsk_bind.argtypes = [vp, vp, vp, vp, vp]
+        L.nsk_set_state.argtypes = [vp, vp]
+        L.nsk_get_state.argtypes = [vp, vp]
+        L.nsk_rhs.argtypes = [vp, vp, vp, C.c_double]
+        L.nsk_dt_estimate.argtypes = [vp, C.c_double, dp]
+        L.nsk_rk_step.argtypes = [vp, C.c_double, C.c_int]
+        L.nsk_diagnostics.argtypes = [vp, C.POINTER(nsk_diag)]
+        L.nsk_set_params.argtypes = [vp, C.POINTER(nsk_params)]
+        L.nsk_set_tile.argtypes = [vp, C.c_int, C.c_int]
+        L.nsk_autotune.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), dp]
+        L.nsk_timing_enable.argtypes = [vp, C.c_int]
+        L.nsk_timing_read.argtypes = [vp, dp]
+        L.nsk_strerror.argtypes = [C.c_int]
+        L.nsk_strerror.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, rc: int) -> int:
+    if rc != NSK_OK:
+        raise NskError(fn, rc)
+    return rc
+
+
+def nsk_strerror(code: int) -> str:
+    return load().nsk_strerror(code).decode()
+
+
+def make_mesh(dim, N, nel, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), xbreaks=None):
+    """Fill an nsk_mesh.  The returned keep-alive list must outlive the call
+    to nsk_create (the library copies the breakpoints)."""
+    m = nsk_mesh()
+    m.dim, m.N = dim, N
+    keep = []
+    for d in range(3):
+        m.nel[d] = int(nel[d]) if d < len(nel) else 1
+        m.lo[d] = float(lo[d]) if d < len(lo) else 0.0
+        m.hi[d] = float(hi[d]) if d < len(hi) else 1.0
+        if xbreaks is not None and d < len(xbreaks) and xbreaks[d] is not None:
+            arr = (C.c_double * len(xbreaks[d]))(*[float(v) for v in xbreaks[d]])
+            keep.append(arr)
+            m.xbreaks[d] = C.cast(arr, C.POINTER(C.c_double))
+    return m, keep
+
+
+def make_params(T=0.85, eps=1e-3, kappa=1e-5, alpha=500.0, beta=1e-3, diss_c=1, precision=0, flux=0, closure=0):
+    p = nsk_params()
+    p.T, p.eps, p.kappa, p.alpha, p.beta = T, eps, kappa, alpha, beta
+    p.flux, p.diss_c, p.precision, p.closure = flux, diss_c, precision, closure
+    return p
+
+
+# ---- thin forwards, one per C entry point ---------------------------------
+def nsk_create(mesh: nsk_mesh, params: nsk_params) -> int:
+    h = C.c_void_p()
+    _check("nsk_create", load().nsk_create(C.byref(mesh), C.byref(params), C.byref(h)))
+    return h.value
+
+
+def nsk_destroy(ctx: int) -> None:
+    load().nsk_destroy(ctx)
+
+
+def nsk_state_size(ctx: int) -> int:
+    return load().nsk_state_size(ctx)
+
+
+def nsk_workspace_bytes(ctx: int) -> int:
+    return load().nsk_workspace_bytes(ctx)
+
+
+def nsk_bind(ctx: int, d_U: int, d_dU: int, d_work: int, stream: int) -> None:
+    _check("nsk_bind", load().nsk_bind(ctx, d_U, d_dU, d_work, stream))
+
+
+def nsk_set_state(ctx: int, d_src: int) -> None:
+    _check("nsk_set_state", load().nsk_set_state(ctx, d_src))
+
+
+def nsk_get_state(ctx: int, d_dst: int) -> None:
+    _check("nsk_get_state", load().nsk_get_state(ctx, d_dst))
+
+
+def nsk_rhs(ctx: int, d_U: int, d_R: int, t: float = 0.0) -> None:
+    _check("nsk_rhs", load().nsk_rhs(ctx, d_U, d_R, t))
+
+
+def nsk_dt_estimate(ctx: int, cfl: float) -> float:
+    out = C.c_double()
+    _check("nsk_dt_estimate", load().nsk_dt_estimate(ctx, cfl, C.byref(out)))
+    return out.value
+
+
+def nsk_rk_step(ctx: int, dt: float, nsteps: int) -> None:
+    _check("nsk_rk_step", load().nsk_rk_step(ctx, dt, nsteps))
+
+
+def nsk_diagnostics(ctx: int) -> tuple[int, nsk_diag]:
+    d = nsk_diag()
+    rc = load().nsk_diagnostics(ctx, C.byref(d))
+    if rc not in (NSK_OK, NSK_ENONPHYS):
+        raise NskError("nsk_diagnostics", rc)
+    return rc, d
+
+
+def nsk_set_params(ctx: int, params: nsk_params) -> None:
+    _check("nsk_set_params", load().nsk_set_params(ctx, C.byref(params)))
+
+
+def nsk_set_tile(ctx: int, variant: int, xcd_remap: int) -> None:
+    _check("nsk_set_tile", load().nsk_set_tile(ctx, variant, xcd_remap))
+
+
+def nsk_autotune(ctx: int, reps: int = 3) -> tuple[int, int, list]:
+    v, r = C.c_int(), C.c_int()
+    ms = (C.c_double * 4)()
+    _check("nsk_autotune", load().nsk_autotune(ctx, reps, C.byref(v), C.byref(r), ms))
+    return v.value, r.value, list(ms)
+
+
+def nsk_timing_enable(ctx: int, enable: int) -> None:
+    _check("nsk_timing_enable", load().nsk_timing_enable(ctx, enable))
+
+
+def nsk_timing_read(ctx: int) -> tuple[float, float, int]:
+    out = (C.c_double * 3)()
+    _check("nsk_timing_read", load().nsk_timing_read(ctx, out))
+    return out[0], out[1], int(out[2])
+
+
+# ---- convenience owner of the device buffers (torch) ----------------------
+@dataclass
+class Solver:
+    """Owns a context plus torch-allocated state, register and workspace."""
+
+    dim: int
+    N: int
+    nel: tuple
+    lo: tuple = (0.0, 0.0, 0.0)
+    hi: tuple = (1.0, 1.0, 1.0)
+    T: float = 0.85
+    eps: float = 1e-3
+    kappa: float = 1e-5
+    alpha: float = 500.0
+    beta: float = 1e-3
+    diss_c: int = 1
+    precision: int = 0
+    xbreaks: list | None = None
+    device: str = "cuda:0"
+    stream: object = None
+    ctx: int = field(default=0, init=False)
+
+    def __post_init__(self):
+        import torch
+
+        mesh, keep = make_mesh(self.dim, self.N, self.nel, self.lo, self.hi, self.xbreaks)
+        params = make_params(self.T, self.eps, self.kappa, self.alpha, self.beta, self.diss_c, self.precision)
+        self.ctx = nsk_create(mesh, params)
+        del keep
+        n = nsk_state_size(self.ctx)
+        self.nvar = self.dim + 2
+        self.nnode = (self.N + 1) ** self.dim
+        self.nelem = n // (self.nvar * self.nnode)
+        dev = torch.device(self.device)
+        self.U = torch.zeros(n, dtype=torch.float64, device=dev)
+        self.dU = torch.zeros(n, dtype=torch.float64, device=dev)
+        self.work = torch.zeros(nsk_workspace_bytes(self.ctx) + 256, dtype=torch.uint8, device=dev)
+        base = self.work.data_ptr()
+        self._work_ptr = (base + 255) // 256 * 256
+        if self.stream is None:
+            self.stream = torch.cuda.current_stream(dev)
+        nsk_bind(self.ctx, self.U.data_ptr(), self.dU.data_ptr(), self._work_ptr, self.stream.cuda_stream)
+
+    @property
+    def shape(self):
+        return (self.nvar, self.nelem, self.nnode)
+
+    def set_state(self, U) -> None:
+        import torch
+
+        t = torch.as_tensor(U, dtype=torch.float64).reshape(-1).to(self.U.device).contiguous()
+        if t.numel() != self.U.numel():
+            raise ValueError("state size mismatch")
+        with torch.cuda.stream(self.stream):
+            nsk_set_state(self.ctx, t.data_ptr())
+        self.stream.synchronize()
+
+    def get_state(self):
+        import torch
+
+        out = torch.empty_like(self.U)
+        nsk_get_state(self.ctx, out.data_ptr())
+        self.stream.synchronize()
+        return out.reshape(self.shape)
+
+    def rhs(self, U):
+        import torch
+
+        t = torch.as_tensor(U, dtype=torch.float64).reshape(-1).to(self.U.device).contiguous()
+        R = torch.empty_like(t)
+        nsk_rhs(self.ctx, t.data_ptr(), R.data_ptr(), 0.0)
+        self.stream.synchronize()
+        return R.reshape(self.shape)
+
+    def rk_step(self, dt: float, nsteps: int = 1) -> None:
+        nsk_rk_step(self.ctx, dt, nsteps)
+
+    def dt_estimate(self, cfl: float) -> float:
+        return nsk_dt_estimate(self.ctx, cfl)
+
+    def diagnostics(self) -> dict:
+        rc, d = nsk_diagnostics(self.ctx)
+        return {
+            "mass": list(d.mass)[: self.nvar],
+            "e_kin": d.e_kin,
+            "e_total": d.e_total,
+            "l2_rho_minus_c": d.l2_rho_minus_c,
+            "rho_min": d.rho_min,
+            "rho_max": d.rho_max,
+            "max_wavespeed": d.max_wavespeed,
+            "nonfinite": d.nonfinite,
+            "status": d.status,
+        }
+
+    def close(self) -> None:
+        if self.ctx:
+            nsk_destroy(self.ctx)
+            self.ctx = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

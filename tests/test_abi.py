@@ -1,0 +1,109 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/nsk.h declares, and nsk_create (host only) validates its input."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1912_12059_amd import nsk
+
+HDR_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(HDR_DIR):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(HDR_DIR, fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(nsk_\w+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported():
+    lib = C.CDLL(nsk.LIB_PATH)
+    names = _declared()
+    assert "nsk_rk_step" in names and "nsk_create" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_names_match_header():
+    for n in _declared():
+        assert hasattr(nsk, n), f"binding lacks {n}"
+
+
+def _ok_mesh(dim=3, N=4, nel=(4, 3, 2)):
+    return nsk.make_mesh(dim, N, nel)
+
+
+def test_create_sizes():
+    m, keep = _ok_mesh()
+    ctx = nsk.nsk_create(m, nsk.make_params())
+    try:
+        assert nsk.nsk_state_size(ctx) == 5 * 24 * 125
+        assert nsk.nsk_workspace_bytes(ctx) >= 8 * (5 + 9) * 24 * 125
+        m2, _ = nsk.make_mesh(2, 3, (5, 6))
+        ctx2 = nsk.nsk_create(m2, nsk.make_params(precision=1))
+        assert nsk.nsk_state_size(ctx2) == 4 * 30 * 16
+        nsk.nsk_destroy(ctx2)
+    finally:
+        nsk.nsk_destroy(ctx)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dim=0), dict(dim=4), dict(N=0), dict(N=7), dict(nel=(0, 3, 2)), dict(nel=(4, -1, 2)),
+])
+def test_create_rejects_bad_mesh(bad):
+    kw = dict(dim=3, N=4, nel=(4, 3, 2))
+    kw.update(bad)
+    m, keep = nsk.make_mesh(**kw)
+    with pytest.raises(nsk.NskError) as e:
+        nsk.nsk_create(m, nsk.make_params())
+    assert e.value.code == nsk.NSK_EINVAL
+
+
+@pytest.mark.parametrize("bad", [
+    dict(T=0.0), dict(T=1.0), dict(alpha=0.0), dict(beta=0.0), dict(beta=-1.0), dict(eps=-1e-3),
+    dict(kappa=-1.0), dict(precision=2), dict(flux=1), dict(closure=1), dict(diss_c=2),
+    dict(alpha=float("nan")),
+])
+def test_create_rejects_bad_params(bad):
+    m, keep = _ok_mesh()
+    with pytest.raises(nsk.NskError) as e:
+        nsk.nsk_create(m, nsk.make_params(**bad))
+    assert e.value.code == nsk.NSK_EINVAL
+
+
+def test_3d_degree_6_unsupported():
+    m, keep = nsk.make_mesh(3, 6, (2, 2, 2))
+    with pytest.raises(nsk.NskError) as e:
+        nsk.nsk_create(m, nsk.make_params())
+    assert e.value.code == nsk.NSK_EUNSUPPORTED
+
+
+def test_create_rejects_bad_breakpoints():
+    m, keep = nsk.make_mesh(1, 3, (3,), xbreaks=[[0.0, 0.5, 0.4, 1.0]])
+    with pytest.raises(nsk.NskError):
+        nsk.nsk_create(m, nsk.make_params())
+
+
+def test_unbound_calls_fail_cleanly():
+    m, keep = _ok_mesh()
+    ctx = nsk.nsk_create(m, nsk.make_params())
+    try:
+        for fn, args in ((nsk.nsk_rk_step, (1e-6, 1)), (nsk.nsk_dt_estimate, (0.5,)),
+                         (nsk.nsk_set_state, (1,)), (nsk.nsk_get_state, (1,))):
+            with pytest.raises(nsk.NskError) as e:
+                fn(ctx, *args)
+            assert e.value.code == nsk.NSK_EUNBOUND
+        with pytest.raises(nsk.NskError):
+            nsk.nsk_rk_step(ctx, -1.0, 1)
+    finally:
+        nsk.nsk_destroy(ctx)
+
+
+def test_strerror():
+    assert "invalid" in nsk.nsk_strerror(nsk.NSK_EINVAL)
+    assert nsk.nsk_strerror(12345) == "unknown error"
