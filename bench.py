@@ -116,11 +116,24 @@ def main() -> int:
     ap.add_argument("--workload", default="3d-collision", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tile", default="auto", help="auto (autotuner) or 'variant,remap', e.g. 0,1")
+    ap.add_argument("--tile", default="auto", help="auto (autotuner) or 'variant,order', e.g. 0,4")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run plain device copies of MIB MiB (to scale HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build", file=sys.stderr)
         return 2
+    if args.copy_calibration:
+        import torch
+
+        n = args.copy_calibration * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": n * 8, "copies": 4}))
+        return 0
 
     import torch
 
@@ -143,12 +156,12 @@ def main() -> int:
     del U
     dt = s.dt_estimate(0.5)
     if args.tile == "auto":
-        variant, remap, tune_ms = nsk.nsk_autotune(s.ctx, 3)
+        variant, order, tune_ms = nsk.nsk_autotune(s.ctx, 3)
     else:
-        variant, remap = (int(x) for x in args.tile.split(","))
-        nsk.nsk_set_tile(s.ctx, variant, remap)
+        variant, order = (int(x) for x in args.tile.split(","))
+        nsk.nsk_set_tile(s.ctx, variant, order)
         tune_ms = None
-    print(f"[bench] tile variant={variant} xcd_remap={remap} tune_ms={tune_ms}", file=sys.stderr, flush=True)
+    print(f"[bench] tile variant={variant} order={order} tune_ms={tune_ms}", file=sys.stderr, flush=True)
     print(f"[bench] dt={dt:.4e}, warmup {args.warmup} steps", file=sys.stderr, flush=True)
     s.rk_step(dt, args.warmup)
     torch.cuda.synchronize()
@@ -196,7 +209,7 @@ def main() -> int:
             "nvar": m.nvar,
             "precision": args.precision,
             "dt": dt,
-            "tile": {"variant": variant, "xcd_remap": remap, "autotune_ms": tune_ms},
+            "tile": {"variant": variant, "order": order, "autotune_ms": tune_ms},
         },
         "roofline": {
             "bound": "hbm",

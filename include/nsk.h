@@ -140,20 +140,25 @@ int nsk_rk_step(nsk_ctx* ctx, double dt, int nsteps);
 int nsk_diagnostics(nsk_ctx* ctx, nsk_diag* host_out);
 
 /* Launch shape (performance only; results are bitwise identical for every
- * choice): variant 0 or 1 selects the number of elements per workgroup
- * (about 256 threads, or twice as many elements where LDS allows);
- * xcd_remap 1 renumbers workgroups so each of the 8 XCDs sweeps one
- * contiguous range of elements, 0 keeps the hardware order. */
-int nsk_set_tile(nsk_ctx* ctx, int variant, int xcd_remap);
+ * choice).  variant 0: as many elements per workgroup as fit about 256
+ * threads within 40 KB of LDS; variant 1: half as many.  order selects the
+ * element work order: 0 natural order in the hardware's round-robin over
+ * XCDs; 1 natural order cut into one contiguous range per XCD; 2..5 x-y
+ * tiles of 4, 6, 8, 12 elements marched along z in 3D (x-strips of 16, 24,
+ * 32, 48 elements marched along y in 2D), one contiguous range per XCD.
+ * With a bound context a new order is uploaded at once (waits for the
+ * stream).  Defaults: variant 0, order 4 in 3D, order 0 otherwise. */
+int nsk_set_tile(nsk_ctx* ctx, int variant, int order);
 
 /* Autotuner over the launch shapes of nsk_set_tile: times `reps`
- * right-hand-side evaluations of the bound state for each of the four
- * (variant, xcd_remap) pairs with HIP events, keeps the fastest in the
- * context and returns it; ms_out (4 doubles, may be NULL) receives the mean
- * ms per evaluation in the order (0,0), (0,1), (1,0), (1,1).  Uses the
- * workspace's second state buffer as scratch, so it must be called between
- * steps (never inside a step), and waits for the stream. */
-int nsk_autotune(nsk_ctx* ctx, int reps, int* variant_out, int* remap_out, double* ms_out);
+ * right-hand-side evaluations of the bound state for each (variant, order)
+ * pair with HIP events, keeps the fastest in the context and returns it;
+ * ms_out (12 doubles, may be NULL) receives the mean ms per evaluation at
+ * index variant * 6 + order (-1 for pairs skipped because they coincide with
+ * another, e.g. tiled orders in 1D).  Uses the workspace's second state
+ * buffer as scratch, so it must be called between steps, and waits for the
+ * stream. */
+int nsk_autotune(nsk_ctx* ctx, int reps, int* variant_out, int* order_out, double* ms_out);
 
 /* Changes alpha, beta, eps, kappa of an existing context (same mesh). */
 int nsk_set_params(nsk_ctx* ctx, const nsk_params* params);

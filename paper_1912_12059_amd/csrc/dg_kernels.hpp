@@ -1,6 +1,7 @@
 // Device kernels of the DGSEM right-hand side for relaxation model II
 // (Hitz, Keim, Munz, Rohde, Sec. 2.3 for the model, Sec. 3.1 for the scheme),
-// written for gfx950 (64-wide wavefronts, 160 KB LDS per CU, 8 XCDs).
+// written for gfx950 (64-wide wavefronts, 160 KB LDS per CU, 8 XCDs with a
+// private 4 MB L2 each).
 //
 // One stage of the explicit scheme is two launches:
 //   lift_kernel : state U -> G, where G holds per node the viscous stress
@@ -10,17 +11,20 @@
 //                 pointwise source, then either R (dU/dt) or the fused
 //                 low-storage Runge-Kutta stage update of U and the register.
 //
-// Work layout: a workgroup owns EPB consecutive elements; one thread per
-// (element, node) for nodal work and one thread per (element, direction,
-// side, face node) for face work, in a single pass.  The element's own data
-// is staged in LDS, so its own face traces come from LDS; the neighbour's
-// trace needs the whole Gauss line of the neighbour element (Gauss nodes do
-// not contain the element ends), which is read from global memory where the
-// neighbour's own workgroup has pulled it into cache.  Workgroups are
-// renumbered so that each XCD sweeps one contiguous range of elements (its L2
-// then holds the x- and y-neighbours).  Each face value is computed
-// identically by both elements that share it, so the scheme stays
-// conservative bit for bit.
+// Work layout.  A workgroup owns EPB elements, one thread per (element, node).
+// Direction by direction, the two neighbour elements across the d-faces are
+// loaded whole with coalesced loads (one thread per node) into LDS: with
+// Gauss-Legendre nodes the element ends are not nodes, so a face trace needs
+// every node of the neighbour's line.  Face traces, the numerical flux and
+// the contraction with the derivative matrix then work from LDS.  Each face
+// value is computed identically by both elements sharing it (same operands,
+// same order), so the scheme stays conservative bit for bit.
+//
+// Element order.  Which elements a workgroup owns comes from a host-built
+// table.  The hardware hands consecutive workgroups to the XCDs in turn;
+// renumbering the workgroups so that each XCD walks one contiguous range of
+// that table, and building the table so that each range is a set of x-y tiles
+// marched along z, keeps the neighbour re-reads inside the XCD's L2.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -50,8 +54,7 @@ struct Shape {
 template <int DIM, int NP, int EPB>
 struct Tile {
   using Sh = Shape<DIM, NP>;
-  static constexpr int NITEMS = EPB * DIM * 2 * Sh::NF;  // face work items
-  static constexpr int THREADS = round64(cmax(EPB * Sh::NN, NITEMS));
+  static constexpr int THREADS = round64(cmax(EPB * Sh::NN, EPB * 2 * Sh::NF));
 };
 
 // stride of Gauss index along direction d inside an element
@@ -77,10 +80,11 @@ struct BasisArgs {
 
 struct MeshArgs {
   const double* h2[3];  // 2 / h per element index along each direction
+  const int* order;     // element of each position of the work order
   int nel[3];
   int E;                // number of elements
   long long S;          // E * NN, stride between variables
-  int nxcd;             // XCDs to spread contiguous element ranges over
+  int nxcd;             // XCDs sharing the work order in contiguous ranges
 };
 
 struct PhysArgs {
@@ -104,33 +108,51 @@ struct StageArgs {
 // -------------------------------------------------------------------------
 template <typename R>
 __device__ __forceinline__ R p_alpha(R rho, R T, R alpha) {
-  return R(8) * T * rho / (R(3) - rho) - R(3) * rho * rho + R(0.5) * alpha * rho * rho;
+  const R q = R(1) / (R(3) - rho);
+  return R(8) * T * rho * q - R(3) * rho * rho + R(0.5) * alpha * rho * rho;
 }
 
 template <typename R>
 __device__ __forceinline__ R sound_speed(R rho, R T, R alpha) {
-  R q = R(3) - rho;
-  return sqrt(R(24) * T / (q * q) - R(6) * rho + alpha * rho);
+  const R q = R(1) / (R(3) - rho);
+  return sqrt(R(24) * T * q * q - R(6) * rho + alpha * rho);
+}
+
+// p_alpha and a together, sharing the reciprocal 1/(3 - rho)
+template <typename R>
+__device__ __forceinline__ void p_alpha_sound(R rho, R T, R alpha, R& pa, R& a) {
+  const R q = R(1) / (R(3) - rho);
+  pa = R(8) * T * rho * q - R(3) * rho * rho + R(0.5) * alpha * rho * rho;
+  a = sqrt(R(24) * T * q * q - R(6) * rho + alpha * rho);
 }
 
 // EoS in the working precision R, except inside the spinodal band where the
 // Van-der-Waals pressure is evaluated in FP64 (mixed-precision rule).
 template <typename R>
+__device__ __forceinline__ bool eos_in_fp64(double rho64, const PhysArgs& ph) {
+  return sizeof(R) == sizeof(double) || (rho64 > ph.rho_lo64 && rho64 < ph.rho_hi64);
+}
+
+template <typename R>
 __device__ __forceinline__ R p_alpha_guarded(double rho64, const PhysArgs& ph) {
-  if (sizeof(R) == sizeof(double) || (rho64 > ph.rho_lo64 && rho64 < ph.rho_hi64))
-    return R(p_alpha<double>(rho64, ph.T, ph.alpha));
+  if (eos_in_fp64<R>(rho64, ph)) return R(p_alpha<double>(rho64, ph.T, ph.alpha));
   return p_alpha<R>(R(rho64), R(ph.T), R(ph.alpha));
 }
 
 template <typename R>
-__device__ __forceinline__ R sound_guarded(double rho64, const PhysArgs& ph) {
-  if (sizeof(R) == sizeof(double) || (rho64 > ph.rho_lo64 && rho64 < ph.rho_hi64))
-    return R(sound_speed<double>(rho64, ph.T, ph.alpha));
-  return sound_speed<R>(R(rho64), R(ph.T), R(ph.alpha));
+__device__ __forceinline__ void p_alpha_sound_guarded(double rho64, const PhysArgs& ph, R& pa, R& a) {
+  if (eos_in_fp64<R>(rho64, ph)) {
+    double p64, a64;
+    p_alpha_sound<double>(rho64, ph.T, ph.alpha, p64, a64);
+    pa = R(p64);
+    a = R(a64);
+  } else {
+    p_alpha_sound<R>(R(rho64), R(ph.T), R(ph.alpha), pa, a);
+  }
 }
 
 // Hardware hands consecutive workgroups to the XCDs in turn; renumber them
-// so that XCD x works through one contiguous range of tiles.
+// so that XCD x works through one contiguous range of the work order.
 __device__ __forceinline__ int remap_block(int b, int G, int nx) {
   if (nx <= 1) return b;
   const int q = G / nx, r = G - (G / nx) * nx;
@@ -138,18 +160,23 @@ __device__ __forceinline__ int remap_block(int b, int G, int nx) {
   return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
-// Per-element geometry for the workgroup: neighbour ids and 2/h.
+// Per-workgroup element data: element ids (-1 past the end), neighbour ids
+// and 2/h.
 template <int DIM, int EPB>
 struct ElemInfo {
+  int e[EPB];
   int nb[EPB][DIM][2];
   double h2[EPB][DIM];
 };
 
 template <int DIM, int EPB>
-__device__ __forceinline__ void elem_info(ElemInfo<DIM, EPB>& info, int e0, const MeshArgs& m, int tid) {
+__device__ __forceinline__ void elem_info(ElemInfo<DIM, EPB>& info, const MeshArgs& m, int tid) {
   if (tid < EPB) {
-    const int e = e0 + tid;
-    if (e < m.E) {
+    const int L = remap_block(blockIdx.x, gridDim.x, m.nxcd);
+    const int pos = L * EPB + tid;
+    const int e = pos < m.E ? m.order[pos] : -1;
+    info.e[tid] = e;
+    if (e >= 0) {
       int idx[3];
       idx[0] = e % m.nel[0];
       const int r = e / m.nel[0];
@@ -185,81 +212,98 @@ __device__ __forceinline__ int face_of(int d, int n) {
   return (n % sd) + sd * (n / (sd * NP));
 }
 
+// Convective flux of model II in direction d; irho = 1/rho.
+template <int DIM, typename R>
+__device__ __forceinline__ void conv_flux(int d, const R* u, R irho, R pa, R* F) {
+  const R vd = u[1 + d] * irho;
+  F[0] = u[1 + d];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) F[1 + j] = vd * u[1 + j] + (j == d ? pa : R(0));
+  F[DIM + 1] = R(0);
+}
+
 // -------------------------------------------------------------------------
-// Lifting: G = (tau, grad c) from the BR1 gradients of (v, c).
+// Lifting: G = (tau, grad c) from the BR1 gradients of (v, c):
+//   q_d,i = (2/h_d) [ (L+_i w*_+ - L-_i w*_-) / omega_i - sum_l Dhat_il w_l ]
+// along each d-line, w* = (w_left + w_right) / 2 on the faces.
 // -------------------------------------------------------------------------
 template <int DIM, int NP, int EPB, typename R, typename GT>
 __global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
 lift_kernel(const double* __restrict__ U, GT* __restrict__ G, BasisArgs bas, MeshArgs msh, PhysArgs ph) {
   using Sh = Shape<DIM, NP>;
-  using Tl = Tile<DIM, NP, EPB>;
   constexpr int NN = Sh::NN, NF = Sh::NF, NL = Sh::NLIFT;
   __shared__ R sW[EPB][NL][NN];             // nodal primitives (v, c)
+  __shared__ R sNbW[EPB][2][NL][NN];        // primitives of the two neighbours in direction d
   __shared__ R sWs[EPB][DIM][2][NL][NF];    // central face values w*
   __shared__ R sD[NP][NP];
   __shared__ R sLm[NP], sLp[NP], sIw[NP];
   __shared__ ElemInfo<DIM, EPB> info;
 
   const int tid = threadIdx.x;
-  const int blk = remap_block(blockIdx.x, gridDim.x, msh.nxcd);
-  const int e0 = blk * EPB;
   const long long S = msh.S;
   if (tid < NP * NP) sD[tid / NP][tid % NP] = R(bas.Dhat[tid / NP][tid % NP]);
   if (tid < NP) { sLm[tid] = R(bas.Lm[tid]); sLp[tid] = R(bas.Lp[tid]); sIw[tid] = R(bas.invw[tid]); }
-  elem_info<DIM, EPB>(info, e0, msh, tid);
+  elem_info<DIM, EPB>(info, msh, tid);
+  __syncthreads();
 
   const int el = tid / NN, n = tid - (tid / NN) * NN;
-  const int e = e0 + el;
-  const bool active = el < EPB && e < msh.E;
+  const int e = el < EPB ? info.e[el] : -1;
+  const bool active = e >= 0;
 
-  // step 1: nodal primitives
   if (active) {
     const long long o = (long long)e * NN + n;
-    const double rho = U[o];
+    const double irho = 1.0 / U[o];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) sW[el][d][n] = R(U[(1 + d) * S + o] / rho);
+    for (int d = 0; d < DIM; ++d) sW[el][d][n] = R(U[(1 + d) * S + o] * irho);
     sW[el][DIM][n] = R(U[(DIM + 1) * S + o]);
   }
-  __syncthreads();
 
-  // step 2: central traces w* = (w_left + w_right) / 2 on every face
-  if (tid < Tl::NITEMS) {
-    const int f = tid % NF;
-    const int s = (tid / NF) & 1;
-    const int d = (tid / (2 * NF)) % DIM;
-    const int le = tid / (2 * NF * DIM);
-    if (e0 + le < msh.E) {
-      const int nb = info.nb[le][d][s];
-      const int base = face_base<NP>(d, f);
-      const int sd = dstride<NP>(d);
-      R own[NL], oth[NL];
 #pragma unroll
-      for (int k = 0; k < NL; ++k) { own[k] = R(0); oth[k] = R(0); }
+  for (int d = 0; d < DIM; ++d) {  // unrolled: d-dependent index math is compile-time
+    if (active) {
 #pragma unroll
-      for (int l = 0; l < NP; ++l) {
-        const R Lo = s ? sLp[l] : sLm[l];
-        const R Ln = s ? sLm[l] : sLp[l];
-        const int node = base + l * sd;
-        const long long on = (long long)nb * NN + node;
-        const double rho = U[on];
+      for (int s = 0; s < 2; ++s) {
+        const long long on = (long long)info.nb[el][d][s] * NN + n;
+        const double irho = 1.0 / U[on];
 #pragma unroll
-        for (int k = 0; k < NL; ++k) own[k] += Lo * sW[le][k][node];
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) oth[k] += Ln * R(U[(1 + k) * S + on] / rho);
-        oth[DIM] += Ln * R(U[(DIM + 1) * S + on]);
-      }
-#pragma unroll
-      for (int k = 0; k < NL; ++k) {
-        // left state first: on side + the element is left, on side - it is right
-        const R wl = s ? own[k] : oth[k];
-        const R wr = s ? oth[k] : own[k];
-        sWs[le][d][s][k][f] = R(0.5) * (wl + wr);
+        for (int k = 0; k < DIM; ++k) sNbW[el][s][k][n] = R(U[(1 + k) * S + on] * irho);
+        sNbW[el][s][DIM][n] = R(U[(DIM + 1) * S + on]);
       }
     }
+    __syncthreads();
+    if (tid < EPB * 2 * NF) {
+      const int f = tid % NF;
+      const int s = (tid / NF) & 1;
+      const int le = tid / (2 * NF);
+      if (info.e[le] >= 0) {
+        const int base = face_base<NP>(d, f);
+        const int sd = dstride<NP>(d);
+        R own[NL], oth[NL];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) { own[k] = R(0); oth[k] = R(0); }
+#pragma unroll
+        for (int l = 0; l < NP; ++l) {
+          const R Lo = s ? sLp[l] : sLm[l];   // own trace on side s
+          const R Ln = s ? sLm[l] : sLp[l];   // neighbour trace on the opposite side
+          const int node = base + l * sd;
+#pragma unroll
+          for (int k = 0; k < NL; ++k) {
+            own[k] += Lo * sW[le][k][node];
+            oth[k] += Ln * sNbW[le][s][k][node];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+          // left state first: on side + the element is left, on side - it is right
+          const R wl = s ? own[k] : oth[k];
+          const R wr = s ? oth[k] : own[k];
+          sWs[le][d][s][k][f] = R(0.5) * (wl + wr);
+        }
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
-  // step 3: lifted gradients q[d][k] = d w_k / d x_d, then tau and grad c
   if (active) {
     R q[DIM][NL];
 #pragma unroll
@@ -296,50 +340,43 @@ lift_kernel(const double* __restrict__ U, GT* __restrict__ G, BasisArgs bas, Mes
 }
 
 // -------------------------------------------------------------------------
-// Right-hand side and fused Runge-Kutta stage.
+// Right-hand side and fused Runge-Kutta stage:
+//   R_i = sum_d (2/h_d) [ sum_l Dhat_il F_d,l - (L+_i F*_+ - L-_i F*_-) / omega_i ] + S_i
+// with F_d = Fc_d(U) - Fv_d(G), F* = Rusanov(U-, U+) - (Fv(G-) + Fv(G+)) / 2
+// and S = (0, alpha rho grad c, (alpha/beta)(rho - c)); then
+//   dU <- A dU + dt R,  U <- U + B dU.
 // -------------------------------------------------------------------------
-// Convective flux of model II in direction d.
-template <int DIM, typename R>
-__device__ __forceinline__ void conv_flux(int d, const R* u, R pa, R* F) {
-  const R vd = u[1 + d] / u[0];
-  F[0] = u[1 + d];
-#pragma unroll
-  for (int j = 0; j < DIM; ++j) F[1 + j] = vd * u[1 + j] + (j == d ? pa : R(0));
-  F[DIM + 1] = R(0);
-}
-
 template <int DIM, int NP, int EPB, typename R, typename GT>
 __global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
 rhs_kernel(const double* __restrict__ U, const GT* __restrict__ G, double* __restrict__ Uout,
            double* __restrict__ dU, BasisArgs bas, MeshArgs msh, PhysArgs ph, StageArgs st) {
   using Sh = Shape<DIM, NP>;
-  using Tl = Tile<DIM, NP, EPB>;
   constexpr int NN = Sh::NN, NF = Sh::NF, NV = Sh::NVAR, NT = Sh::NTAU, NG = Sh::NG;
+  constexpr int NX = NV + DIM + 1;          // per node: U and the viscous flux components of direction d
   constexpr bool MIXED = sizeof(R) != sizeof(double);
   constexpr int R64E = MIXED ? EPB : 1, R64N = MIXED ? NN : 1;
-  __shared__ R sUG[EPB][NV + NG][NN];       // own state and G (own face traces)
-  __shared__ double sRho64[R64E][R64N];     // FP64 density (mixed precision only)
-  __shared__ R sF[EPB][NV][NN];             // total flux Fc - Fv in one direction
-  __shared__ R sFs[EPB][DIM][2][NV][NF];    // numerical flux on the faces
+  __shared__ R sOwn[EPB][NX][NN];           // own U and (tau_{.d}, dc/dx_d)
+  __shared__ R sNb[EPB][2][NX][NN];         // the same for the two neighbours in direction d
+  __shared__ double sRho64[R64E][3][R64N];  // FP64 densities (mixed precision only)
+  __shared__ R sF[EPB][NV][NN];             // total flux Fc_d - Fv_d
+  __shared__ R sFs[EPB][2][NV][NF];         // numerical flux on the two d-faces
   __shared__ R sD[NP][NP];
   __shared__ R sLm[NP], sLp[NP], sIw[NP];
   __shared__ ElemInfo<DIM, EPB> info;
 
   const int tid = threadIdx.x;
-  const int blk = remap_block(blockIdx.x, gridDim.x, msh.nxcd);
-  const int e0 = blk * EPB;
   const long long S = msh.S;
   if (tid < NP * NP) sD[tid / NP][tid % NP] = R(bas.Dhat[tid / NP][tid % NP]);
   if (tid < NP) { sLm[tid] = R(bas.Lm[tid]); sLp[tid] = R(bas.Lp[tid]); sIw[tid] = R(bas.invw[tid]); }
-  elem_info<DIM, EPB>(info, e0, msh, tid);
+  elem_info<DIM, EPB>(info, msh, tid);
+  __syncthreads();
 
   const int el = tid / NN, n = tid - (tid / NN) * NN;
-  const int e = e0 + el;
-  const bool active = el < EPB && e < msh.E;
-  const long long o = (long long)e * NN + n;
+  const int e = el < EPB ? info.e[el] : -1;
+  const bool active = e >= 0;
+  const long long o = (long long)(active ? e : 0) * NN + n;
   const R kb = R(ph.kb);
 
-  // step 1: own state and G into registers and LDS; prefetch the register dU
   double rho64 = 0.0, c64 = 0.0;
   double u64[NV], du_old[NV];
   R u[NV], g[NG];
@@ -359,101 +396,108 @@ rhs_kernel(const double* __restrict__ U, const GT* __restrict__ G, double* __res
     rho64 = u64[0];
     c64 = u64[DIM + 1];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) { u[v] = R(u64[v]); sUG[el][v][n] = u[v]; }
-#pragma unroll
-    for (int k = 0; k < NG; ++k) sUG[el][NV + k][n] = g[k];
-    if (MIXED) sRho64[MIXED ? el : 0][MIXED ? n : 0] = rho64;
+    for (int v = 0; v < NV; ++v) { u[v] = R(u64[v]); sOwn[el][v][n] = u[v]; }
+    if (MIXED) sRho64[MIXED ? el : 0][0][MIXED ? n : 0] = rho64;
   }
-  __syncthreads();
-
-  // step 2: face fluxes F* = Rusanov(uL, uR) - (Fv(gL) + Fv(gR)) / 2, one
-  // thread per (element, direction, side, face node); own side from LDS
-  if (tid < Tl::NITEMS) {
-    const int f = tid % NF;
-    const int s = (tid / NF) & 1;
-    const int d = (tid / (2 * NF)) % DIM;
-    const int le = tid / (2 * NF * DIM);
-    if (e0 + le < msh.E) {
-      const int nb = info.nb[le][d][s];
-      const int base = face_base<NP>(d, f);
-      const int sd = dstride<NP>(d);
-      double ro64 = 0.0, rn64 = 0.0;   // density traces in FP64 (EoS guard)
-      R uo[NV], un[NV], vo[DIM + 1], vn[DIM + 1];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) { uo[v] = R(0); un[v] = R(0); }
-#pragma unroll
-      for (int k = 0; k <= DIM; ++k) { vo[k] = R(0); vn[k] = R(0); }
-#pragma unroll
-      for (int l = 0; l < NP; ++l) {
-        const int node = base + l * sd;
-        const long long on = (long long)nb * NN + node;
-        const R Lo = s ? sLp[l] : sLm[l];   // own trace on side s
-        const R Ln = s ? sLm[l] : sLp[l];   // neighbour trace on the opposite side
-        const double Lo64 = s ? bas.Lp[l] : bas.Lm[l];
-        const double Ln64 = s ? bas.Lm[l] : bas.Lp[l];
-        const double rn = U[on];
-        const double ro = MIXED ? sRho64[MIXED ? le : 0][MIXED ? node : 0] : double(sUG[le][0][node]);
-        ro64 += Lo64 * ro;
-        rn64 += Ln64 * rn;
-        uo[0] += Lo * sUG[le][0][node];
-        un[0] += Ln * R(rn);
-#pragma unroll
-        for (int v = 1; v < NV; ++v) {
-          uo[v] += Lo * sUG[le][v][node];
-          un[v] += Ln * R(U[v * S + on]);
-        }
-#pragma unroll
-        for (int j = 0; j < DIM; ++j) {
-          const int gi = tau_index<DIM>(j, d);
-          vo[j] += Lo * sUG[le][NV + gi][node];
-          vn[j] += Ln * R(G[(long long)gi * S + on]);
-        }
-        vo[DIM] += Lo * sUG[le][NV + NT + d][node];
-        vn[DIM] += Ln * R(G[(long long)(NT + d) * S + on]);
-      }
-      // left/right in direction d: on side + this element is the left state
-      R uL[NV], uR[NV], vL[DIM + 1], vR[DIM + 1];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) { uL[v] = s ? uo[v] : un[v]; uR[v] = s ? un[v] : uo[v]; }
-#pragma unroll
-      for (int k = 0; k <= DIM; ++k) { vL[k] = s ? vo[k] : vn[k]; vR[k] = s ? vn[k] : vo[k]; }
-      const double rL = s ? ro64 : rn64, rR = s ? rn64 : ro64;
-      const R paL = p_alpha_guarded<R>(rL, ph), paR = p_alpha_guarded<R>(rR, ph);
-      const R aL = sound_guarded<R>(rL, ph), aR = sound_guarded<R>(rR, ph);
-      const R sL = fabs(uL[1 + d] / uL[0]) + aL;
-      const R sR = fabs(uR[1 + d] / uR[0]) + aR;
-      const R lam = sL > sR ? sL : sR;
-      R FL[NV], FR[NV];
-      conv_flux<DIM, R>(d, uL, paL, FL);
-      conv_flux<DIM, R>(d, uR, paR, FR);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const R diss = (v == NV - 1 && !ph.diss_c) ? R(0) : lam * (uR[v] - uL[v]);
-        R Fs = R(0.5) * (FL[v] + FR[v]) - R(0.5) * diss;
-        if (v >= 1 && v <= DIM) Fs -= R(0.5) * (vL[v - 1] + vR[v - 1]);
-        if (v == NV - 1) Fs -= R(0.5) * kb * (vL[DIM] + vR[DIM]);
-        sFs[le][d][s][v][f] = Fs;
-      }
-    }
+  R pa = R(0), irho = R(0);
+  if (active) {
+    pa = p_alpha_guarded<R>(rho64, ph);
+    irho = R(1) / u[0];
   }
-
-  // step 3: per direction, stage the nodal flux F_d in LDS and contract
   R acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = R(0);
-  R pa = R(0);
-  if (active) pa = p_alpha_guarded<R>(rho64, ph);
+
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    if (d > 0) __syncthreads();  // previous direction's contraction is done
+  for (int d = 0; d < DIM; ++d) {  // unrolled: d-dependent index math is compile-time
     if (active) {
+      // own viscous components of direction d and the nodal total flux
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) sOwn[el][NV + j][n] = g[tau_index<DIM>(j, d)];
+      sOwn[el][NV + DIM][n] = g[NT + d];
       R F[NV];
-      conv_flux<DIM, R>(d, u, pa, F);
+      conv_flux<DIM, R>(d, u, irho, pa, F);
 #pragma unroll
       for (int j = 0; j < DIM; ++j) F[1 + j] -= g[tau_index<DIM>(j, d)];
       F[DIM + 1] -= kb * g[NT + d];
 #pragma unroll
       for (int v = 0; v < NV; ++v) sF[el][v][n] = F[v];
+      // the two neighbours, coalesced
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const long long on = (long long)info.nb[el][d][s] * NN + n;
+        const double rn = U[on];
+        if (MIXED) sRho64[MIXED ? el : 0][1 + s][MIXED ? n : 0] = rn;
+        sNb[el][s][0][n] = R(rn);
+#pragma unroll
+        for (int v = 1; v < NV; ++v) sNb[el][s][v][n] = R(U[v * S + on]);
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) sNb[el][s][NV + j][n] = R(G[(long long)tau_index<DIM>(j, d) * S + on]);
+        sNb[el][s][NV + DIM][n] = R(G[(long long)(NT + d) * S + on]);
+      }
+    }
+    __syncthreads();
+    if (tid < EPB * 2 * NF) {
+      const int f = tid % NF;
+      const int s = (tid / NF) & 1;
+      const int le = tid / (2 * NF);
+      if (info.e[le] >= 0) {
+        const int base = face_base<NP>(d, f);
+        const int sd = dstride<NP>(d);
+        double ro64 = 0.0, rn64 = 0.0;   // density traces in FP64 (EoS guard)
+        R uo[NV], un[NV], vo[DIM + 1], vn[DIM + 1];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) { uo[v] = R(0); un[v] = R(0); }
+#pragma unroll
+        for (int k = 0; k <= DIM; ++k) { vo[k] = R(0); vn[k] = R(0); }
+#pragma unroll
+        for (int l = 0; l < NP; ++l) {
+          const int node = base + l * sd;
+          const R Lo = s ? sLp[l] : sLm[l];   // own trace on side s
+          const R Ln = s ? sLm[l] : sLp[l];   // neighbour trace on the opposite side
+          const double Lo64 = s ? bas.Lp[l] : bas.Lm[l];
+          const double Ln64 = s ? bas.Lm[l] : bas.Lp[l];
+          const double ro = MIXED ? sRho64[MIXED ? le : 0][0][MIXED ? node : 0] : double(sOwn[le][0][node]);
+          const double rn = MIXED ? sRho64[MIXED ? le : 0][1 + s][MIXED ? node : 0] : double(sNb[le][s][0][node]);
+          ro64 += Lo64 * ro;
+          rn64 += Ln64 * rn;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            uo[v] += Lo * sOwn[le][v][node];
+            un[v] += Ln * sNb[le][s][v][node];
+          }
+#pragma unroll
+          for (int k = 0; k <= DIM; ++k) {
+            vo[k] += Lo * sOwn[le][NV + k][node];
+            vn[k] += Ln * sNb[le][s][NV + k][node];
+          }
+        }
+        // left/right in direction d: on side + this element is the left state
+        R uL[NV], uR[NV], vL[DIM + 1], vR[DIM + 1];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) { uL[v] = s ? uo[v] : un[v]; uR[v] = s ? un[v] : uo[v]; }
+#pragma unroll
+        for (int k = 0; k <= DIM; ++k) { vL[k] = s ? vo[k] : vn[k]; vR[k] = s ? vn[k] : vo[k]; }
+        const double rL = s ? ro64 : rn64, rR = s ? rn64 : ro64;
+        R paL, paR, aL, aR;
+        p_alpha_sound_guarded<R>(rL, ph, paL, aL);
+        p_alpha_sound_guarded<R>(rR, ph, paR, aR);
+        const R irL = R(1) / uL[0], irR = R(1) / uR[0];
+        const R sL = fabs(uL[1 + d] * irL) + aL;
+        const R sR = fabs(uR[1 + d] * irR) + aR;
+        const R lam = sL > sR ? sL : sR;
+        R FL[NV], FR[NV];
+        conv_flux<DIM, R>(d, uL, irL, paL, FL);
+        conv_flux<DIM, R>(d, uR, irR, paR, FR);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const R diss = (v == NV - 1 && !ph.diss_c) ? R(0) : lam * (uR[v] - uL[v]);
+          R Fs = R(0.5) * (FL[v] + FR[v]) - R(0.5) * diss;
+          if (v >= 1 && v <= DIM) Fs -= R(0.5) * (vL[v - 1] + vR[v - 1]);
+          if (v == NV - 1) Fs -= R(0.5) * kb * (vL[DIM] + vR[DIM]);
+          sFs[le][s][v][f] = Fs;
+        }
+      }
     }
     __syncthreads();
     if (active) {
@@ -470,12 +514,13 @@ rhs_kernel(const double* __restrict__ U, const GT* __restrict__ G, double* __res
         R vol = R(0);
 #pragma unroll
         for (int l = 0; l < NP; ++l) vol += Drow[l] * sF[el][v][n + (l - i) * sd];
-        acc[v] += h2 * (vol - (lp * sFs[el][d][1][v][f] - lm * sFs[el][d][0][v][f]));
+        acc[v] += h2 * (vol - (lp * sFs[el][1][v][f] - lm * sFs[el][0][v][f]));
       }
     }
+    __syncthreads();  // LDS reused by the next direction
   }
 
-  // step 4: source (FP64) and update
+  // source (FP64) and update
   if (active) {
     double Rv[NV];
 #pragma unroll
@@ -483,7 +528,6 @@ rhs_kernel(const double* __restrict__ U, const GT* __restrict__ G, double* __res
 #pragma unroll
     for (int d = 0; d < DIM; ++d) Rv[1 + d] += ph.alpha * rho64 * double(g[NT + d]);
     Rv[DIM + 1] += ph.ab * (rho64 - c64);
-
     if (st.mode == 0) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) Uout[v * S + o] = Rv[v];

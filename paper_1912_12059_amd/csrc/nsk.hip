@@ -1,10 +1,12 @@
 // libnsk host side: the C ABI declared in include/nsk.h.
 //
 // Builds the 1D Gauss-Legendre basis and the geometry on the host, lays out
-// the caller-provided workspace, and enqueues the kernels of dg_kernels.hpp on
-// the bound stream.  No device memory is allocated here.
+// the caller-provided workspace, builds the element work order, and enqueues
+// the kernels of dg_kernels.hpp on the bound stream.  No device memory is
+// allocated here.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -119,6 +121,16 @@ double rk_real_limit() {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Launch shapes: elements-per-workgroup variants x element work orders.
+constexpr int kTileVariants = 2;
+constexpr int kOrders = 6;
+// order 0: natural element order in hardware round-robin; 1: natural order,
+// one contiguous range per XCD; 2..5: x-y tiles of kTileEdge[order] elements
+// (3D) marched along z, or x-strips of 4x that width marched along y (2D),
+// one contiguous range per XCD.
+constexpr int kTileEdge[kOrders] = {0, 0, 4, 6, 8, 12};
+constexpr int kXcds = 8;
+
 }  // namespace
 
 struct nsk_ctx {
@@ -132,10 +144,12 @@ struct nsk_ctx {
   double zR = 0.0;
   double rho_lo64 = 0.0, rho_hi64 = 0.0;
   // workspace layout (byte offsets)
-  size_t off_U2 = 0, off_G = 0, off_h2[3] = {0, 0, 0}, off_wq = 0, off_part = 0, off_out = 0, ws_bytes = 0;
+  size_t off_U2 = 0, off_G = 0, off_h2[3] = {0, 0, 0}, off_wq = 0, off_order = 0, off_part = 0, off_out = 0;
+  size_t ws_bytes = 0;
   int diag_blocks = 0;
-  int tile = 0;      // elements-per-workgroup variant (0 or 1)
-  int nxcd = 8;      // XCDs the block order is spread over (1 = hardware order)
+  int tile = 0;      // elements-per-workgroup variant
+  int order = 0;     // element work order
+  std::vector<int> order_host;
   // bound memory
   bool bound = false;
   double* U = nullptr;
@@ -154,6 +168,8 @@ int check_params(const nsk_params* p) {
   if (!p) return NSK_EINVAL;
   if (!(p->T > 0.0 && p->T < 1.0)) return NSK_EINVAL;
   if (!(p->alpha > 0.0) || !(p->beta > 0.0) || !(p->eps >= 0.0) || !(p->kappa >= 0.0)) return NSK_EINVAL;
+  if (!std::isfinite(p->alpha) || !std::isfinite(p->beta) || !std::isfinite(p->eps) || !std::isfinite(p->kappa))
+    return NSK_EINVAL;
   if (p->flux != 0 || p->closure != 0) return NSK_EINVAL;
   if (p->precision != 0 && p->precision != 1) return NSK_EINVAL;
   if (p->diss_c != 0 && p->diss_c != 1) return NSK_EINVAL;
@@ -176,6 +192,40 @@ void spinodal_band(double T, double& lo, double& hi) {
   hi = root(1.0, 3.0 - 1e-9) + 0.05;
 }
 
+// Element work order for one of the kOrders choices (see kTileEdge).
+void build_order(const nsk_ctx* c, int order, std::vector<int>& out) {
+  const int E = (int)c->E, nx = c->nel[0], ny = c->nel[1], nz = c->nel[2];
+  out.clear();
+  out.reserve(E);
+  const int T = kTileEdge[order];
+  if (T == 0 || c->dim == 1) {
+    for (int e = 0; e < E; ++e) out.push_back(e);
+    return;
+  }
+  if (c->dim == 2) {
+    const int W = 4 * T;
+    for (int x0 = 0; x0 < nx; x0 += W)
+      for (int y = 0; y < ny; ++y)
+        for (int x = x0; x < std::min(nx, x0 + W); ++x) out.push_back(x + nx * y);
+    return;
+  }
+  for (int y0 = 0; y0 < ny; y0 += T)
+    for (int x0 = 0; x0 < nx; x0 += T)
+      for (int z = 0; z < nz; ++z)
+        for (int y = y0; y < std::min(ny, y0 + T); ++y)
+          for (int x = x0; x < std::min(nx, x0 + T); ++x) out.push_back(x + nx * (y + ny * z));
+}
+
+int upload_order(nsk_ctx* c, int order) {
+  build_order(c, order, c->order_host);
+  if (hipMemcpyAsync(c->work + c->off_order, c->order_host.data(), sizeof(int) * c->order_host.size(),
+                     hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    return NSK_EHIP;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return NSK_EHIP;
+  c->order = order;
+  return NSK_OK;
+}
+
 BasisArgs basis_args(const nsk_ctx* c) {
   BasisArgs b;
   std::memset(&b, 0, sizeof(b));
@@ -194,9 +244,10 @@ MeshArgs mesh_args(const nsk_ctx* c) {
     m.h2[d] = reinterpret_cast<const double*>(c->work + c->off_h2[d]);
     m.nel[d] = c->nel[d];
   }
+  m.order = reinterpret_cast<const int*>(c->work + c->off_order);
   m.E = (int)c->E;
   m.S = c->S;
-  m.nxcd = c->nxcd;
+  m.nxcd = c->order == 0 ? 1 : kXcds;
   return m;
 }
 
@@ -216,7 +267,7 @@ PhysArgs phys_args(const nsk_ctx* c) {
 }
 
 // ---------------------------------------------------------------------------
-// Launch dispatch over (dim, N, precision)
+// Launch dispatch over (dim, N, precision, elements per workgroup)
 // ---------------------------------------------------------------------------
 // events of the next timed stage, or nullptr when timing is off or full
 hipEvent_t* stage_events(nsk_ctx* c, const StageArgs& st) {
@@ -224,19 +275,19 @@ hipEvent_t* stage_events(nsk_ctx* c, const StageArgs& st) {
   return &c->events[3 * (size_t)c->timed++];
 }
 
-// Elements per workgroup: variant 0 fills about 256 threads, variant 1
-// doubles it where the LDS of the right-hand-side kernel stays within 64 KB.
+// Elements per workgroup: variant 0 is the largest count up to about 256
+// threads whose right-hand-side LDS (FP64) stays within 40 KB; variant 1 is
+// half of it (at least one).
 template <int DIM, int NP>
 struct Epb {
   using Sh = Shape<DIM, NP>;
-  static constexpr int A = cmax(1, 256 / cmax(Sh::NN, 2 * DIM * Sh::NF));
-  template <typename R>
-  static constexpr int rhs_lds(int epb) {
-    return (int)sizeof(R) * epb * ((Sh::NVAR + Sh::NG) * Sh::NN + Sh::NVAR * Sh::NN + DIM * 2 * Sh::NVAR * Sh::NF) +
-           (sizeof(R) == 4 ? 8 * epb * Sh::NN : 8) + 1024;
+  static constexpr int NX = Sh::NVAR + DIM + 1;
+  static constexpr int lds(int epb) {
+    return 8 * epb * (3 * NX * Sh::NN + Sh::NVAR * Sh::NN + 2 * Sh::NVAR * Sh::NF) + 1024;
   }
-  static constexpr bool B_OK = rhs_lds<double>(2 * A) <= 65536;
-  static constexpr int B = B_OK ? 2 * A : A;
+  static constexpr int pick(int epb) { return (epb <= 1 || lds(epb) <= 40960) ? (epb < 1 ? 1 : epb) : pick(epb - 1); }
+  static constexpr int V0 = pick(256 / Sh::NN);
+  static constexpr int V1 = V0 / 2 < 1 ? 1 : V0 / 2;
 };
 
 template <int DIM, int NP, int EPB, typename R, typename GT>
@@ -260,14 +311,14 @@ int launch_stage_e(nsk_ctx* c, const double* Uin, double* Uout, double* dU, cons
 
 template <int DIM, int NP, typename R, typename GT>
 int launch_stage_t(nsk_ctx* c, const double* Uin, double* Uout, double* dU, const StageArgs& st) {
-  if (c->tile == 1 && Epb<DIM, NP>::B_OK)
-    return launch_stage_e<DIM, NP, Epb<DIM, NP>::B, R, GT>(c, Uin, Uout, dU, st);
-  return launch_stage_e<DIM, NP, Epb<DIM, NP>::A, R, GT>(c, Uin, Uout, dU, st);
+  if (c->tile == 1 && Epb<DIM, NP>::V1 != Epb<DIM, NP>::V0)
+    return launch_stage_e<DIM, NP, Epb<DIM, NP>::V1, R, GT>(c, Uin, Uout, dU, st);
+  return launch_stage_e<DIM, NP, Epb<DIM, NP>::V0, R, GT>(c, Uin, Uout, dU, st);
 }
 
 template <int DIM, int NP, typename GT>
 int launch_diag_t(nsk_ctx* c, const double* Uin) {
-  constexpr int EPB = Epb<DIM, NP>::A;
+  constexpr int EPB = Epb<DIM, NP>::V0;
   using Tl = Tile<DIM, NP, EPB>;
   const BasisArgs b = basis_args(c);
   const MeshArgs m = mesh_args(c);
@@ -323,6 +374,17 @@ int dispatch(nsk_ctx* c, int what, const double* Uin, double* Uout, double* dU, 
 
 double* state_buf(nsk_ctx* c, int which) {
   return which == 0 ? c->U : reinterpret_cast<double*>(c->work + c->off_U2);
+}
+
+int run_diag(nsk_ctx* c, double* h) {
+  StageArgs st{0.0, 0.0, 0.0, 0};
+  int rc = dispatch(c, 1, state_buf(c, c->cur), nullptr, nullptr, st);
+  if (rc) return rc;
+  if (hipMemcpyAsync(h, c->work + c->off_out, sizeof(double) * kDiagSlots, hipMemcpyDeviceToHost, c->stream) !=
+      hipSuccess)
+    return NSK_EHIP;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return NSK_EHIP;
+  return NSK_OK;
 }
 
 }  // namespace
@@ -404,6 +466,8 @@ int nsk_create(const nsk_mesh* mesh, const nsk_params* params, nsk_ctx** out) {
   }
   c->off_wq = off;
   off = align256(off + sizeof(double) * kMaxNP);
+  c->off_order = off;
+  off = align256(off + sizeof(int) * (size_t)c->E);
   long long blk = (c->E + kDiagThreads - 1) / kDiagThreads;
   c->diag_blocks = (int)(blk < 1024 ? blk : 1024);
   c->off_part = off;
@@ -411,6 +475,8 @@ int nsk_create(const nsk_mesh* mesh, const nsk_params* params, nsk_ctx** out) {
   c->off_out = off;
   off = align256(off + sizeof(double) * 16);
   c->ws_bytes = off;
+  // default launch shape: tiled work order in 3D, natural order otherwise
+  c->order = c->dim == 3 ? 4 : 0;
   *out = c;
   return NSK_OK;
 }
@@ -480,6 +546,8 @@ int nsk_bind(nsk_ctx* c, double* d_U, double* d_dU, void* d_work, void* hip_stre
   if (hipMemsetAsync(c->dU, 0, sizeof(double) * nsk_state_size(c), c->stream) != hipSuccess) return NSK_EHIP;
   // the host arrays above are stack/heap memory owned here: wait for the copies
   if (hipStreamSynchronize(c->stream) != hipSuccess) return NSK_EHIP;
+  int rc = upload_order(c, c->order);
+  if (rc) return rc;
   c->bound = true;
   return NSK_OK;
 }
@@ -534,17 +602,6 @@ int nsk_rk_step(nsk_ctx* c, double dt, int nsteps) {
   return NSK_OK;
 }
 
-static int run_diag(nsk_ctx* c, double* h) {
-  StageArgs st{0.0, 0.0, 0.0, 0};
-  int rc = dispatch(c, 1, state_buf(c, c->cur), nullptr, nullptr, st);
-  if (rc) return rc;
-  if (hipMemcpyAsync(h, c->work + c->off_out, sizeof(double) * kDiagSlots, hipMemcpyDeviceToHost, c->stream) !=
-      hipSuccess)
-    return NSK_EHIP;
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return NSK_EHIP;
-  return NSK_OK;
-}
-
 int nsk_diagnostics(nsk_ctx* c, nsk_diag* o) {
   if (!c || !o) return NSK_EINVAL;
   if (!c->bound) return NSK_EUNBOUND;
@@ -591,28 +648,35 @@ int nsk_dt_estimate(nsk_ctx* c, double cfl, double* dt_out) {
   return NSK_OK;
 }
 
-int nsk_set_tile(nsk_ctx* c, int variant, int xcd_remap) {
-  if (!c || (variant != 0 && variant != 1) || (xcd_remap != 0 && xcd_remap != 1)) return NSK_EINVAL;
+int nsk_set_tile(nsk_ctx* c, int variant, int order) {
+  if (!c || variant < 0 || variant >= kTileVariants || order < 0 || order >= kOrders) return NSK_EINVAL;
   c->tile = variant;
-  c->nxcd = xcd_remap ? 8 : 1;
-  return NSK_OK;
+  if (!c->bound) {
+    c->order = order;
+    return NSK_OK;
+  }
+  return order == c->order ? NSK_OK : upload_order(c, order);
 }
 
-int nsk_autotune(nsk_ctx* c, int reps, int* variant_out, int* remap_out, double* ms_out) {
+int nsk_autotune(nsk_ctx* c, int reps, int* variant_out, int* order_out, double* ms_out) {
   if (!c || reps < 1) return NSK_EINVAL;
   if (!c->bound) return NSK_EUNBOUND;
   if (c->cur != 0) return NSK_EINVAL;  // the scratch state buffer must be free
-  const int keep_tile = c->tile, keep_nxcd = c->nxcd;
+  const int keep_tile = c->tile, keep_order = c->order;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return NSK_EHIP;
   if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return NSK_EHIP; }
   StageArgs st{0.0, 0.0, 0.0, 0};
   double best = INFINITY;
-  int bv = keep_tile, br = keep_nxcd > 1;
+  int bv = keep_tile, bo = keep_order;
   int rc = NSK_OK;
-  for (int k = 0; k < 4 && rc == NSK_OK; ++k) {
-    c->tile = k >> 1;
-    c->nxcd = (k & 1) ? 8 : 1;
+  for (int k = 0; k < kTileVariants * kOrders && rc == NSK_OK; ++k) {
+    const int v = k / kOrders, o = k % kOrders;
+    if (ms_out) ms_out[k] = -1.0;
+    // orders that coincide for this mesh (1D, or the same tiles) are skipped
+    if (o >= 2 && c->dim == 1) continue;
+    rc = nsk_set_tile(c, v, o);
+    if (rc) break;
     // right-hand side of the bound state written into the scratch state buffer
     rc = dispatch(c, 0, c->U, state_buf(c, 1), nullptr, st);
     if (rc) break;
@@ -627,14 +691,14 @@ int nsk_autotune(nsk_ctx* c, int reps, int* variant_out, int* remap_out, double*
     }
     const double per = ms / reps;
     if (ms_out) ms_out[k] = per;
-    if (per < best) { best = per; bv = k >> 1; br = k & 1; }
+    if (per < best) { best = per; bv = v; bo = o; }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  c->tile = rc == NSK_OK ? bv : keep_tile;
-  c->nxcd = rc == NSK_OK ? (br ? 8 : 1) : keep_nxcd;
+  int rc2 = nsk_set_tile(c, rc == NSK_OK ? bv : keep_tile, rc == NSK_OK ? bo : keep_order);
+  if (rc == NSK_OK) rc = rc2;
   if (variant_out) *variant_out = c->tile;
-  if (remap_out) *remap_out = c->nxcd > 1;
+  if (order_out) *order_out = c->order;
   return rc;
 }
 

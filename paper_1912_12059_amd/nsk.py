@@ -194,13 +194,13 @@ def nsk_set_params(ctx: int, params: nsk_params) -> None:
     _check("nsk_set_params", load().nsk_set_params(ctx, C.byref(params)))
 
 
-def nsk_set_tile(ctx: int, variant: int, xcd_remap: int) -> None:
-    _check("nsk_set_tile", load().nsk_set_tile(ctx, variant, xcd_remap))
+def nsk_set_tile(ctx: int, variant: int, order: int) -> None:
+    _check("nsk_set_tile", load().nsk_set_tile(ctx, variant, order))
 
 
 def nsk_autotune(ctx: int, reps: int = 3) -> tuple[int, int, list]:
     v, r = C.c_int(), C.c_int()
-    ms = (C.c_double * 4)()
+    ms = (C.c_double * 12)()
     _check("nsk_autotune", load().nsk_autotune(ctx, reps, C.byref(v), C.byref(r), ms))
     return v.value, r.value, list(ms)
 

@@ -181,14 +181,15 @@ def test_bitwise_determinism(gpu):
 
 @pytest.mark.parametrize("dim,N,nel", [(1, 3, (37,)), (2, 4, (13, 11)), (3, 3, (7, 5, 3)), (3, 4, (5, 5, 3))])
 def test_launch_shapes_bitwise_identical(gpu, dim, N, nel):
-    """Every (elements-per-workgroup, XCD order) launch shape gives the same
-    bits, for ragged element counts that leave partial workgroups."""
+    """Every (elements-per-workgroup, element work order) launch shape gives
+    the same bits, for ragged element counts that leave partial workgroups
+    and partial tiles."""
     m, U = I.smooth_random(dim, N, nel, seed=40 + N)
     outs = []
     for variant in (0, 1):
-        for remap in (0, 1):
+        for order in range(6):
             s = _solver(gpu, m, **PHYS)
-            gpu.nsk_set_tile(s.ctx, variant, remap)
+            gpu.nsk_set_tile(s.ctx, variant, order)
             s.set_state(U)
             s.rk_step(1e-6, 3)
             outs.append(s.get_state().cpu().numpy())
@@ -202,8 +203,8 @@ def test_autotune_keeps_results(gpu):
     m, U = I.smooth_random(3, 4, (6, 5, 4), seed=8)
     s = _solver(gpu, m, **PHYS)
     s.set_state(U)
-    variant, remap, ms = gpu.nsk_autotune(s.ctx, 2)
-    assert variant in (0, 1) and remap in (0, 1) and all(x > 0 for x in ms)
+    variant, order, ms = gpu.nsk_autotune(s.ctx, 2)
+    assert variant in (0, 1) and 0 <= order < 6 and all(x > 0 or x == -1 for x in ms)
     got = s.get_state().cpu().numpy()
     assert np.array_equal(got, U)  # autotuning does not touch the state
     s.close()
