@@ -108,13 +108,134 @@ def cpu_baseline(name: str, sample, sub, budget_s: float = 20.0):
     }
 
 
+def run_form(nsk, m, U0, w, precision: int, steps: int, warmup: int, tile: str):
+    """Time `steps` LSRK4(5) steps of one precision form from the resident
+    state U0 (torch, device).  Returns timings, the stage-kernel means from
+    HIP events on the bound stream, and the final state (device)."""
+    import torch
+
+    s = nsk.Solver(dim=m.dim, N=m.N, nel=tuple(m.nel), lo=tuple(m.lo), hi=tuple(m.hi), alpha=w["alpha"],
+                   beta=1e-3, eps=1e-3, kappa=1e-5, precision=precision)
+    s.set_state(U0)
+    dt = s.dt_estimate(0.5)
+    if tile == "auto":
+        variant, order, tune_ms = nsk.nsk_autotune(s.ctx, 3)
+    else:
+        variant, order = (int(x) for x in tile.split(","))
+        nsk.nsk_set_tile(s.ctx, variant, order)
+        tune_ms = None
+    print(f"[bench] precision={precision} tile variant={variant} order={order} dt={dt:.4e}", file=sys.stderr,
+          flush=True)
+    # warm-up from the initial state, then restart from it for the timed steps
+    s.rk_step(dt, warmup)
+    s.set_state(U0)
+    torch.cuda.synchronize()
+    nsk.nsk_timing_enable(s.ctx, 1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s.stream)
+    t0 = time.perf_counter()
+    s.rk_step(dt, steps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    ms_lift, ms_rhs, nst = nsk.nsk_timing_read(s.ctx)
+    nsk.nsk_timing_enable(s.ctx, 0)
+    diag = s.diagnostics()
+    final = s.get_state()
+    s.close()
+    return {"ms": ms, "wall": wall, "ms_lift": ms_lift / max(nst, 1), "ms_rhs": ms_rhs / max(nst, 1), "dt": dt,
+            "variant": variant, "order": order, "tune_ms": tune_ms, "diag": diag, "final": final}
+
+
+def run_batched(nsk, steps: int, warmup: int):
+    """The batched collision sweep: 24 3D head-on collisions (n_x x 32 x 32
+    elements, n_x in 32..64, N in {3,4,5}, We ~ U[5,150], impact ~ U[0,0.5] R,
+    alpha = 1000) in mixed precision, advanced as one batch (per-degree
+    persistent kernels, two steps per graph replay), against the same 24
+    instances run one after another in plain FP64."""
+    import torch
+
+    from paper_1912_12059_amd import inputs as I
+
+    sweep = I.batched_sweep()
+    steps += steps % 2  # whole graph replays
+    meshes = [{"nel": s["nel"], "N": s["N"], "lo": s["lo"], "hi": s["hi"]} for s in sweep]
+    print(f"[bench] batched sweep: {len(sweep)} instances", file=sys.stderr, flush=True)
+    init = []
+    for s in sweep:
+        _, U = I.collision_3d(nel=s["nel"], N=s["N"], We=s["We"], radius=s["radius"], lo=s["lo"], hi=s["hi"],
+                              impact=s["impact"], device="cuda:0")
+        init.append(U.reshape(-1))
+    dofs = [u.numel() // 5 for u in init]
+    b = nsk.Batch(meshes, alpha=1000.0, beta=1e-3, eps=1e-3, kappa=1e-5, precision=1)
+    for i, u in enumerate(init):
+        b.set_state(i, u)
+    dt = b.dt_estimate(0.5)
+    tune_ms = nsk.nsk_batch_autotune(b.b, 2)
+    groups = nsk.nsk_batch_groups(b.b)
+    b.rk_step(dt, warmup + warmup % 2)
+    for i, u in enumerate(init):
+        b.set_state(i, u)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(b.stream)
+    b.rk_step(dt, steps)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    ms_batch = e0.elapsed_time(e1)
+    finals = [b.get_state(i) for i in range(len(sweep))]
+    b.close()
+    del b
+    # sequential plain FP64, same states and dt
+    ms_seq, l2max = 0.0, 0.0
+    for i, s in enumerate(sweep):
+        sv = nsk.Solver(dim=3, N=s["N"], nel=s["nel"], lo=s["lo"], hi=s["hi"], alpha=1000.0, beta=1e-3, eps=1e-3,
+                        kappa=1e-5, precision=0)
+        sv.set_state(init[i])
+        nsk.nsk_autotune(sv.ctx, 2)
+        sv.rk_step(dt, 1)
+        sv.set_state(init[i])
+        torch.cuda.synchronize()
+        e0.record(sv.stream)
+        sv.rk_step(dt, steps)
+        e1.record(sv.stream)
+        torch.cuda.synchronize()
+        ms_seq += e0.elapsed_time(e1)
+        ref = sv.get_state().reshape(-1)
+        sv.close()
+        n = dofs[i]
+        l2 = float(torch.linalg.vector_norm(finals[i][:n] - ref[:n]) / torch.linalg.vector_norm(ref[:n]))
+        l2max = max(l2max, l2)
+    work = sum(dofs) * 5 * steps
+    return {
+        "instances": len(sweep),
+        "dofs": sum(dofs),
+        "steps": steps,
+        "dt": dt,
+        "precision": "mixed (FP32 volume/surface, FP64 state, RK, source, near-spinodal EoS)",
+        "value": work / (ms_batch * 1e-3),
+        "unit": "DOF-stage/s",
+        "ms_per_step": ms_batch / steps,
+        "sequential_fp64_value": work / (ms_seq * 1e-3),
+        "speedup_vs_sequential_fp64": ms_seq / ms_batch,
+        "max_l2_rel_rho_vs_fp64": l2max,
+        "groups": groups,
+        "autotune_ms": tune_ms[: 8 * len(groups)],
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--workload", default="3d-collision", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="form reported as value; the other one is measured beside it unless --no-forms")
+    ap.add_argument("--no-forms", action="store_true", help="skip the second precision form and the batch")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched collision sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="auto", help="auto (autotuner) or 'variant,order', e.g. 0,4")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -140,12 +261,9 @@ def main() -> int:
     from paper_1912_12059_amd import nsk
 
     w = WORKLOADS[args.workload]
-    mixed = args.precision == "mixed"
     print(f"[bench] building {args.workload} state", file=sys.stderr, flush=True)
     m, U = build_state(args.workload)
-    s = nsk.Solver(dim=m.dim, N=m.N, nel=tuple(m.nel), lo=tuple(m.lo), hi=tuple(m.hi), alpha=w["alpha"],
-                   beta=1e-3, eps=1e-3, kappa=1e-5, precision=1 if mixed else 0)
-    s.set_state(torch.from_numpy(U.reshape(-1)))
+    U0 = torch.from_numpy(U.reshape(-1)).to("cuda:0")
     if m.dim == 3:
         sub = (16, 16, 16)
         block = ((24, 16), (16, 16), (16, 16))  # around the first droplet's interface
@@ -154,41 +272,22 @@ def main() -> int:
         block = ((16, 32), (32, 32))
     sample = None if args.no_cpu_baseline else sample_block(U, m.nel, block)
     del U
-    dt = s.dt_estimate(0.5)
-    if args.tile == "auto":
-        variant, order, tune_ms = nsk.nsk_autotune(s.ctx, 3)
-    else:
-        variant, order = (int(x) for x in args.tile.split(","))
-        nsk.nsk_set_tile(s.ctx, variant, order)
-        tune_ms = None
-    print(f"[bench] tile variant={variant} order={order} tune_ms={tune_ms}", file=sys.stderr, flush=True)
-    print(f"[bench] dt={dt:.4e}, warmup {args.warmup} steps", file=sys.stderr, flush=True)
-    s.rk_step(dt, args.warmup)
-    torch.cuda.synchronize()
-    nsk.nsk_timing_enable(s.ctx, 1)
-    dev = torch.device("cuda:0")
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(s.stream)
-    t0 = time.perf_counter()
-    s.rk_step(dt, args.steps)
-    e1.record(s.stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    ms_lift, ms_rhs, nst = nsk.nsk_timing_read(s.ctx)
-    nsk.nsk_timing_enable(s.ctx, 0)
-    diag = s.diagnostics()
     dofs = m.nelem * m.nnode
-    rate = dofs * 5 * args.steps / (ms * 1e-3)
+    main_prec = 1 if args.precision == "mixed" else 0
+    forms = {}
+    order = [main_prec] if args.no_forms else [main_prec, 1 - main_prec]
+    for prec in order:
+        forms[prec] = run_form(nsk, m, U0, w, prec, args.steps, args.warmup, args.tile)
+    r = forms[main_prec]
+    mixed = main_prec == 1
+    rate = dofs * 5 * args.steps / (r["ms"] * 1e-3)
     bp_first = bytes_per_node(m.dim, True, mixed)
     bp = bytes_per_node(m.dim, False, mixed)
     # average algorithmic bytes per launch of the rhs kernel over the 5 stages
     rhs_bytes = dofs * (bp_first["rhs"] + 4 * bp["rhs"]) / 5.0
     lift_bytes = dofs * bp["lift"]
-    avg_rhs_ms = ms_rhs / max(nst, 1)
-    avg_lift_ms = ms_lift / max(nst, 1)
-    achieved = rhs_bytes / (avg_rhs_ms * 1e-3) / 1e9
+    achieved = rhs_bytes / (r["ms_rhs"] * 1e-3) / 1e9
+    diag = r["diag"]
     out = {
         "metric": METRIC,
         "value": rate,
@@ -196,7 +295,7 @@ def main() -> int:
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
+        "ms_per_step": r["ms"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -208,8 +307,8 @@ def main() -> int:
             "dofs": dofs,
             "nvar": m.nvar,
             "precision": args.precision,
-            "dt": dt,
-            "tile": {"variant": variant, "order": order, "autotune_ms": tune_ms},
+            "dt": r["dt"],
+            "tile": {"variant": r["variant"], "order": r["order"], "autotune_ms": r["tune_ms"]},
         },
         "roofline": {
             "bound": "hbm",
@@ -219,16 +318,34 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
-            "avg_ms": avg_rhs_ms,
-            "lift_avg_ms": avg_lift_ms,
-            "lift_achieved_GBs": lift_bytes / (avg_lift_ms * 1e-3) / 1e9 if avg_lift_ms > 0 else None,
+            "avg_ms": r["ms_rhs"],
+            "bytes_per_launch": rhs_bytes,
+            "lift_avg_ms": r["ms_lift"],
+            "lift_achieved_GBs": lift_bytes / (r["ms_lift"] * 1e-3) / 1e9 if r["ms_lift"] > 0 else None,
             "stage_bytes_per_node": (bp["lift"] + bp["rhs"]),
-            "stage_GBs": dofs * (bp["lift"] + bp["rhs"]) / ((avg_rhs_ms + avg_lift_ms) * 1e-3) / 1e9,
+            "stage_GBs": dofs * (bp["lift"] + bp["rhs"]) / ((r["ms_rhs"] + r["ms_lift"]) * 1e-3) / 1e9,
         },
         "diag_after": {"mass_rho": diag["mass"][0], "e_total": diag["e_total"], "status": diag["status"]},
-        "wall_s": wall,
+        "wall_s": r["wall"],
     }
-    s.close()
+    if len(forms) == 2:
+        f64, mx = forms[0], forms[1]
+        rho64 = f64["final"][0].reshape(-1)
+        rhom = mx["final"][0].reshape(-1)
+        l2 = float(torch.linalg.vector_norm(rhom - rho64) / torch.linalg.vector_norm(rho64))
+        out["forms"] = {
+            "fp64": {"value": dofs * 5 * args.steps / (f64["ms"] * 1e-3), "ms_per_step": f64["ms"] / args.steps,
+                     "rhs_ms": f64["ms_rhs"], "lift_ms": f64["ms_lift"]},
+            "mixed": {"value": dofs * 5 * args.steps / (mx["ms"] * 1e-3), "ms_per_step": mx["ms"] / args.steps,
+                      "rhs_ms": mx["ms_rhs"], "lift_ms": mx["ms_lift"],
+                      "speedup_vs_fp64": f64["ms"] / mx["ms"],
+                      "l2_rel_rho_vs_fp64": l2,
+                      "l2_note": f"relative L2 of rho, mixed vs FP64 GPU run, same initial state and dt, "
+                                 f"after {args.steps} steps"},
+        }
+    del forms
+    if not args.no_forms and not args.no_batched and args.workload == "3d-collision":
+        out.setdefault("forms", {})["batched"] = run_batched(nsk, 10, 2)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, sample, sub)

@@ -174,6 +174,65 @@ int nsk_set_params(nsk_ctx* ctx, const nsk_params* params);
 int nsk_timing_enable(nsk_ctx* ctx, int enable);
 int nsk_timing_read(nsk_ctx* ctx, double out[3]);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many 3D instances of uneven mesh size and degree advanced
+ * together with one shared parameter set and one shared time step.  The
+ * states of all instances are packed into one device buffer; instance i
+ * starts nsk_batch_state_offset(i) doubles into it and has the layout of a
+ * single context.  Instances of one degree form a group; each stage runs one
+ * persistent lifting and one persistent right-hand-side kernel per group,
+ * and two full steps (ten stages) are captured into one HIP graph that
+ * nsk_batch_rk_step replays.
+ * ------------------------------------------------------------------------ */
+typedef struct nsk_batch nsk_batch;
+
+/* meshes[0..ninst-1] must all be 3D (NSK_EUNSUPPORTED otherwise); the
+ * validation rules of nsk_create apply per instance.  Host only. */
+int nsk_batch_create(const nsk_mesh* meshes, int ninst, const nsk_params* params, nsk_batch** out);
+
+/* Frees the batch and its instance contexts (waits for the bound stream). */
+void nsk_batch_destroy(nsk_batch* b);
+
+/* Doubles in the packed state buffer (each instance slice 256-byte aligned). */
+size_t nsk_batch_state_size(const nsk_batch* b);
+
+/* Offset in doubles of instance inst inside the packed state buffer. */
+size_t nsk_batch_state_offset(const nsk_batch* b, int inst);
+
+/* Bytes of device workspace nsk_batch_bind expects. */
+size_t nsk_batch_workspace_bytes(const nsk_batch* b);
+
+/* Binds caller-owned device memory: d_U and d_dU hold nsk_batch_state_size()
+ * doubles each, d_work nsk_batch_workspace_bytes() bytes; all 256-byte
+ * aligned.  hip_stream must be a created stream (not the null stream), since
+ * the step graph is captured on it. */
+int nsk_batch_bind(nsk_batch* b, double* d_U, double* d_dU, void* d_work, void* hip_stream);
+
+/* Context of instance inst (owned by the batch, bound to its slices): use it
+ * with nsk_set_state, nsk_get_state, nsk_rhs and nsk_diagnostics.  Do not
+ * destroy it, rebind it or step it with nsk_rk_step. */
+int nsk_batch_ctx(nsk_batch* b, int inst, nsk_ctx** out);
+
+/* Smallest nsk_dt_estimate over the instances.  Waits for the stream. */
+int nsk_batch_dt_estimate(nsk_batch* b, double cfl, double* dt_out);
+
+/* Advances every instance by nsteps steps of size dt: nsteps/2 replays of
+ * the captured two-step graph (re-captured when dt changes), then one
+ * ordinary step if nsteps is odd.  Asynchronous. */
+int nsk_batch_rk_step(nsk_batch* b, double dt, int nsteps);
+
+/* Autotuner per degree group: times `reps` evaluations of the group's two
+ * persistent kernels (right-hand side into scratch) for each
+ * elements-per-workgroup variant (0, 1) and persistent grid of 1, 2, 4, 8
+ * workgroups per CU, keeps the fastest per group.  ms_out (may be NULL,
+ * 8 doubles per group) receives the means at group*8 + variant*4 + grid
+ * index.  Call between steps; waits for the stream. */
+int nsk_batch_autotune(nsk_batch* b, int reps, double* ms_out);
+
+/* Describes up to max groups: polynomial degree, chosen variant and grid
+ * multiplier.  Returns the number of groups. */
+int nsk_batch_groups(const nsk_batch* b, int* N_out, int* variant_out, int* gridmul_out, int max);
+
 /* Static text for an NSK_* code. */
 const char* nsk_strerror(int code);
 

@@ -7,9 +7,10 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 REPO = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libnsk.so")
-SOURCES = [os.path.join(HERE, "csrc", "nsk.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "nsk.hip"), os.path.join(HERE, "csrc", "batch.hip")]
 DEPENDS = SOURCES + [
     os.path.join(HERE, "csrc", "dg_kernels.hpp"),
+    os.path.join(HERE, "csrc", "host_common.hpp"),
     os.path.join(REPO, "include", "nsk.h"),
 ]
 
@@ -26,10 +27,19 @@ FLAGS = [
 
 
 def build_lib() -> str:
+    """Compile every source to an object in parallel, then link libnsk.so."""
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(HERE, "csrc", os.path.basename(src) + ".o")
+        objs.append(obj)
+        procs.append(subprocess.Popen([HIPCC] + [f for f in FLAGS if f != "-shared"] + ["-c", "-o", obj, src]))
+    if any(p.wait() != 0 for p in procs):
+        raise RuntimeError("hipcc failed")
     tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + SOURCES
-    subprocess.check_call(cmd)
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, LIB)
+    for obj in objs:
+        os.remove(obj)
     return LIB
 
 

@@ -170,9 +170,8 @@ struct ElemInfo {
 };
 
 template <int DIM, int EPB>
-__device__ __forceinline__ void elem_info(ElemInfo<DIM, EPB>& info, const MeshArgs& m, int tid) {
+__device__ __forceinline__ void elem_info(ElemInfo<DIM, EPB>& info, const MeshArgs& m, int L, int tid) {
   if (tid < EPB) {
-    const int L = remap_block(blockIdx.x, gridDim.x, m.nxcd);
     const int pos = L * EPB + tid;
     const int e = pos < m.E ? m.order[pos] : -1;
     info.e[tid] = e;
@@ -228,8 +227,8 @@ __device__ __forceinline__ void conv_flux(int d, const R* u, R irho, R pa, R* F)
 // along each d-line, w* = (w_left + w_right) / 2 on the faces.
 // -------------------------------------------------------------------------
 template <int DIM, int NP, int EPB, typename R, typename GT>
-__global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
-lift_kernel(const double* __restrict__ U, GT* __restrict__ G, BasisArgs bas, MeshArgs msh, PhysArgs ph) {
+__device__ __forceinline__ void lift_block(int L, const double* __restrict__ U, GT* __restrict__ G,
+                                           const BasisArgs& bas, const MeshArgs& msh, const PhysArgs& ph) {
   using Sh = Shape<DIM, NP>;
   constexpr int NN = Sh::NN, NF = Sh::NF, NL = Sh::NLIFT;
   __shared__ R sW[EPB][NL][NN];             // nodal primitives (v, c)
@@ -243,7 +242,7 @@ lift_kernel(const double* __restrict__ U, GT* __restrict__ G, BasisArgs bas, Mes
   const long long S = msh.S;
   if (tid < NP * NP) sD[tid / NP][tid % NP] = R(bas.Dhat[tid / NP][tid % NP]);
   if (tid < NP) { sLm[tid] = R(bas.Lm[tid]); sLp[tid] = R(bas.Lp[tid]); sIw[tid] = R(bas.invw[tid]); }
-  elem_info<DIM, EPB>(info, msh, tid);
+  elem_info<DIM, EPB>(info, msh, L, tid);
   __syncthreads();
 
   const int el = tid / NN, n = tid - (tid / NN) * NN;
@@ -347,9 +346,9 @@ lift_kernel(const double* __restrict__ U, GT* __restrict__ G, BasisArgs bas, Mes
 //   dU <- A dU + dt R,  U <- U + B dU.
 // -------------------------------------------------------------------------
 template <int DIM, int NP, int EPB, typename R, typename GT>
-__global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
-rhs_kernel(const double* __restrict__ U, const GT* __restrict__ G, double* __restrict__ Uout,
-           double* __restrict__ dU, BasisArgs bas, MeshArgs msh, PhysArgs ph, StageArgs st) {
+__device__ __forceinline__ void rhs_block(int L, const double* __restrict__ U, const GT* __restrict__ G,
+                                          double* __restrict__ Uout, double* __restrict__ dU, const BasisArgs& bas,
+                                          const MeshArgs& msh, const PhysArgs& ph, const StageArgs& st) {
   using Sh = Shape<DIM, NP>;
   constexpr int NN = Sh::NN, NF = Sh::NF, NV = Sh::NVAR, NT = Sh::NTAU, NG = Sh::NG;
   constexpr int NX = NV + DIM + 1;          // per node: U and the viscous flux components of direction d
@@ -368,7 +367,7 @@ rhs_kernel(const double* __restrict__ U, const GT* __restrict__ G, double* __res
   const long long S = msh.S;
   if (tid < NP * NP) sD[tid / NP][tid % NP] = R(bas.Dhat[tid / NP][tid % NP]);
   if (tid < NP) { sLm[tid] = R(bas.Lm[tid]); sLp[tid] = R(bas.Lp[tid]); sIw[tid] = R(bas.invw[tid]); }
-  elem_info<DIM, EPB>(info, msh, tid);
+  elem_info<DIM, EPB>(info, msh, L, tid);
   __syncthreads();
 
   const int el = tid / NN, n = tid - (tid / NN) * NN;
@@ -543,6 +542,69 @@ rhs_kernel(const double* __restrict__ U, const GT* __restrict__ G, double* __res
 }
 
 // -------------------------------------------------------------------------
+// One launch per stage kernel over a single mesh.
+// -------------------------------------------------------------------------
+template <int DIM, int NP, int EPB, typename R, typename GT>
+__global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
+lift_kernel(const double* __restrict__ U, GT* __restrict__ G, BasisArgs bas, MeshArgs msh, PhysArgs ph) {
+  lift_block<DIM, NP, EPB, R, GT>(remap_block(blockIdx.x, gridDim.x, msh.nxcd), U, G, bas, msh, ph);
+}
+
+template <int DIM, int NP, int EPB, typename R, typename GT>
+__global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
+rhs_kernel(const double* __restrict__ U, const GT* __restrict__ G, double* __restrict__ Uout,
+           double* __restrict__ dU, BasisArgs bas, MeshArgs msh, PhysArgs ph, StageArgs st) {
+  rhs_block<DIM, NP, EPB, R, GT>(remap_block(blockIdx.x, gridDim.x, msh.nxcd), U, G, Uout, dU, bas, msh, ph, st);
+}
+
+// -------------------------------------------------------------------------
+// Persistent kernels over a batch of instances with the same degree.  The
+// work list holds (instance, logical block) items; workgroup w takes the
+// contiguous item range [w * chunk, (w + 1) * chunk), so that consecutive
+// blocks of one instance's tiled work order stay on one XCD.
+// -------------------------------------------------------------------------
+struct BatchInst {
+  const double* U;     // stage input state
+  double* Uout;        // stage output state (or R)
+  double* dU;          // Runge-Kutta register
+  void* G;             // lifted gradients (tau, grad c)
+  MeshArgs msh;        // mesh of the instance (nxcd unused)
+};
+
+struct BatchItem {
+  int inst;            // instance index
+  int L;               // logical block of that instance
+};
+
+template <int DIM, int NP, int EPB, typename R, typename GT>
+__global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
+lift_kernel_batch(const BatchInst* __restrict__ inst, const BatchItem* __restrict__ items, int nitems, int chunk,
+                  BasisArgs bas, PhysArgs ph) {
+  const int first = blockIdx.x * chunk;
+  const int last = min(nitems, first + chunk);
+  for (int it = first; it < last; ++it) {
+    const BatchItem w = items[it];
+    const BatchInst& I = inst[w.inst];
+    lift_block<DIM, NP, EPB, R, GT>(w.L, I.U, reinterpret_cast<GT*>(I.G), bas, I.msh, ph);
+    __syncthreads();  // LDS is reused by the next item
+  }
+}
+
+template <int DIM, int NP, int EPB, typename R, typename GT>
+__global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
+rhs_kernel_batch(const BatchInst* __restrict__ inst, const BatchItem* __restrict__ items, int nitems, int chunk,
+                 BasisArgs bas, PhysArgs ph, StageArgs st) {
+  const int first = blockIdx.x * chunk;
+  const int last = min(nitems, first + chunk);
+  for (int it = first; it < last; ++it) {
+    const BatchItem w = items[it];
+    const BatchInst& I = inst[w.inst];
+    rhs_block<DIM, NP, EPB, R, GT>(w.L, I.U, reinterpret_cast<const GT*>(I.G), I.Uout, I.dU, bas, I.msh, ph, st);
+    __syncthreads();
+  }
+}
+
+// -------------------------------------------------------------------------
 // Diagnostics: per-block partial sums, then one block reduces in a fixed
 // order (deterministic).  Slots: 0..4 conserved integrals, 5 kinetic energy,
 // 6 E^alpha, 7 (rho-c)^2, 8 rho min, 9 rho max, 10 max wave speed,
@@ -642,6 +704,7 @@ diag_partial_kernel(const double* __restrict__ U, const GT* __restrict__ G, doub
   if (tid < kDiagSlots) part[(long long)blockIdx.x * kDiagSlots + tid] = red[tid][0];
 }
 
+template <int SLOTS>
 __global__ void __launch_bounds__(kDiagThreads) diag_final_kernel(const double* __restrict__ part, int nblocks,
                                                                   double* __restrict__ out) {
   __shared__ double red[kDiagSlots][kDiagThreads];

@@ -133,11 +133,13 @@ def collision_speed(We: float, radius: float, rho_l: float, sigma: float) -> flo
 
 def collision_3d(nel=(96, 48, 48), N: int = 4, We: float = 40.0, radius: float = 0.2,
                  lo=(0.0, 0.0, 0.0), hi=(2.0, 1.0, 1.0), centres=None, width: float = 0.02,
-                 impact: float = 0.0, noise: float = 0.0, seed: int = SEED_NOISE, dtype=np.float64):
+                 impact: float = 0.0, noise: float = 0.0, seed: int = SEED_NOISE, dtype=np.float64,
+                 device=None):
     """Two droplets of radius R approaching head-on along x (initial
     condition of Sec. 4.3.1, density written as rho_v + (rho_l - rho_v)/2
     sum_i [1 - tanh((d_i - R)/w)]).  ``impact`` offsets the droplets by
-    -+impact/2 in y."""
+    -+impact/2 in y.  With ``device`` (a torch device string) the same state
+    is built there with torch and returned as a torch tensor (no noise)."""
     kc = constants()
     yl = kc["young_laplace"][f"{radius:.3f}"]
     rl, rv = yl["rho_l"], yl["rho_v"]
@@ -149,23 +151,31 @@ def collision_3d(nel=(96, 48, 48), N: int = 4, We: float = 40.0, radius: float =
         centres = ((xm - 0.15 * Lx, cy - 0.5 * impact, cz), (xm + 0.15 * Lx, cy + 0.5 * impact, cz))
     m = Mesh(3, N, tuple(nel), tuple(lo), tuple(hi))
     X = node_coords(m)
+    if device is not None:
+        import torch as xp
+
+        X = xp.from_numpy(X).to(device)
+        minimg = lambda dx, L: dx - L * xp.round(dx / L)
+    else:
+        xp = np
+        minimg = _min_image
     L = [hi[d] - lo[d] for d in range(3)]
     prof = []
     for c in centres:
-        dist = np.sqrt(sum(_min_image(X[d] - c[d], L[d]) ** 2 for d in range(3)))
-        prof.append(1.0 - np.tanh((dist - radius) / width))
+        dist = xp.sqrt(sum(minimg(X[d] - c[d], L[d]) ** 2 for d in range(3)))
+        prof.append(1.0 - xp.tanh((dist - radius) / width))
     rho = rv + 0.5 * (rl - rv) * (prof[0] + prof[1])
     xm = 0.5 * (centres[0][0] + centres[1][0])
-    vx = np.where(X[0] < xm, 0.5 * U * prof[0], -0.5 * U * prof[1])
+    vx = xp.where(X[0] < xm, 0.5 * U * prof[0], -0.5 * U * prof[1])
     del X
-    if noise:
+    if noise and device is None:
         rho = rho + np.random.Generator(np.random.PCG64(seed)).uniform(-noise, noise, rho.shape)
-    z = np.zeros_like(rho)
-    out = np.empty((5,) + rho.shape, dtype=dtype)
+    if device is not None:
+        out = xp.zeros((5,) + tuple(rho.shape), dtype=xp.float64, device=device)
+    else:
+        out = np.zeros((5,) + rho.shape, dtype=dtype)
     out[0] = rho
     out[1] = rho * vx
-    out[2] = z
-    out[3] = z
     out[4] = rho
     return m, out
 

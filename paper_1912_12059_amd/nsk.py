@@ -95,6 +95,22 @@ def load() -> C.CDLL:
         L.nsk_set_params.argtypes = [vp, C.POINTER(nsk_params)]
         L.nsk_set_tile.argtypes = [vp, C.c_int, C.c_int]
         L.nsk_autotune.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), dp]
+        ip = C.POINTER(C.c_int)
+        L.nsk_batch_create.argtypes = [C.POINTER(nsk_mesh), C.c_int, C.POINTER(nsk_params), C.POINTER(vp)]
+        L.nsk_batch_destroy.argtypes = [vp]
+        L.nsk_batch_destroy.restype = None
+        L.nsk_batch_state_size.argtypes = [vp]
+        L.nsk_batch_state_size.restype = C.c_size_t
+        L.nsk_batch_state_offset.argtypes = [vp, C.c_int]
+        L.nsk_batch_state_offset.restype = C.c_size_t
+        L.nsk_batch_workspace_bytes.argtypes = [vp]
+        L.nsk_batch_workspace_bytes.restype = C.c_size_t
+        L.nsk_batch_bind.argtypes = [vp, vp, vp, vp, vp]
+        L.nsk_batch_ctx.argtypes = [vp, C.c_int, C.POINTER(vp)]
+        L.nsk_batch_dt_estimate.argtypes = [vp, C.c_double, dp]
+        L.nsk_batch_rk_step.argtypes = [vp, C.c_double, C.c_int]
+        L.nsk_batch_autotune.argtypes = [vp, C.c_int, dp]
+        L.nsk_batch_groups.argtypes = [vp, ip, ip, ip, C.c_int]
         L.nsk_timing_enable.argtypes = [vp, C.c_int]
         L.nsk_timing_read.argtypes = [vp, dp]
         L.nsk_strerror.argtypes = [C.c_int]
@@ -215,6 +231,63 @@ def nsk_timing_read(ctx: int) -> tuple[float, float, int]:
     return out[0], out[1], int(out[2])
 
 
+def nsk_batch_create(meshes: list, params: nsk_params) -> int:
+    arr = (nsk_mesh * len(meshes))(*meshes)
+    h = C.c_void_p()
+    _check("nsk_batch_create", load().nsk_batch_create(arr, len(meshes), C.byref(params), C.byref(h)))
+    return h.value
+
+
+def nsk_batch_destroy(b: int) -> None:
+    load().nsk_batch_destroy(b)
+
+
+def nsk_batch_state_size(b: int) -> int:
+    return load().nsk_batch_state_size(b)
+
+
+def nsk_batch_state_offset(b: int, inst: int) -> int:
+    return load().nsk_batch_state_offset(b, inst)
+
+
+def nsk_batch_workspace_bytes(b: int) -> int:
+    return load().nsk_batch_workspace_bytes(b)
+
+
+def nsk_batch_bind(b: int, d_U: int, d_dU: int, d_work: int, stream: int) -> None:
+    _check("nsk_batch_bind", load().nsk_batch_bind(b, d_U, d_dU, d_work, stream))
+
+
+def nsk_batch_ctx(b: int, inst: int) -> int:
+    h = C.c_void_p()
+    _check("nsk_batch_ctx", load().nsk_batch_ctx(b, inst, C.byref(h)))
+    return h.value
+
+
+def nsk_batch_dt_estimate(b: int, cfl: float) -> float:
+    out = C.c_double()
+    _check("nsk_batch_dt_estimate", load().nsk_batch_dt_estimate(b, cfl, C.byref(out)))
+    return out.value
+
+
+def nsk_batch_rk_step(b: int, dt: float, nsteps: int) -> None:
+    _check("nsk_batch_rk_step", load().nsk_batch_rk_step(b, dt, nsteps))
+
+
+def nsk_batch_autotune(b: int, reps: int = 2) -> list:
+    ng = load().nsk_batch_groups(b, None, None, None, 0)
+    ms = (C.c_double * (8 * max(ng, 1)))()
+    _check("nsk_batch_autotune", load().nsk_batch_autotune(b, reps, ms))
+    return list(ms)
+
+
+def nsk_batch_groups(b: int) -> list:
+    n = load().nsk_batch_groups(b, None, None, None, 0)
+    Ns, vs, gm = (C.c_int * n)(), (C.c_int * n)(), (C.c_int * n)()
+    load().nsk_batch_groups(b, Ns, vs, gm, n)
+    return [{"N": Ns[i], "variant": vs[i], "gridmul": gm[i]} for i in range(n)]
+
+
 # ---- convenience owner of the device buffers (torch) ----------------------
 @dataclass
 class Solver:
@@ -319,3 +392,73 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Owns a batch of 3D instances plus torch-allocated packed state,
+    register and workspace, and a dedicated stream (the step graph is
+    captured on it)."""
+
+    def __init__(self, meshes: list, T=0.85, eps=1e-3, kappa=1e-5, alpha=1000.0, beta=1e-3, diss_c=1,
+                 precision=1, device="cuda:0"):
+        import torch
+
+        keep, cm = [], []
+        for m in meshes:
+            mm, k = make_mesh(3, m["N"], m["nel"], m.get("lo", (0.0, 0.0, 0.0)), m.get("hi", (1.0, 1.0, 1.0)))
+            cm.append(mm)
+            keep.append(k)
+        params = make_params(T, eps, kappa, alpha, beta, diss_c, precision)
+        self.b = nsk_batch_create(cm, params)
+        self.ninst = len(meshes)
+        dev = torch.device(device)
+        self.stream = torch.cuda.Stream(dev)
+        n = nsk_batch_state_size(self.b)
+        self.U = torch.zeros(n, dtype=torch.float64, device=dev)
+        self.dU = torch.zeros(n, dtype=torch.float64, device=dev)
+        self.work = torch.zeros(nsk_batch_workspace_bytes(self.b) + 256, dtype=torch.uint8, device=dev)
+        wp = (self.work.data_ptr() + 255) // 256 * 256
+        torch.cuda.synchronize(dev)
+        nsk_batch_bind(self.b, self.U.data_ptr(), self.dU.data_ptr(), wp, self.stream.cuda_stream)
+        self.meshes = meshes
+        self.sizes = []
+        for i, m in enumerate(meshes):
+            nn = (m["N"] + 1) ** 3
+            self.sizes.append(5 * int(m["nel"][0]) * int(m["nel"][1]) * int(m["nel"][2]) * nn)
+
+    def view(self, i: int):
+        o = nsk_batch_state_offset(self.b, i)
+        return self.U[o:o + self.sizes[i]]
+
+    def set_state(self, i: int, U) -> None:
+        import torch
+
+        t = torch.as_tensor(U, dtype=torch.float64).reshape(-1)
+        self.stream.synchronize()
+        self.view(i).copy_(t.to(self.U.device))
+        torch.cuda.synchronize(self.U.device)
+
+    def get_state(self, i: int):
+        self.stream.synchronize()
+        return self.view(i).clone()
+
+    def ctx(self, i: int) -> int:
+        return nsk_batch_ctx(self.b, i)
+
+    def dt_estimate(self, cfl: float) -> float:
+        return nsk_batch_dt_estimate(self.b, cfl)
+
+    def rk_step(self, dt: float, nsteps: int) -> None:
+        nsk_batch_rk_step(self.b, dt, nsteps)
+
+    def close(self) -> None:
+        if self.b:
+            nsk_batch_destroy(self.b)
+            self.b = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
