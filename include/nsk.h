@@ -180,9 +180,10 @@ int nsk_timing_read(nsk_ctx* ctx, double out[3]);
  * states of all instances are packed into one device buffer; instance i
  * starts nsk_batch_state_offset(i) doubles into it and has the layout of a
  * single context.  Instances of one degree form a group; each stage runs one
- * persistent lifting and one persistent right-hand-side kernel per group,
- * and two full steps (ten stages) are captured into one HIP graph that
- * nsk_batch_rk_step replays.
+ * lifting and one right-hand-side kernel per group over the group's list of
+ * (instance, element block) items, either one workgroup per item or a
+ * persistent grid walking the list in rounds, and two full steps (ten
+ * stages) are captured into one HIP graph that nsk_batch_rk_step replays.
  * ------------------------------------------------------------------------ */
 typedef struct nsk_batch nsk_batch;
 
@@ -222,16 +223,21 @@ int nsk_batch_dt_estimate(nsk_batch* b, double cfl, double* dt_out);
 int nsk_batch_rk_step(nsk_batch* b, double dt, int nsteps);
 
 /* Autotuner per degree group: times `reps` evaluations of the group's two
- * persistent kernels (right-hand side into scratch) for each
- * elements-per-workgroup variant (0, 1) and persistent grid of 1, 2, 4, 8
- * workgroups per CU, keeps the fastest per group.  ms_out (may be NULL,
- * 8 doubles per group) receives the means at group*8 + variant*4 + grid
- * index.  Call between steps; waits for the stream. */
+ * kernels (right-hand side into scratch), first for each element order
+ * 0..5 of nsk_set_tile applied to every member instance, then, with the
+ * fastest order, for each elements-per-workgroup variant (0, 1) and grid
+ * multiplier m in {0, 2, 4, 8} (m = 0: one workgroup per item; otherwise a
+ * persistent grid of m workgroups per CU), and keeps the fastest per group.
+ * ms_out (may be NULL, 14 doubles per group) receives the means: at
+ * group*14 + variant*4 + multiplier index, and at group*14 + 8 + order.
+ * Call between steps; waits for the stream. */
 int nsk_batch_autotune(nsk_batch* b, int reps, double* ms_out);
 
-/* Describes up to max groups: polynomial degree, chosen variant and grid
- * multiplier.  Returns the number of groups. */
-int nsk_batch_groups(const nsk_batch* b, int* N_out, int* variant_out, int* gridmul_out, int max);
+/* Describes up to max groups: polynomial degree, chosen variant, grid
+ * multiplier (0: one workgroup per item) and element order of the member
+ * instances.  Any output pointer may be NULL.  Returns the number of
+ * groups. */
+int nsk_batch_groups(const nsk_batch* b, int* N_out, int* variant_out, int* gridmul_out, int* order_out, int max);
 
 /* Static text for an NSK_* code. */
 const char* nsk_strerror(int code);

@@ -1,12 +1,13 @@
 // libnsk batched form: many 3D instances of uneven mesh size and degree
 // advanced together.  Each instance is an ordinary context bound to a slice
 // of one packed state buffer and of one workspace.  Instances are grouped by
-// degree; per group and per stage one persistent lifting kernel and one
-// persistent right-hand-side kernel walk a list of (instance, element block)
-// items.  Two full Runge-Kutta steps (ten stages, every group) are captured
-// into one HIP graph that is replayed, so the whole batch advances with one
-// graph launch per two steps.  A built-in autotuner picks, per degree and
-// precision, the elements per workgroup and the persistent grid size.
+// degree; per group and per stage one lifting kernel and one right-hand-side
+// kernel walk a list of (instance, element block) items, one workgroup per
+// item or a persistent grid taking the list in rounds.  Two full Runge-Kutta
+// steps (ten stages, every group) are captured into one HIP graph that is
+// replayed, so the whole batch advances with one graph launch per two steps.
+// A built-in autotuner picks, per degree and precision, the elements per
+// workgroup and the grid size.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,7 +22,9 @@
 
 namespace {
 
-constexpr int kGridMults[4] = {1, 2, 4, 8};
+// persistent grid = CUs * m; m = 0: one workgroup per item (no persistence)
+constexpr int kGridMults[4] = {0, 2, 4, 8};
+constexpr int kBatchTuneSlots = 8 + kOrders;  // timings per group in nsk_batch_autotune
 
 struct BatchGroup {
   int np = 0;                 // N + 1
@@ -30,7 +33,7 @@ struct BatchGroup {
   size_t cap_items = 0;       // capacity in items (sum of element counts)
   int nitems = 0;             // items for the current variant
   int variant = 0;            // elements-per-workgroup variant
-  int gridmul = 2;            // persistent grid = CUs * gridmul
+  int gridmul = 0;            // grid = CUs * gridmul, 0: one workgroup per item
 };
 
 }  // namespace
@@ -125,13 +128,18 @@ int launch_group_e(nsk_batch* b, const BatchGroup& g, int parity, const StageArg
   const PhysArgs ph = phys_args(b->ctx[g.inst[0]]);
   const BatchInst* desc = reinterpret_cast<const BatchInst*>(b->work + b->off_desc) + parity * b->ninst;
   const BatchItem* items = reinterpret_cast<const BatchItem*>(b->work + g.off_items);
-  int grid = std::min(g.nitems, b->ncu * g.gridmul);
-  const int chunk = (g.nitems + grid - 1) / grid;
-  grid = (g.nitems + chunk - 1) / chunk;
-  hipLaunchKernelGGL((lift_kernel_batch<3, NP, EPB, R, GT>), dim3(grid), dim3(Tl::THREADS), 0, b->stream, desc, items,
-                     g.nitems, chunk, bas, ph);
-  hipLaunchKernelGGL((rhs_kernel_batch<3, NP, EPB, R, GT>), dim3(grid), dim3(Tl::THREADS), 0, b->stream, desc, items,
-                     g.nitems, chunk, bas, ph, st);
+  if (g.gridmul == 0) {
+    hipLaunchKernelGGL((lift_kernel_batch1<3, NP, EPB, R, GT>), dim3(g.nitems), dim3(Tl::THREADS), 0, b->stream, desc,
+                       items, bas, ph);
+    hipLaunchKernelGGL((rhs_kernel_batch1<3, NP, EPB, R, GT>), dim3(g.nitems), dim3(Tl::THREADS), 0, b->stream, desc,
+                       items, bas, ph, st);
+  } else {
+    const int grid = std::min(g.nitems, b->ncu * g.gridmul);
+    hipLaunchKernelGGL((lift_kernel_batch<3, NP, EPB, R, GT>), dim3(grid), dim3(Tl::THREADS), 0, b->stream, desc,
+                       items, g.nitems, bas, ph);
+    hipLaunchKernelGGL((rhs_kernel_batch<3, NP, EPB, R, GT>), dim3(grid), dim3(Tl::THREADS), 0, b->stream, desc,
+                       items, g.nitems, bas, ph, st);
+  }
   return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
 }
 
@@ -336,7 +344,31 @@ int nsk_batch_autotune(nsk_batch* b, int reps, double* ms_out) {
   int rc = NSK_OK;
   for (size_t gi = 0; gi < b->groups.size() && rc == NSK_OK; ++gi) {
     BatchGroup& g = b->groups[gi];
+    // element order of the member instances, with the current launch shape
     double best = INFINITY;
+    int bo = b->ctx[g.inst[0]]->order;
+    for (int o = 0; o < kOrders && rc == NSK_OK; ++o) {
+      for (int i : g.inst)
+        if ((rc = upload_order(b->ctx[i], o)) != NSK_OK) break;
+      if (rc || (rc = upload_tables(b)) != NSK_OK) break;
+      float ms = 0.f;
+      if ((rc = launch_group(b, g, 0, st)) != NSK_OK) break;
+      if (hipEventRecord(e0, b->stream) != hipSuccess) { rc = NSK_EHIP; break; }
+      for (int r = 0; r < reps && rc == NSK_OK; ++r) rc = launch_group(b, g, 0, st);
+      if (rc || hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        if (!rc) rc = NSK_EHIP;
+        break;
+      }
+      const double per = ms / reps;
+      if (ms_out) ms_out[gi * kBatchTuneSlots + 8 + o] = per;
+      if (per < best) { best = per; bo = o; }
+    }
+    for (int i : g.inst)
+      if (rc == NSK_OK) rc = upload_order(b->ctx[i], bo);
+    if (rc) break;
+    // elements per workgroup and grid
+    best = INFINITY;
     int bv = g.variant, bm = g.gridmul;
     for (int v = 0; v < kTileVariants && rc == NSK_OK; ++v) {
       g.variant = v;
@@ -354,7 +386,7 @@ int nsk_batch_autotune(nsk_batch* b, int reps, double* ms_out) {
           break;
         }
         const double per = ms / reps;
-        if (ms_out) ms_out[gi * 8 + v * 4 + mi] = per;
+        if (ms_out) ms_out[gi * kBatchTuneSlots + v * 4 + mi] = per;
         if (per < best) { best = per; bv = v; bm = kGridMults[mi]; }
       }
     }
@@ -367,13 +399,14 @@ int nsk_batch_autotune(nsk_batch* b, int reps, double* ms_out) {
   return rc ? rc : rc2;
 }
 
-int nsk_batch_groups(const nsk_batch* b, int* np_out, int* variant_out, int* gridmul_out, int max) {
+int nsk_batch_groups(const nsk_batch* b, int* np_out, int* variant_out, int* gridmul_out, int* order_out, int max) {
   if (!b) return NSK_EINVAL;
   const int n = (int)b->groups.size();
   for (int i = 0; i < n && i < max; ++i) {
     if (np_out) np_out[i] = b->groups[i].np - 1;
     if (variant_out) variant_out[i] = b->groups[i].variant;
     if (gridmul_out) gridmul_out[i] = b->groups[i].gridmul;
+    if (order_out) order_out[i] = b->ctx[b->groups[i].inst[0]]->order;
   }
   return n;
 }

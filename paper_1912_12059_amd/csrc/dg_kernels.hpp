@@ -227,7 +227,7 @@ __device__ __forceinline__ void conv_flux(int d, const R* u, R irho, R pa, R* F)
 // along each d-line, w* = (w_left + w_right) / 2 on the faces.
 // -------------------------------------------------------------------------
 template <int DIM, int NP, int EPB, typename R, typename GT>
-__device__ __forceinline__ void lift_block(int L, const double* __restrict__ U, GT* __restrict__ G,
+__device__ __forceinline__ void lift_block(int L, int tid, const double* __restrict__ U, GT* __restrict__ G,
                                            const BasisArgs& bas, const MeshArgs& msh, const PhysArgs& ph) {
   using Sh = Shape<DIM, NP>;
   constexpr int NN = Sh::NN, NF = Sh::NF, NL = Sh::NLIFT;
@@ -238,7 +238,6 @@ __device__ __forceinline__ void lift_block(int L, const double* __restrict__ U, 
   __shared__ R sLm[NP], sLp[NP], sIw[NP];
   __shared__ ElemInfo<DIM, EPB> info;
 
-  const int tid = threadIdx.x;
   const long long S = msh.S;
   if (tid < NP * NP) sD[tid / NP][tid % NP] = R(bas.Dhat[tid / NP][tid % NP]);
   if (tid < NP) { sLm[tid] = R(bas.Lm[tid]); sLp[tid] = R(bas.Lp[tid]); sIw[tid] = R(bas.invw[tid]); }
@@ -346,7 +345,7 @@ __device__ __forceinline__ void lift_block(int L, const double* __restrict__ U, 
 //   dU <- A dU + dt R,  U <- U + B dU.
 // -------------------------------------------------------------------------
 template <int DIM, int NP, int EPB, typename R, typename GT>
-__device__ __forceinline__ void rhs_block(int L, const double* __restrict__ U, const GT* __restrict__ G,
+__device__ __forceinline__ void rhs_block(int L, int tid, const double* __restrict__ U, const GT* __restrict__ G,
                                           double* __restrict__ Uout, double* __restrict__ dU, const BasisArgs& bas,
                                           const MeshArgs& msh, const PhysArgs& ph, const StageArgs& st) {
   using Sh = Shape<DIM, NP>;
@@ -363,7 +362,6 @@ __device__ __forceinline__ void rhs_block(int L, const double* __restrict__ U, c
   __shared__ R sLm[NP], sLp[NP], sIw[NP];
   __shared__ ElemInfo<DIM, EPB> info;
 
-  const int tid = threadIdx.x;
   const long long S = msh.S;
   if (tid < NP * NP) sD[tid / NP][tid % NP] = R(bas.Dhat[tid / NP][tid % NP]);
   if (tid < NP) { sLm[tid] = R(bas.Lm[tid]); sLp[tid] = R(bas.Lp[tid]); sIw[tid] = R(bas.invw[tid]); }
@@ -547,14 +545,15 @@ __device__ __forceinline__ void rhs_block(int L, const double* __restrict__ U, c
 template <int DIM, int NP, int EPB, typename R, typename GT>
 __global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
 lift_kernel(const double* __restrict__ U, GT* __restrict__ G, BasisArgs bas, MeshArgs msh, PhysArgs ph) {
-  lift_block<DIM, NP, EPB, R, GT>(remap_block(blockIdx.x, gridDim.x, msh.nxcd), U, G, bas, msh, ph);
+  lift_block<DIM, NP, EPB, R, GT>(remap_block(blockIdx.x, gridDim.x, msh.nxcd), threadIdx.x, U, G, bas, msh, ph);
 }
 
 template <int DIM, int NP, int EPB, typename R, typename GT>
 __global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
 rhs_kernel(const double* __restrict__ U, const GT* __restrict__ G, double* __restrict__ Uout,
            double* __restrict__ dU, BasisArgs bas, MeshArgs msh, PhysArgs ph, StageArgs st) {
-  rhs_block<DIM, NP, EPB, R, GT>(remap_block(blockIdx.x, gridDim.x, msh.nxcd), U, G, Uout, dU, bas, msh, ph, st);
+  rhs_block<DIM, NP, EPB, R, GT>(remap_block(blockIdx.x, gridDim.x, msh.nxcd), threadIdx.x, U, G, Uout, dU, bas, msh,
+                                 ph, st);
 }
 
 // -------------------------------------------------------------------------
@@ -571,35 +570,77 @@ struct BatchInst {
   MeshArgs msh;        // mesh of the instance (nxcd unused)
 };
 
+constexpr int kBatchXcds = 8;  // XCDs the batched kernels spread rounds over
+
 struct BatchItem {
   int inst;            // instance index
   int L;               // logical block of that instance
 };
 
+// Batched kernels: a group of instances of one degree shares a list of
+// (instance, element block) items.  The one-item form gives every item its
+// own workgroup; the persistent form runs a fixed grid that takes the list
+// in rounds of gridDim.x consecutive items.  In both, each XCD takes a
+// contiguous slice of the items in flight, so neighbouring elements meet in
+// the same L2.
 template <int DIM, int NP, int EPB, typename R, typename GT>
 __global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
-lift_kernel_batch(const BatchInst* __restrict__ inst, const BatchItem* __restrict__ items, int nitems, int chunk,
+lift_kernel_batch1(const BatchInst* __restrict__ inst, const BatchItem* __restrict__ items, BasisArgs bas,
+                   PhysArgs ph) {
+  const BatchItem w = items[remap_block(blockIdx.x, gridDim.x, kBatchXcds)];
+  const BatchInst& I = inst[w.inst];
+  lift_block<DIM, NP, EPB, R, GT>(w.L, threadIdx.x, I.U, reinterpret_cast<GT*>(I.G), bas, I.msh, ph);
+}
+
+template <int DIM, int NP, int EPB, typename R, typename GT>
+__global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
+rhs_kernel_batch1(const BatchInst* __restrict__ inst, const BatchItem* __restrict__ items, BasisArgs bas,
+                  PhysArgs ph, StageArgs st) {
+  const BatchItem w = items[remap_block(blockIdx.x, gridDim.x, kBatchXcds)];
+  const BatchInst& I = inst[w.inst];
+  rhs_block<DIM, NP, EPB, R, GT>(w.L, threadIdx.x, I.U, reinterpret_cast<const GT*>(I.G), I.Uout, I.dU, bas, I.msh,
+                                 ph, st);
+}
+
+// The thread index handed to the block functions is made opaque in every
+// round: otherwise the compiler hoists the per-thread basis and index work
+// out of the loop and holds it in registers across items, which lowers
+// occupancy.
+__device__ __forceinline__ int opaque_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+template <int DIM, int NP, int EPB, typename R, typename GT>
+__global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
+lift_kernel_batch(const BatchInst* __restrict__ inst, const BatchItem* __restrict__ items, int nitems,
                   BasisArgs bas, PhysArgs ph) {
-  const int first = blockIdx.x * chunk;
-  const int last = min(nitems, first + chunk);
-  for (int it = first; it < last; ++it) {
-    const BatchItem w = items[it];
-    const BatchInst& I = inst[w.inst];
-    lift_block<DIM, NP, EPB, R, GT>(w.L, I.U, reinterpret_cast<GT*>(I.G), bas, I.msh, ph);
+  const int slot = remap_block(blockIdx.x, gridDim.x, kBatchXcds);
+  for (int base = 0; base < nitems; base += gridDim.x) {
+    const int it = base + slot;
+    if (it < nitems) {
+      const BatchItem w = items[it];
+      const BatchInst& I = inst[w.inst];
+      lift_block<DIM, NP, EPB, R, GT>(w.L, opaque_tid(), I.U, reinterpret_cast<GT*>(I.G), bas, I.msh, ph);
+    }
     __syncthreads();  // LDS is reused by the next item
   }
 }
 
 template <int DIM, int NP, int EPB, typename R, typename GT>
 __global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
-rhs_kernel_batch(const BatchInst* __restrict__ inst, const BatchItem* __restrict__ items, int nitems, int chunk,
+rhs_kernel_batch(const BatchInst* __restrict__ inst, const BatchItem* __restrict__ items, int nitems,
                  BasisArgs bas, PhysArgs ph, StageArgs st) {
-  const int first = blockIdx.x * chunk;
-  const int last = min(nitems, first + chunk);
-  for (int it = first; it < last; ++it) {
-    const BatchItem w = items[it];
-    const BatchInst& I = inst[w.inst];
-    rhs_block<DIM, NP, EPB, R, GT>(w.L, I.U, reinterpret_cast<const GT*>(I.G), I.Uout, I.dU, bas, I.msh, ph, st);
+  const int slot = remap_block(blockIdx.x, gridDim.x, kBatchXcds);
+  for (int base = 0; base < nitems; base += gridDim.x) {
+    const int it = base + slot;
+    if (it < nitems) {
+      const BatchItem w = items[it];
+      const BatchInst& I = inst[w.inst];
+      rhs_block<DIM, NP, EPB, R, GT>(w.L, opaque_tid(), I.U, reinterpret_cast<const GT*>(I.G), I.Uout, I.dU, bas,
+                                     I.msh, ph, st);
+    }
     __syncthreads();
   }
 }
