@@ -67,7 +67,7 @@ typedef struct {
   double T;       /* temperature of the isotherm (reduced units), 0 < T < 1 */
   double eps;     /* viscosity eps = 1/Re                                   */
   double kappa;   /* eps^2 gamma, coefficient of the Laplacian of c         */
-  double alpha;   /* Korteweg relaxation parameter (> 0)                    */
+  double alpha;   /* relaxation parameter, > 6 (1 - T) (hyperbolicity)     */
   double beta;    /* parabolic relaxation parameter (> 0)                   */
   int flux;       /* 0 = Rusanov (the only flux built)                      */
   int diss_c;     /* 1 = Rusanov dissipation also on c, 0 = not on c        */
@@ -90,7 +90,7 @@ typedef struct {
  * memory is touched).  Rejects dim outside 1..3, N outside 1..6, nel < 1,
  * (NSK_EUNSUPPORTED for dim = 3 with N = 6, whose element tile exceeds 64 KB
  * of LDS),
- * non-increasing breakpoints, T outside (0,1), alpha <= 0, beta <= 0,
+ * non-increasing breakpoints, T outside (0,1), alpha <= 6 (1 - T), beta <= 0,
  * eps < 0, kappa < 0.  *out is set on success. */
 int nsk_create(const nsk_mesh* mesh, const nsk_params* params, nsk_ctx** out);
 

@@ -167,6 +167,9 @@ int check_params(const nsk_params* p) {
   if (!(p->alpha > 0.0) || !(p->beta > 0.0) || !(p->eps >= 0.0) || !(p->kappa >= 0.0)) return NSK_EINVAL;
   if (!std::isfinite(p->alpha) || !std::isfinite(p->beta) || !std::isfinite(p->eps) || !std::isfinite(p->kappa))
     return NSK_EINVAL;
+  // model II is hyperbolic only for alpha > -min W''(rho) = 6 (1 - T), the
+  // minimum of the reduced Van-der-Waals W'' being taken at rho = 1
+  if (!(p->alpha > 6.0 * (1.0 - p->T))) return NSK_EINVAL;
   if (p->flux != 0 || p->closure != 0) return NSK_EINVAL;
   if (p->precision != 0 && p->precision != 1) return NSK_EINVAL;
   if (p->diss_c != 0 && p->diss_c != 1) return NSK_EINVAL;
