@@ -106,6 +106,30 @@ int or_diagnostics(const or_prob* P, const double* U, double* out);
 /* Nodal coordinates (for tests): X[d][elem][node]. */
 int or_node_coords(const or_prob* P, double* X);
 
+/* ---------------- learned closure (no counterpart in the paper) ------------ */
+#define OR_MLP_IN 4
+#define OR_MLP_HIDDEN 64
+#define OR_MLP_OUT 2
+#define OR_MLP_NPARAM 8770
+double or_gelu(double z);
+double or_gelu_d(double z);
+long or_mlp_nparam(void);
+/* Y[n][2] = network(X[n][4]) with parameters w (layout in mlp.c). */
+void or_mlp_forward(const double* w, const double* X, long n, double* Y);
+/* Returns L = 1/(2n) sum (y - t)^2 and writes dL/dw into grad[8770]. */
+double or_mlp_loss_grad(const double* w, const double* X, const double* Yt, long n, double* grad);
+/* One Adam step (step number t >= 1) on np parameters. */
+void or_adam_step(double* w, double* m, double* v, const double* g, long np, double lr, double b1, double b2,
+                  double eps, int t);
+/* Features X[node][4] and unit gradient direction nvec[d][node] (either may
+ * be NULL); norm = (s0, k0, s1, k1, k2, k3, g0, out_m, out_c). */
+int or_closure_features(const or_prob* P, const double* U, const double* norm, double* X, double* nvec);
+/* Closure source in the layout of U (zero on rho). */
+int or_closure_source(const or_prob* P, const double* U, const double* w, const double* norm, double* Sc);
+/* Nudging step toward a reference state; records features and targets. */
+int or_closure_nudge(const or_prob* P, double* U, const double* Uref, double dt, double tau, double cmap,
+                     const double* norm, double* X, double* Y);
+
 #ifdef __cplusplus
 }
 #endif

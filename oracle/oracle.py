@@ -18,7 +18,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
-SOURCES = ["basis.c", "thermo.c", "lsrk.c", "dg_weak.c", "dg_strong.c", "mlp.c"]
+SOURCES = ["basis.c", "thermo.c", "lsrk.c", "dg_weak.c", "dg_strong.c", "mlp.c", "closure.c"]
 
 
 def build(force: bool = True) -> str:
@@ -97,15 +97,20 @@ def _declare(L):
     L.or_dt.restype = C.c_double
     L.or_diagnostics.argtypes = [C.POINTER(_Prob), _dp, _dp]
     L.or_node_coords.argtypes = [C.POINTER(_Prob), _dp]
-    if hasattr(L, "or_mlp_forward"):
-        _declare_mlp(L)
-
-
-def _declare_mlp(L):
-    L.or_mlp_forward.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp]
-    L.or_mlp_loss_grad.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp]
+    L.or_gelu.argtypes = [C.c_double]
+    L.or_gelu.restype = C.c_double
+    L.or_gelu_d.argtypes = [C.c_double]
+    L.or_gelu_d.restype = C.c_double
+    L.or_mlp_nparam.restype = C.c_long
+    L.or_mlp_forward.argtypes = [_dp, _dp, C.c_long, _dp]
+    L.or_mlp_loss_grad.argtypes = [_dp, _dp, _dp, C.c_long, _dp]
     L.or_mlp_loss_grad.restype = C.c_double
-    L.or_adam_step.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int]
+    L.or_adam_step.argtypes = [_dp, _dp, _dp, _dp, C.c_long, C.c_double, C.c_double, C.c_double, C.c_double,
+                               C.c_int]
+    L.or_closure_features.argtypes = [C.POINTER(_Prob), _dp, _dp, _dp, _dp]
+    L.or_closure_source.argtypes = [C.POINTER(_Prob), _dp, _dp, _dp, _dp]
+    L.or_closure_nudge.argtypes = [C.POINTER(_Prob), _dp, _dp, C.c_double, C.c_double, C.c_double, _dp, _dp,
+                                   _dp]
 
 
 def _ptr(a: np.ndarray):
@@ -332,3 +337,84 @@ def node_coords(P: Problem) -> np.ndarray:
     pc = P.c()
     lib().or_node_coords(C.byref(pc), _ptr(X))
     return X
+
+
+# --------------------------------------------------------------------------
+# learned closure: network, training step, features, nudging
+# --------------------------------------------------------------------------
+MLP_NPARAM = 8770
+CLOSURE_NORM_KEYS = ("s0", "k0", "s1", "k1", "k2", "k3", "g0", "out_m", "out_c")
+
+
+def gelu(z: float) -> float:
+    return lib().or_gelu(z)
+
+
+def gelu_d(z: float) -> float:
+    return lib().or_gelu_d(z)
+
+
+def mlp_forward(w, X) -> np.ndarray:
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 4)
+    Y = np.zeros((X.shape[0], 2))
+    lib().or_mlp_forward(_ptr(w), _ptr(X), X.shape[0], _ptr(Y))
+    return Y
+
+
+def mlp_loss_grad(w, X, Yt):
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 4)
+    Yt = np.ascontiguousarray(Yt, dtype=np.float64).reshape(-1, 2)
+    g = np.zeros(MLP_NPARAM)
+    loss = lib().or_mlp_loss_grad(_ptr(w), _ptr(X), _ptr(Yt), X.shape[0], _ptr(g))
+    return loss, g
+
+
+def adam_step(w, m, v, g, lr, b1, b2, eps, t):
+    """In place on w, m, v (float64 arrays)."""
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    lib().or_adam_step(_ptr(w), _ptr(m), _ptr(v), _ptr(g), w.size, lr, b1, b2, eps, t)
+
+
+def _norm(norm) -> np.ndarray:
+    if isinstance(norm, dict):
+        norm = [norm[k] for k in CLOSURE_NORM_KEYS]
+    return np.ascontiguousarray(norm, dtype=np.float64)
+
+
+def closure_features(P: Problem, U, norm):
+    U = _state(P, U)
+    S = P.nelem * P.nnode
+    X = np.zeros((S, 4))
+    nv = np.zeros((P.dim, S))
+    nm = _norm(norm)
+    pc = P.c()
+    if lib().or_closure_features(C.byref(pc), _ptr(U), _ptr(nm), _ptr(X), _ptr(nv)) != 0:
+        raise RuntimeError("or_closure_features failed")
+    return X, nv
+
+
+def closure_source(P: Problem, U, w, norm):
+    U = _state(P, U)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    Sc = np.zeros_like(U).reshape(P.shape())
+    nm = _norm(norm)
+    pc = P.c()
+    if lib().or_closure_source(C.byref(pc), _ptr(U), _ptr(w), _ptr(nm), _ptr(Sc)) != 0:
+        raise RuntimeError("or_closure_source failed")
+    return Sc
+
+
+def closure_nudge(P: Problem, U, Uref, dt, tau, cmap, norm):
+    """Returns (U_new, X, Y); U is not modified."""
+    Un = _state(P, U).copy()
+    Ur = _state(P, Uref)
+    S = P.nelem * P.nnode
+    X = np.zeros((S, 4))
+    Y = np.zeros((S, 2))
+    nm = _norm(norm)
+    pc = P.c()
+    if lib().or_closure_nudge(C.byref(pc), _ptr(Un), _ptr(Ur), dt, tau, cmap, _ptr(nm), _ptr(X), _ptr(Y)) != 0:
+        raise RuntimeError("or_closure_nudge failed")
+    return Un.reshape(P.shape()), X, Y
