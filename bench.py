@@ -168,7 +168,7 @@ def run_form(nsk, m, U0, w, precision: int, steps: int, warmup: int, tile: str):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
-    ms_lift, ms_rhs, nst = nsk.nsk_timing_read(s.ctx)
+    ms_lift, ms_rhs, nst, _ = nsk.nsk_timing_read(s.ctx)
     nsk.nsk_timing_enable(s.ctx, 0)
     diag = s.diagnostics()
     final = s.get_state()

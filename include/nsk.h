@@ -40,6 +40,7 @@
 #ifndef NSK_H
 #define NSK_H
 #include <stddef.h>
+#include <stdint.h>
 
 #ifdef __cplusplus
 extern "C" {
@@ -72,7 +73,7 @@ typedef struct {
   int flux;       /* 0 = Rusanov (the only flux built)                      */
   int diss_c;     /* 1 = Rusanov dissipation also on c, 0 = not on c        */
   int precision;  /* 0 = FP64 throughout; 1 = mixed (FP32 volume/surface)   */
-  int closure;    /* reserved, must be 0                                    */
+  int closure;    /* 1: add the learned closure source (nsk_closure_set)   */
 } nsk_params;
 
 typedef struct {
@@ -165,14 +166,96 @@ int nsk_set_params(nsk_ctx* ctx, const nsk_params* params);
 
 /* Kernel timing with HIP events on the bound stream (measurement only).
  * nsk_timing_enable(ctx, 1) makes every stage enqueued by nsk_rk_step record
- * events before the lifting kernel, between the two kernels and after the
- * right-hand-side/update kernel (at most 4096 stages until the next read).
- * nsk_timing_read waits for the stream and returns out[0] = summed ms of the
- * lifting kernel, out[1] = summed ms of the right-hand-side/update kernel,
- * out[2] = number of stages timed, then clears the record.
+ * events before the lifting kernel, after it, after the closure kernel (if
+ * any) and after the right-hand-side/update kernel (at most 4096 stages
+ * until the next read).  nsk_timing_read waits for the stream and returns
+ * out[0] = summed ms of the lifting kernel, out[1] = summed ms of the
+ * right-hand-side/update kernel, out[2] = number of stages timed, out[3] =
+ * summed ms of the closure kernel, then clears the record.
  * nsk_timing_enable(ctx, 0) stops recording and releases the events. */
 int nsk_timing_enable(nsk_ctx* ctx, int enable);
-int nsk_timing_read(nsk_ctx* ctx, double out[3]);
+int nsk_timing_read(nsk_ctx* ctx, double out[4]);
+
+/* ------------------------------------------------------------------------
+ * Learned closure (no counterpart in the paper; the paper's model II is the
+ * closure-free method).  A per-node network
+ *   x -> 64 -> 64 -> 64 -> y,  GELU (erf form) on the hidden layers,
+ * with BF16 parameters and FP32 accumulation, adds to the right-hand side
+ *   momentum: out_m y_0 n,   c: out_c y_1,   n = g / sqrt(|g|^2 + g0^2),
+ * from element-local features of the state (g = grad rho and lap = the
+ * Laplacian of rho, both from the collocation derivative applied inside the
+ * element):
+ *   x = ((rho - s0) k0, (c - s1) k1, |g| k2, lap k3).
+ * Parameters are NSK_MLP_NPARAM BF16 values (IEEE binary32 truncated to the
+ * upper 16 bits, rounded to nearest even), weights row-major [out][in]:
+ *   W1[64][4] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[2][64] b4[2].
+ * The closure is trained on nudged pairs of runs (nsk_closure_nudge) with
+ * the training kernels below.
+ * ------------------------------------------------------------------------ */
+#define NSK_MLP_NPARAM 8770
+
+typedef struct {
+  float s0, k0;     /* rho feature: (rho - s0) k0                            */
+  float s1, k1;     /* c feature: (c - s1) k1                                */
+  float k2, k3;     /* |grad rho| k2, Laplacian of rho times k3              */
+  float g0;         /* > 0: regularisation of the unit direction n           */
+  float out_m;      /* scale of the momentum output                          */
+  float out_c;      /* scale of the c output                                 */
+} nsk_closure_norm;
+
+/* Sets the network of a context created with params.closure = 1.  d_w_bf16
+ * is a device pointer to NSK_MLP_NPARAM BF16 values that the caller keeps
+ * valid and unchanged while the context steps (it is read, not copied).
+ * Each stage then runs one closure kernel (features + network, FP32 result
+ * in the workspace) before the right-hand-side kernel, which adds the source
+ * in FP64.  NSK_EINVAL if the context has closure = 0, an argument is NULL,
+ * a scale is not finite or g0 <= 0.  nsk_rhs, nsk_rk_step and nsk_autotune
+ * of a closure context return NSK_EINVAL until a network is set.  Host only. */
+int nsk_closure_set(nsk_ctx* ctx, const uint16_t* d_w_bf16, const nsk_closure_norm* norm);
+
+/* One nudging step on the bound state of any context (training pairs):
+ * with the reference state d_Uref (layout of the state, device) mapped into
+ * this model's frame, U* = (rho_r, m_r, rho_r + cmap (c_r - rho_r)), and the
+ * features x and direction n of the current state U under *norm (its
+ * out_m, out_c are not used),
+ *   d_X[node][4] = x(U),  d_Y[node][2] = ((m* - m).n / tau, (c* - c) / tau)
+ * (either may be NULL; node = elem * (N+1)^dim + local node), then
+ *   m += (dt / tau)(m* - m),  c += (dt / tau)(c* - c);  rho is unchanged.
+ * tau > 0, dt >= 0, norm->g0 > 0.  Asynchronous on the bound stream. */
+int nsk_closure_nudge(nsk_ctx* ctx, const nsk_closure_norm* norm, const double* d_Uref, double dt, double tau,
+                      double cmap, float* d_X, float* d_Y);
+
+/* Network outputs y (unscaled) of n feature vectors: d_X[n][4] (16-byte
+ * aligned) -> d_Y[n][2], with the inference kernel of the closure (BF16
+ * MFMA).  Device pointers; asynchronous on hip_stream. */
+int nsk_mlp_forward(const uint16_t* d_w_bf16, const float* d_X, long long n, float* d_Y, void* hip_stream);
+
+/* Bytes of device workspace for nsk_mlp_loss_grad with n <= batch samples
+ * and for nsk_mlp_moments. */
+size_t nsk_mlp_workspace_bytes(long long batch);
+
+/* Loss L = 1/(2n) sum_s sum_o (y_so - q_o t_so)^2 of n samples (targets t
+ * scaled by q_0 = tscale0, q_1 = tscale1) and its gradient
+ * with respect to the NSK_MLP_NPARAM parameters, in FP32 with the network's
+ * rounding points (BF16 parameters, BF16 activations of the first two hidden
+ * layers; the backward pass takes that rounding as the identity).  Sample s
+ * is row d_idx[s] of d_X[.][4] and d_Y[.][2] (d_idx may be NULL: row s).
+ * d_grad receives NSK_MLP_NPARAM floats, d_loss (may be NULL) one float.  The
+ * per-workgroup partial sums are added in a fixed order (deterministic).
+ * d_ws: nsk_mlp_workspace_bytes(n) bytes.  Asynchronous on hip_stream. */
+int nsk_mlp_loss_grad(const uint16_t* d_w_bf16, const float* d_X, const float* d_Y, const int* d_idx, long long n,
+                      float tscale0, float tscale1, void* d_ws, float* d_grad, float* d_loss, void* hip_stream);
+
+/* Adam step t (>= 1) of Kingma and Ba on the FP32 master parameters
+ * d_master, with first and second moments d_m, d_v (zero before step 1);
+ * d_w_bf16 receives the master values rounded to BF16.  Asynchronous. */
+int nsk_mlp_adam(float* d_master, uint16_t* d_w_bf16, float* d_m, float* d_v, const float* d_grad, int t,
+                 double lr, double beta1, double beta2, double eps, void* hip_stream);
+
+/* Column means and standard deviations of d_Y[n][ncol] (ncol <= 4):
+ * d_out[0..ncol-1] = means, d_out[ncol..2 ncol-1] = standard deviations
+ * (FP64, device).  d_ws: nsk_mlp_workspace_bytes(1) bytes.  Asynchronous. */
+int nsk_mlp_moments(const float* d_Y, long long n, int ncol, void* d_ws, double* d_out, void* hip_stream);
 
 /* ------------------------------------------------------------------------
  * Batched form: many 3D instances of uneven mesh size and degree advanced
@@ -187,8 +270,9 @@ int nsk_timing_read(nsk_ctx* ctx, double out[3]);
  * ------------------------------------------------------------------------ */
 typedef struct nsk_batch nsk_batch;
 
-/* meshes[0..ninst-1] must all be 3D (NSK_EUNSUPPORTED otherwise); the
- * validation rules of nsk_create apply per instance.  Host only. */
+/* meshes[0..ninst-1] must all be 3D and params->closure 0 (NSK_EUNSUPPORTED
+ * otherwise); the validation rules of nsk_create apply per instance.  Host
+ * only. */
 int nsk_batch_create(const nsk_mesh* meshes, int ninst, const nsk_params* params, nsk_batch** out);
 
 /* Frees the batch and its instance contexts (waits for the bound stream). */

@@ -7,9 +7,10 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 REPO = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libnsk.so")
-SOURCES = [os.path.join(HERE, "csrc", "nsk.hip"), os.path.join(HERE, "csrc", "batch.hip")]
+SOURCES = [os.path.join(HERE, "csrc", n) for n in ("nsk.hip", "batch.hip", "closure.hip")]
 DEPENDS = SOURCES + [
     os.path.join(HERE, "csrc", "dg_kernels.hpp"),
+    os.path.join(HERE, "csrc", "closure.hpp"),
     os.path.join(HERE, "csrc", "host_common.hpp"),
     os.path.join(REPO, "include", "nsk.h"),
 ]

@@ -1,0 +1,359 @@
+// Device code of the learned closure: a per-node network
+//   x (4 features) -> 64 -> 64 -> 64 -> y (2), GELU (erf form),
+// with BF16 parameters and FP32 accumulation, whose outputs add
+//   S_m = out_m y_0 n,  S_c = out_c y_1,   n = grad rho / sqrt(|grad rho|^2 + g0^2)
+// to the momentum and c equations of relaxation model II.  The paper defines
+// no closure; it is trained on nudged pairs of runs at a moderate and a large
+// relaxation parameter.
+//
+// Features are element-local (no lifting): with the collocation derivative D
+// of the Gauss-Legendre basis applied along each direction inside an element,
+//   g_d = (2/h_d) D rho,   lap = sum_d (2/h_d)^2 D (D rho),
+//   x = ((rho - s0) k0, (c - s1) k1, |g| k2, lap k3).
+//
+// Inference (closure_kernel) on gfx950: a workgroup of 256 threads takes
+// whole elements (up to 256 nodes).  Features are formed per node from the
+// densities staged in LDS; the network runs per wavefront on 64 nodes with
+// the nodes as the columns of v_mfma_f32_32x32x8bf16: layer 1 (4 -> 64) in
+// FP32 directly in the B-operand layout, layers 2 and 3 as BF16 MFMA (the
+// accumulator layout of one layer is the B-operand layout of the next), and
+// layer 4 as an FP32 dot product finished across the two half-waves.
+//
+// Training runs in FP32 vector arithmetic with the same rounding points
+// (BF16 parameters; BF16 activations where inference feeds an MFMA), so the
+// trained network is the one inference evaluates up to summation order.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dg_kernels.hpp"
+
+namespace nsk {
+
+constexpr int kMlpIn = 4, kMlpHid = 64, kMlpOut = 2;
+// parameter blocks, row-major [out][in]
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kMlpHid * kMlpIn;
+constexpr int kOffW2 = kOffB1 + kMlpHid;
+constexpr int kOffB2 = kOffW2 + kMlpHid * kMlpHid;
+constexpr int kOffW3 = kOffB2 + kMlpHid;
+constexpr int kOffB3 = kOffW3 + kMlpHid * kMlpHid;
+constexpr int kOffW4 = kOffB3 + kMlpHid;
+constexpr int kOffB4 = kOffW4 + kMlpOut * kMlpHid;
+constexpr int kMlpParams = kOffB4 + kMlpOut;  // 8770
+
+constexpr int kClosureThreads = 256;
+// the small parameter blocks kept in LDS as FP32 by the inference kernels
+constexpr int kCW1 = 0, kCB1 = kCW1 + kMlpHid * kMlpIn, kCB2 = kCB1 + kMlpHid, kCB3 = kCB2 + kMlpHid,
+              kCW4 = kCB3 + kMlpHid, kCB4 = kCW4 + kMlpOut * kMlpHid, kCSmall = kCB4 + kMlpOut;
+
+struct ClosureArgs {
+  const uint16_t* w;       // BF16 parameters
+  double D[kMaxNP][kMaxNP];  // collocation derivative D_ij = l_j'(xi_i)
+  float s0, k0, s1, k1, k2, k3, g0, out_m, out_c;
+};
+
+// ---- BF16 -----------------------------------------------------------------
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_round(float f) { return bf16_to_f32(f32_to_bf16(f)); }
+
+// ---- GELU (erf form) --------------------------------------------------------
+// erf from Abramowitz & Stegun formula 7.1.26 (absolute error <= 1.5e-7),
+// far below the BF16 rounding of the activations.
+__device__ __forceinline__ float erf_as(float x) {
+  const float a = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * a);
+  const float poly =
+      t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+  const float e = 1.0f - poly * __expf(-a * a);
+  return copysignf(e, x);
+}
+
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float gelu_df(float z) {
+  const float Phi = 0.5f * (1.0f + erf_as(z * 0.70710678118654752f));
+  return Phi + z * 0.39894228040143268f * __expf(-0.5f * z * z);
+}
+
+// ---- element-local features ---------------------------------------------------
+template <int DIM, int NP>
+struct ClosureShape {
+  static constexpr int NN = ipow<NP, DIM>::v;
+  static constexpr int EPB = (kClosureThreads / NN) > 0 ? kClosureThreads / NN : 1;
+  static constexpr int SLOTS = EPB * NN;
+};
+
+__device__ __forceinline__ int elem_index_dir(const MeshArgs& m, long long e, int d) {
+  if (d == 0) return int(e % m.nel[0]);
+  if (d == 1) return int((e / m.nel[0]) % m.nel[1]);
+  return int(e / ((long long)m.nel[0] * m.nel[1]));
+}
+
+// Per node thread t < SLOTS: gradient, unit direction and features of the
+// node.  sRho and sDer are LDS scratch of the workgroup; every thread of the
+// workgroup must call (it synchronises).
+template <int DIM, int NP>
+__device__ __forceinline__ void closure_features(int t, long long e, bool active, double rho, double c,
+                                                 const MeshArgs& msh, const ClosureArgs& ca,
+                                                 double* sRho, double (*sDer)[ClosureShape<DIM, NP>::SLOTS],
+                                                 float x[4], double nvec[DIM]) {
+  constexpr int NN = ClosureShape<DIM, NP>::NN;
+  const int el = t / NN, n = t - (t / NN) * NN;
+  if (t < ClosureShape<DIM, NP>::SLOTS) sRho[t] = active ? rho : 0.0;
+  __syncthreads();
+  double g[DIM], h2[DIM];
+  double gg = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    g[d] = 0.0;
+    h2[d] = 0.0;
+    if (active) {
+      const int sd = dstride<NP>(d);
+      const int i = (n / sd) % NP;
+      const int base = el * NN + n - i * sd;
+      h2[d] = msh.h2[d][elem_index_dir(msh, e, d)];
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < NP; ++j) s += ca.D[i][j] * sRho[base + j * sd];
+      g[d] = h2[d] * s;
+      sDer[d][t] = g[d];
+      gg += g[d] * g[d];
+    }
+  }
+  __syncthreads();
+  double lap = 0.0;
+  if (active) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int sd = dstride<NP>(d);
+      const int i = (n / sd) % NP;
+      const int base = el * NN + n - i * sd;
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < NP; ++l) s += ca.D[i][l] * sDer[d][base + l * sd];
+      lap += h2[d] * s;
+    }
+  }
+  const double den = sqrt(gg + double(ca.g0) * double(ca.g0));
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) nvec[d] = active ? g[d] / den : 0.0;
+  x[0] = active ? float((rho - double(ca.s0)) * double(ca.k0)) : 0.f;
+  x[1] = active ? float((c - double(ca.s1)) * double(ca.k1)) : 0.f;
+  x[2] = active ? float(sqrt(gg) * double(ca.k2)) : 0.f;
+  x[3] = active ? float(lap * double(ca.k3)) : 0.f;
+}
+
+// ---- network on one wavefront: 64 nodes, features from LDS ------------------
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ short bf16_bits(float f) { return short(f32_to_bf16(f)); }
+
+// Row of output unit of accumulator register r in lane l of a 32x32 block.
+__device__ __forceinline__ int mfma_row(int r, int half) { return (r >> 2) * 8 + half * 4 + (r & 3); }
+
+// sX: features of the workgroup's slots; sW: W2 and W3 as BF16, rows padded
+// to kWPad; slot0: first slot of this wave.  Returns y for slot slot0 + lane.
+constexpr int kWPad = kMlpHid + 4;
+
+__device__ __forceinline__ void mlp_wave(const float4* sX, const uint16_t* sW, const float* sP, int slot0, float y[2]) {
+  const int lane = threadIdx.x & 63;
+  const int half = lane >> 5, col = lane & 31;
+  // layer 1 in the B-operand layout: lane holds units 8s + 4 half + q of
+  // node col of column block jb
+  bf16x4 b1[2][8];
+#pragma unroll
+  for (int jb = 0; jb < 2; ++jb) {
+    const float4 x = sX[slot0 + jb * 32 + col];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int u = 8 * s + 4 * half + q;
+        const float* w1 = sP + kCW1 + u * kMlpIn;
+        const float z = sP[kCB1 + u] + w1[0] * x.x + w1[1] * x.y + w1[2] * x.z + w1[3] * x.w;
+        b1[jb][s][q] = bf16_bits(gelu_f(z));
+      }
+    }
+  }
+  // layers 2 and 3
+  f32x16 acc[2][2];
+  bf16x4 bnext[2][8];
+  const uint16_t* W = sW;
+#pragma unroll
+  for (int layer = 0; layer < 2; ++layer) {
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[ib][jb][r] = 0.f;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib) {
+        const bf16x4 a = *reinterpret_cast<const bf16x4*>(W + (ib * 32 + col) * kWPad + 8 * s + 4 * half);
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) {
+          const bf16x4 b = layer == 0 ? b1[jb][s] : bnext[jb][s];
+          acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[ib][jb], 0, 0, 0);
+        }
+      }
+    }
+    const float* bias = sP + (layer == 0 ? kCB2 : kCB3);
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float bv = bias[ib * 32 + mfma_row(r, half)];
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) acc[ib][jb][r] = gelu_f(acc[ib][jb][r] + bv);
+      }
+    if (layer == 0) {
+      // accumulator rows 8(r/4) + 4 half + r%4 of block ib are exactly the
+      // units of k-step 4 ib + r/4 of the next layer's B operand
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bnext[jb][4 * ib + s][q] = bf16_bits(acc[ib][jb][4 * s + q]);
+      W = sW + kMlpHid * kWPad;
+    }
+  }
+  // layer 4: FP32 dot over this lane's 32 units, then across the half-waves
+  float part[2][2];
+#pragma unroll
+  for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+      float s = 0.f;
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) s += sP[kCW4 + o * kMlpHid + ib * 32 + mfma_row(r, half)] * acc[ib][jb][r];
+      part[jb][o] = s;
+    }
+#pragma unroll
+  for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+    for (int o = 0; o < 2; ++o) part[jb][o] += __shfl_xor(part[jb][o], 32, 64);
+  // lane = half * 32 + col takes node slot0 + lane, i.e. column block half
+  y[0] = sP[kCB4 + 0] + (half ? part[1][0] : part[0][0]);
+  y[1] = sP[kCB4 + 1] + (half ? part[1][1] : part[0][1]);
+}
+
+// Stage the parameters the network reads from LDS: W2, W3 as BF16 with
+// padded rows, and W1, b1, b2, b3, W4, b4 as FP32 in the compact block.
+__device__ __forceinline__ void mlp_stage_params(const uint16_t* __restrict__ w, uint16_t* sW, float* sP) {
+  for (int k = threadIdx.x; k < 2 * kMlpHid * kMlpHid; k += blockDim.x) {
+    const int l = k / (kMlpHid * kMlpHid), rem = k - l * kMlpHid * kMlpHid;
+    const int r = rem / kMlpHid, cc = rem - r * kMlpHid;
+    sW[l * kMlpHid * kWPad + r * kWPad + cc] = w[(l ? kOffW3 : kOffW2) + rem];
+  }
+  for (int k = threadIdx.x; k < kCSmall; k += blockDim.x) {
+    int src;
+    if (k < kCB1) src = kOffW1 + k;
+    else if (k < kCB2) src = kOffB1 + (k - kCB1);
+    else if (k < kCB3) src = kOffB2 + (k - kCB2);
+    else if (k < kCW4) src = kOffB3 + (k - kCB3);
+    else if (k < kCB4) src = kOffW4 + (k - kCW4);
+    else src = kOffB4 + (k - kCB4);
+    sP[k] = bf16_to_f32(w[src]);
+  }
+}
+
+// ---- inference kernels -----------------------------------------------------------
+// Closure source of every node of the mesh: Sc[d] = out_m y0 n_d (d < DIM),
+// Sc[DIM] = out_c y1, FP32, layout [comp][elem][node].
+template <int DIM, int NP>
+__global__ void __launch_bounds__(kClosureThreads)
+closure_kernel(const double* __restrict__ U, float* __restrict__ Sc, MeshArgs msh, ClosureArgs ca) {
+  using CS = ClosureShape<DIM, NP>;
+  constexpr int NN = CS::NN, SLOTS = CS::SLOTS;
+  __shared__ double sRho[SLOTS];
+  __shared__ double sDer[DIM][SLOTS];
+  __shared__ float4 sX[kClosureThreads];
+  __shared__ float sN[DIM][kClosureThreads];
+  __shared__ __attribute__((aligned(16))) uint16_t sW[2 * kMlpHid * kWPad];
+  __shared__ float sP[kCSmall];
+  mlp_stage_params(ca.w, sW, sP);
+  const int t = threadIdx.x;
+  const long long S = msh.S;
+  const long long e = (long long)blockIdx.x * CS::EPB + t / NN;
+  const bool active = t < SLOTS && e < msh.E;
+  const long long o = active ? e * NN + (t - (t / NN) * NN) : 0;
+  const double rho = active ? U[o] : 0.0;
+  const double c = active ? U[(DIM + 1) * S + o] : 0.0;
+  float x[4];
+  double nv[DIM];
+  closure_features<DIM, NP>(t, e, active, rho, c, msh, ca, sRho, sDer, x, nv);
+  sX[t] = make_float4(x[0], x[1], x[2], x[3]);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) sN[d][t] = float(nv[d]);
+  __syncthreads();
+  // every wave runs the network on its 64 slots (inactive slots compute on
+  // zero features and are not written)
+  float y[2];
+  mlp_wave(sX, sW, sP, (t >> 6) << 6, y);
+  if (active) {
+    const float sm = ca.out_m * y[0];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) Sc[d * S + o] = sm * sN[d][t];
+    Sc[DIM * S + o] = ca.out_c * y[1];
+  }
+}
+
+// ---- nudging step: training pairs -------------------------------------------------
+// U* = (rho_r, m_r, rho_r + cmap (c_r - rho_r)); records X = features(U) and
+// Y = ((m* - m).n / tau, (c* - c) / tau); then m, c += (dt/tau)(U* - U).
+template <int DIM, int NP>
+__global__ void __launch_bounds__(kClosureThreads)
+nudge_kernel(double* __restrict__ U, const double* __restrict__ Ur, MeshArgs msh, ClosureArgs ca, double relax,
+             double inv_tau, double cmap, float* __restrict__ X, float* __restrict__ Y) {
+  using CS = ClosureShape<DIM, NP>;
+  constexpr int NN = CS::NN, SLOTS = CS::SLOTS;
+  __shared__ double sRho[SLOTS];
+  __shared__ double sDer[DIM][SLOTS];
+  const int t = threadIdx.x;
+  const long long S = msh.S;
+  const long long e = (long long)blockIdx.x * CS::EPB + t / NN;
+  const bool active = t < SLOTS && e < msh.E;
+  const long long o = active ? e * NN + (t - (t / NN) * NN) : 0;
+  const double rho = active ? U[o] : 0.0;
+  const double c = active ? U[(DIM + 1) * S + o] : 0.0;
+  float x[4];
+  double nv[DIM];
+  closure_features<DIM, NP>(t, e, active, rho, c, msh, ca, sRho, sDer, x, nv);
+  if (!active) return;
+  const double rr = Ur[o];
+  const double cstar = rr + cmap * (Ur[(DIM + 1) * S + o] - rr);
+  double dmn = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const double m = U[(1 + d) * S + o], dm = Ur[(1 + d) * S + o] - m;
+    dmn += dm * nv[d];
+    U[(1 + d) * S + o] = m + relax * dm;
+  }
+  const double dc = cstar - c;
+  U[(DIM + 1) * S + o] = c + relax * dc;
+  if (X) reinterpret_cast<float4*>(X)[o] = make_float4(x[0], x[1], x[2], x[3]);
+  if (Y) {
+    Y[2 * o] = float(dmn * inv_tau);
+    Y[2 * o + 1] = float(dc * inv_tau);
+  }
+}
+
+}  // namespace nsk

@@ -98,6 +98,7 @@ struct PhysArgs {
 struct StageArgs {
   double A, B, dt;   // low-storage coefficients of the stage and step size
   int mode;          // 0: write R; 1: Runge-Kutta stage update
+  const float* closure = nullptr;  // learned closure source [dim+1][elem][node], or none
 };
 
 // -------------------------------------------------------------------------
@@ -525,6 +526,10 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
 #pragma unroll
     for (int d = 0; d < DIM; ++d) Rv[1 + d] += ph.alpha * rho64 * double(g[NT + d]);
     Rv[DIM + 1] += ph.ab * (rho64 - c64);
+    if (st.closure) {
+#pragma unroll
+      for (int d = 0; d <= DIM; ++d) Rv[1 + d] += double(st.closure[d * S + o]);
+    }
     if (st.mode == 0) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) Uout[v * S + o] = Rv[v];

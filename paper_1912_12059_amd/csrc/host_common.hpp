@@ -142,6 +142,7 @@ struct nsk_ctx {
   double rho_lo64 = 0.0, rho_hi64 = 0.0;
   // workspace layout (byte offsets)
   size_t off_U2 = 0, off_G = 0, off_h2[3] = {0, 0, 0}, off_wq = 0, off_order = 0, off_part = 0, off_out = 0;
+  size_t off_cl = 0;  // closure source [dim+1][elem][node], FP32 (closure contexts only)
   size_t ws_bytes = 0;
   int diag_blocks = 0;
   int tile = 0;      // elements-per-workgroup variant
@@ -154,8 +155,11 @@ struct nsk_ctx {
   char* work = nullptr;
   hipStream_t stream = nullptr;
   int cur = 0;  // 0: state in U, 1: state in the workspace copy
+  // learned closure: caller-owned BF16 parameters and the feature/output scaling
+  const uint16_t* cl_w = nullptr;
+  float cl_norm[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   // optional kernel timing
-  std::vector<hipEvent_t> events;  // 3 per timed stage
+  std::vector<hipEvent_t> events;  // 4 per timed stage
   int timed = 0;                   // stages recorded since the last read
 };
 
@@ -170,7 +174,7 @@ int check_params(const nsk_params* p) {
   // model II is hyperbolic only for alpha > -min W''(rho) = 6 (1 - T), the
   // minimum of the reduced Van-der-Waals W'' being taken at rho = 1
   if (!(p->alpha > 6.0 * (1.0 - p->T))) return NSK_EINVAL;
-  if (p->flux != 0 || p->closure != 0) return NSK_EINVAL;
+  if (p->flux != 0 || (p->closure != 0 && p->closure != 1)) return NSK_EINVAL;
   if (p->precision != 0 && p->precision != 1) return NSK_EINVAL;
   if (p->diss_c != 0 && p->diss_c != 1) return NSK_EINVAL;
   return NSK_OK;

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/nsk.h"
+#include "closure.hpp"
 #include "dg_kernels.hpp"
 #include "host_common.hpp"
 
@@ -26,8 +27,20 @@ namespace {
 // ---------------------------------------------------------------------------
 // events of the next timed stage, or nullptr when timing is off or full
 hipEvent_t* stage_events(nsk_ctx* c, const StageArgs& st) {
-  if (st.mode != 1 || c->events.empty() || 3 * (size_t)(c->timed + 1) > c->events.size()) return nullptr;
-  return &c->events[3 * (size_t)c->timed++];
+  if (st.mode != 1 || c->events.empty() || 4 * (size_t)(c->timed + 1) > c->events.size()) return nullptr;
+  return &c->events[4 * (size_t)c->timed++];
+}
+
+ClosureArgs closure_args_of(const nsk_ctx* c) {
+  ClosureArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.w = c->cl_w;
+  for (int i = 0; i < c->np; ++i)
+    for (int j = 0; j < c->np; ++j) a.D[i][j] = c->basis.D[i][j];
+  const float* q = c->cl_norm;
+  a.s0 = q[0]; a.k0 = q[1]; a.s1 = q[2]; a.k1 = q[3]; a.k2 = q[4]; a.k3 = q[5]; a.g0 = q[6];
+  a.out_m = q[7]; a.out_c = q[8];
+  return a;
 }
 
 template <int DIM, int NP, int EPB, typename R, typename GT>
@@ -43,9 +56,19 @@ int launch_stage_e(nsk_ctx* c, const double* Uin, double* Uout, double* dU, cons
   hipLaunchKernelGGL((lift_kernel<DIM, NP, EPB, R, GT>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream, Uin, G, b, m,
                      p);
   if (ev) (void)hipEventRecord(ev[1], c->stream);
-  hipLaunchKernelGGL((rhs_kernel<DIM, NP, EPB, R, GT>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream, Uin, G, Uout,
-                     dU, b, m, p, st);
+  StageArgs sta = st;
+  if (c->par.closure == 1) {
+    using CS = ClosureShape<DIM, NP>;
+    float* Sc = reinterpret_cast<float*>(c->work + c->off_cl);
+    const unsigned cblocks = (unsigned)((c->E + CS::EPB - 1) / CS::EPB);
+    hipLaunchKernelGGL((closure_kernel<DIM, NP>), dim3(cblocks), dim3(kClosureThreads), 0, c->stream, Uin, Sc,
+                       mesh_args(c), closure_args_of(c));
+    sta.closure = Sc;
+  }
   if (ev) (void)hipEventRecord(ev[2], c->stream);
+  hipLaunchKernelGGL((rhs_kernel<DIM, NP, EPB, R, GT>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream, Uin, G, Uout,
+                     dU, b, m, p, sta);
+  if (ev) (void)hipEventRecord(ev[3], c->stream);
   return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
 }
 
@@ -215,6 +238,10 @@ int nsk_create(const nsk_mesh* mesh, const nsk_params* params, nsk_ctx** out) {
   off = align256(off + sizeof(double) * kDiagSlots * (size_t)c->diag_blocks);
   c->off_out = off;
   off = align256(off + sizeof(double) * 16);
+  if (c->par.closure == 1) {
+    c->off_cl = off;
+    off = align256(off + sizeof(float) * (size_t)(c->dim + 1) * c->S);
+  }
   c->ws_bytes = off;
   // default launch shape: tiled work order in 3D, natural order otherwise
   c->order = c->dim == 3 ? 4 : 0;
@@ -236,7 +263,7 @@ int nsk_timing_enable(nsk_ctx* c, int enable) {
   c->events.clear();
   c->timed = 0;
   if (!enable) return NSK_OK;
-  const int n = 3 * 4096;
+  const int n = 4 * 4096;
   c->events.resize(n);
   for (int i = 0; i < n; ++i)
     if (hipEventCreate(&c->events[i]) != hipSuccess) {
@@ -247,17 +274,19 @@ int nsk_timing_enable(nsk_ctx* c, int enable) {
   return NSK_OK;
 }
 
-int nsk_timing_read(nsk_ctx* c, double out[3]) {
+int nsk_timing_read(nsk_ctx* c, double out[4]) {
   if (!c || !out) return NSK_EINVAL;
-  out[0] = out[1] = out[2] = 0.0;
+  out[0] = out[1] = out[2] = out[3] = 0.0;
   if (c->timed == 0) return NSK_OK;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return NSK_EHIP;
   for (int k = 0; k < c->timed; ++k) {
-    float a = 0.f, b = 0.f;
-    if (hipEventElapsedTime(&a, c->events[3 * k], c->events[3 * k + 1]) != hipSuccess) return NSK_EHIP;
-    if (hipEventElapsedTime(&b, c->events[3 * k + 1], c->events[3 * k + 2]) != hipSuccess) return NSK_EHIP;
+    float a = 0.f, b = 0.f, q = 0.f;
+    if (hipEventElapsedTime(&a, c->events[4 * k], c->events[4 * k + 1]) != hipSuccess) return NSK_EHIP;
+    if (hipEventElapsedTime(&q, c->events[4 * k + 1], c->events[4 * k + 2]) != hipSuccess) return NSK_EHIP;
+    if (hipEventElapsedTime(&b, c->events[4 * k + 2], c->events[4 * k + 3]) != hipSuccess) return NSK_EHIP;
     out[0] += a;
     out[1] += b;
+    out[3] += q;
   }
   out[2] = c->timed;
   c->timed = 0;
@@ -319,6 +348,7 @@ int nsk_rhs(nsk_ctx* c, const double* d_U, double* d_R, double t) {
   (void)t;
   if (!c || !d_U || !d_R || d_U == d_R) return NSK_EINVAL;
   if (!c->bound) return NSK_EUNBOUND;
+  if (c->par.closure == 1 && !c->cl_w) return NSK_EINVAL;  // closure enabled, no network set
   StageArgs st{0.0, 0.0, 0.0, 0};
   return dispatch(c, 0, d_U, d_R, nullptr, st);
 }
@@ -326,6 +356,7 @@ int nsk_rhs(nsk_ctx* c, const double* d_U, double* d_R, double t) {
 int nsk_rk_step(nsk_ctx* c, double dt, int nsteps) {
   if (!c || nsteps < 0 || !(dt > 0.0) || !std::isfinite(dt)) return NSK_EINVAL;
   if (!c->bound) return NSK_EUNBOUND;
+  if (c->par.closure == 1 && !c->cl_w) return NSK_EINVAL;  // closure enabled, no network set
   for (int step = 0; step < nsteps; ++step) {
     for (int s = 0; s < 5; ++s) {
       StageArgs st{kRkA[s], kRkB[s], dt, 1};
@@ -403,6 +434,7 @@ int nsk_autotune(nsk_ctx* c, int reps, int* variant_out, int* order_out, double*
   if (!c || reps < 1) return NSK_EINVAL;
   if (!c->bound) return NSK_EUNBOUND;
   if (c->cur != 0) return NSK_EINVAL;  // the scratch state buffer must be free
+  if (c->par.closure == 1 && !c->cl_w) return NSK_EINVAL;  // closure enabled, no network set
   const int keep_tile = c->tile, keep_order = c->order;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return NSK_EHIP;
@@ -447,7 +479,8 @@ int nsk_set_params(nsk_ctx* c, const nsk_params* p) {
   if (!c) return NSK_EINVAL;
   int rc = check_params(p);
   if (rc) return rc;
-  if (p->precision != c->par.precision) return NSK_EINVAL;  // workspace layout depends on it
+  // the workspace layout depends on the precision and the closure flag
+  if (p->precision != c->par.precision || p->closure != c->par.closure) return NSK_EINVAL;
   c->par = *p;
   spinodal_band(c->par.T, c->rho_lo64, c->rho_hi64);
   return NSK_OK;

@@ -53,6 +53,13 @@ class nsk_params(C.Structure):
     ]
 
 
+class nsk_closure_norm(C.Structure):
+    _fields_ = [(k, C.c_float) for k in ("s0", "k0", "s1", "k1", "k2", "k3", "g0", "out_m", "out_c")]
+
+
+NSK_MLP_NPARAM = 8770
+
+
 class nsk_diag(C.Structure):
     _fields_ = [
         ("mass", C.c_double * 5),
@@ -113,6 +120,17 @@ def load() -> C.CDLL:
         L.nsk_batch_groups.argtypes = [vp, ip, ip, ip, ip, C.c_int]
         L.nsk_timing_enable.argtypes = [vp, C.c_int]
         L.nsk_timing_read.argtypes = [vp, dp]
+        fp = C.POINTER(C.c_float)
+        L.nsk_closure_set.argtypes = [vp, vp, C.POINTER(nsk_closure_norm)]
+        L.nsk_closure_nudge.argtypes = [vp, C.POINTER(nsk_closure_norm), vp, C.c_double, C.c_double, C.c_double, vp,
+                                        vp]
+        L.nsk_mlp_forward.argtypes = [vp, vp, C.c_longlong, vp, vp]
+        L.nsk_mlp_workspace_bytes.argtypes = [C.c_longlong]
+        L.nsk_mlp_workspace_bytes.restype = C.c_size_t
+        L.nsk_mlp_loss_grad.argtypes = [vp, vp, vp, vp, C.c_longlong, C.c_float, C.c_float, vp, vp, vp, vp]
+        L.nsk_mlp_adam.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, vp]
+        L.nsk_mlp_moments.argtypes = [vp, C.c_longlong, C.c_int, vp, vp, vp]
+        del fp
         L.nsk_strerror.argtypes = [C.c_int]
         L.nsk_strerror.restype = C.c_char_p
         _lib = L
@@ -225,10 +243,12 @@ def nsk_timing_enable(ctx: int, enable: int) -> None:
     _check("nsk_timing_enable", load().nsk_timing_enable(ctx, enable))
 
 
-def nsk_timing_read(ctx: int) -> tuple[float, float, int]:
-    out = (C.c_double * 3)()
+def nsk_timing_read(ctx: int) -> tuple[float, float, int, float]:
+    """(summed ms of the lifting kernel, of the right-hand-side kernel,
+    number of stages timed, summed ms of the closure kernel)."""
+    out = (C.c_double * 4)()
     _check("nsk_timing_read", load().nsk_timing_read(ctx, out))
-    return out[0], out[1], int(out[2])
+    return out[0], out[1], int(out[2]), out[3]
 
 
 def nsk_batch_create(meshes: list, params: nsk_params) -> int:
@@ -291,6 +311,48 @@ def nsk_batch_groups(b: int) -> list:
     return [{"N": Ns[i], "variant": vs[i], "gridmul": gm[i], "order": od[i]} for i in range(n)]
 
 
+def nsk_closure_set(ctx: int, d_w: int, norm: dict) -> None:
+    nm = _norm_struct(norm)
+    _check("nsk_closure_set", load().nsk_closure_set(ctx, d_w, C.byref(nm)))
+
+
+def _norm_struct(norm: dict) -> nsk_closure_norm:
+    full = {k: 0.0 for k in ("s0", "k0", "s1", "k1", "k2", "k3", "g0", "out_m", "out_c")}
+    full.update(norm)
+    return nsk_closure_norm(**{k: float(v) for k, v in full.items()})
+
+
+def nsk_closure_nudge(ctx: int, norm: dict, d_Uref: int, dt: float, tau: float, cmap: float, d_X: int,
+                      d_Y: int) -> None:
+    nm = _norm_struct(norm)
+    _check("nsk_closure_nudge",
+           load().nsk_closure_nudge(ctx, C.byref(nm), d_Uref, dt, tau, cmap, d_X or None, d_Y or None))
+
+
+def nsk_mlp_forward(d_w: int, d_X: int, n: int, d_Y: int, stream: int) -> None:
+    _check("nsk_mlp_forward", load().nsk_mlp_forward(d_w, d_X, n, d_Y, stream))
+
+
+def nsk_mlp_workspace_bytes(batch: int) -> int:
+    return load().nsk_mlp_workspace_bytes(batch)
+
+
+def nsk_mlp_loss_grad(d_w: int, d_X: int, d_Y: int, d_idx: int, n: int, tscale0: float, tscale1: float, d_ws: int,
+                      d_grad: int, d_loss: int, stream: int) -> None:
+    _check("nsk_mlp_loss_grad",
+           load().nsk_mlp_loss_grad(d_w, d_X, d_Y, d_idx or None, n, tscale0, tscale1, d_ws, d_grad, d_loss or None,
+                                    stream))
+
+
+def nsk_mlp_adam(d_master: int, d_w: int, d_m: int, d_v: int, d_grad: int, t: int, lr: float, beta1: float,
+                 beta2: float, eps: float, stream: int) -> None:
+    _check("nsk_mlp_adam", load().nsk_mlp_adam(d_master, d_w, d_m, d_v, d_grad, t, lr, beta1, beta2, eps, stream))
+
+
+def nsk_mlp_moments(d_Y: int, n: int, ncol: int, d_ws: int, d_out: int, stream: int) -> None:
+    _check("nsk_mlp_moments", load().nsk_mlp_moments(d_Y, n, ncol, d_ws, d_out, stream))
+
+
 # ---- convenience owner of the device buffers (torch) ----------------------
 @dataclass
 class Solver:
@@ -308,6 +370,7 @@ class Solver:
     beta: float = 1e-3
     diss_c: int = 1
     precision: int = 0
+    closure: int = 0
     xbreaks: list | None = None
     device: str = "cuda:0"
     stream: object = None
@@ -317,7 +380,8 @@ class Solver:
         import torch
 
         mesh, keep = make_mesh(self.dim, self.N, self.nel, self.lo, self.hi, self.xbreaks)
-        params = make_params(self.T, self.eps, self.kappa, self.alpha, self.beta, self.diss_c, self.precision)
+        params = make_params(self.T, self.eps, self.kappa, self.alpha, self.beta, self.diss_c, self.precision,
+                             closure=self.closure)
         self.ctx = nsk_create(mesh, params)
         del keep
         n = nsk_state_size(self.ctx)

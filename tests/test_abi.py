@@ -66,7 +66,7 @@ def test_create_rejects_bad_mesh(bad):
 
 @pytest.mark.parametrize("bad", [
     dict(T=0.0), dict(T=1.0), dict(alpha=0.0), dict(alpha=0.9), dict(T=0.5, alpha=2.9), dict(beta=0.0), dict(beta=-1.0), dict(eps=-1e-3),
-    dict(kappa=-1.0), dict(precision=2), dict(flux=1), dict(closure=1), dict(diss_c=2),
+    dict(kappa=-1.0), dict(precision=2), dict(flux=1), dict(closure=2), dict(diss_c=2),
     dict(alpha=float("nan")),
 ])
 def test_create_rejects_bad_params(bad):
@@ -107,3 +107,42 @@ def test_unbound_calls_fail_cleanly():
 def test_strerror():
     assert "invalid" in nsk.nsk_strerror(nsk.NSK_EINVAL)
     assert nsk.nsk_strerror(12345) == "unknown error"
+
+
+def test_closure_host_side_checks():
+    """Closure entry points validate on the host before touching a device."""
+    m, keep = _ok_mesh()
+    plain = nsk.nsk_create(m, nsk.make_params(alpha=200.0))
+    cl = nsk.nsk_create(m, nsk.make_params(alpha=200.0, closure=1))
+    norm = dict(s0=1.0, k0=1.0, s1=1.0, k1=1.0, k2=1.0, k3=1.0, g0=0.1, out_m=1.0, out_c=1.0)
+    try:
+        # a closure context carries its FP32 source buffer in the workspace
+        assert nsk.nsk_workspace_bytes(cl) > nsk.nsk_workspace_bytes(plain)
+        fake = 256  # never dereferenced: every call below fails its host checks
+        with pytest.raises(nsk.NskError):
+            nsk.nsk_closure_set(plain, fake, norm)          # closure not enabled
+        with pytest.raises(nsk.NskError):
+            nsk.nsk_closure_set(cl, fake, dict(norm, g0=0.0))
+        with pytest.raises(nsk.NskError):
+            nsk.nsk_closure_set(cl, fake, dict(norm, k2=float("inf")))
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_closure_nudge(cl, norm, fake, 1e-6, 1e-4, 10.0, 0, 0)
+        assert e.value.code == nsk.NSK_EUNBOUND
+        with pytest.raises(nsk.NskError):
+            nsk.nsk_closure_nudge(cl, norm, fake, 1e-6, 0.0, 10.0, 0, 0)  # tau <= 0
+        # the closure flag fixes the workspace layout
+        with pytest.raises(nsk.NskError):
+            nsk.nsk_set_params(plain, nsk.make_params(alpha=200.0, closure=1))
+        with pytest.raises(nsk.NskError):
+            nsk.nsk_mlp_adam(fake, fake, fake, fake, fake, 0, 1e-3, 0.9, 0.999, 1e-8, 0)  # step 0
+        with pytest.raises(nsk.NskError):
+            nsk.nsk_mlp_loss_grad(fake, fake, fake, 0, 0, 1.0, 1.0, fake, fake, 0, 0)  # no samples
+        nsk.nsk_mlp_forward(fake, fake, 0, fake, 0)  # nothing to do
+        assert nsk.nsk_mlp_workspace_bytes(32768) >= 1024 * 8771 * 4
+        bm, bkeep = nsk.make_mesh(3, 3, (2, 2, 2))
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_batch_create([bm], nsk.make_params(alpha=200.0, closure=1))
+        assert e.value.code == nsk.NSK_EUNSUPPORTED
+    finally:
+        nsk.nsk_destroy(plain)
+        nsk.nsk_destroy(cl)

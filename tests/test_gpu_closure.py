@@ -1,0 +1,260 @@
+"""Learned closure on the GPU against the FP64 oracle: network forward
+(BF16 MFMA), loss gradient and Adam (FP32 training kernels), the nudging step
+and the closure source inside the right-hand side; then what a trained
+network gains over the plain moderate-alpha run.
+
+Tolerances.  The oracle evaluates the network in FP64 with exact erf on the
+same BF16 parameters; the GPU rounds the first two hidden activations to
+BF16 (relative 2^-9) and uses an erf accurate to 1.5e-7.  Each output is a
+sum of about 64 products whose rounding errors are independent, so the
+output error is a few 1e-3 of the scale of those products: the forward
+bound is 1e-2 of the largest output and 4e-3 of its RMS on networks whose
+outputs are not small differences of larger terms (an FP64 emulation of the
+BF16 rounding gives up to 3e-2 of the largest output when they are).
+Gradients: 2e-2 of the gradient norm."""
+import numpy as np
+import pytest
+
+from test_oracle_closure import NPARAM, routing_network
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16(w):
+    from paper_1912_12059_amd import closure as CL
+
+    return CL.bf16_bits_to_f64(CL.to_bf16_bits(w))
+
+
+def _net(gpu, w):
+    from paper_1912_12059_amd import closure as CL
+
+    return CL.Network(params=np.asarray(w, dtype=np.float32))
+
+
+def test_mlp_forward_routing_network(gpu):
+    import torch
+
+    w = routing_network()
+    net = _net(gpu, w)
+    X = np.random.default_rng(0).uniform(-2, 2, (1000, 4)).astype(np.float32)
+    Y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+    # exact in FP64; BF16 rounding of the routed activations costs < 2^-8 |x|
+    np.testing.assert_allclose(Y[:, 0], X[:, 0] + 0.25, atol=2e-2)
+    np.testing.assert_allclose(Y[:, 1], X[:, 1] - X[:, 3] - 0.5, atol=3e-2)
+
+
+@pytest.mark.parametrize("n", [1, 63, 256, 1000, 4099])
+def test_mlp_forward_matches_oracle(O, gpu, n):
+    import torch
+
+    from paper_1912_12059_amd import closure as CL
+
+    w = CL.init_params(seed=3) * 1.5
+    w[np.arange(NPARAM) % 7 == 0] += 0.05  # non-zero biases
+    wb = _bf16(w)
+    X = np.random.default_rng(n).normal(0, 1.2, (n, 4)).astype(np.float32)
+    net = _net(gpu, w)
+    Yg = net.forward(torch.from_numpy(X).cuda()).cpu().numpy().astype(np.float64)
+    Yc = O.mlp_forward(wb, X.astype(np.float64))
+    err = np.abs(Yg - Yc)
+    assert err.max() <= 1e-2 * np.abs(Yc).max()
+    assert np.sqrt((err ** 2).mean()) <= 4e-3 * np.sqrt((Yc ** 2).mean())
+
+
+def test_loss_grad_matches_oracle(O, gpu):
+    import torch
+
+    from paper_1912_12059_amd import closure as CL
+
+    w = CL.init_params(seed=5)
+    w[np.arange(NPARAM) % 5 == 0] += 0.03
+    wb = _bf16(w)
+    rng = np.random.default_rng(6)
+    n = 1000
+    X = rng.normal(0, 1.0, (n, 4)).astype(np.float32)
+    T = rng.normal(0, 1.0, (n, 2)).astype(np.float32)
+    idx = rng.permutation(n)[:777].astype(np.int32)
+    net = _net(gpu, w)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    q = (0.5, 2.0)
+    loss, grad = net.loss_grad(Xd, Td, torch.from_numpy(idx).cuda(), tscale=q)
+    Tq = T[idx].astype(np.float64) * np.array(q)
+    lc, gc = O.mlp_loss_grad(wb, X[idx].astype(np.float64), Tq)
+    assert float(loss.item()) == pytest.approx(lc, rel=1e-2)
+    g = grad.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(g - gc) <= 2e-2 * np.linalg.norm(gc)
+    # the same call twice gives the same bits (fixed-order reduction)
+    loss2, grad2 = net.loss_grad(Xd, Td, torch.from_numpy(idx).cuda(), tscale=q)
+    assert torch.equal(grad, grad2) and torch.equal(loss, loss2)
+
+
+def test_adam_matches_oracle(O, gpu):
+    import torch
+
+    from paper_1912_12059_amd import closure as CL
+
+    w = CL.init_params(seed=7)
+    net = _net(gpu, w)
+    rng = np.random.default_rng(8)
+    wc, mc, vc = w.astype(np.float64), np.zeros(NPARAM), np.zeros(NPARAM)
+    for t in range(1, 4):
+        g = rng.normal(0, 1e-2, NPARAM).astype(np.float32)
+        net.adam(torch.from_numpy(g).cuda(), 1e-3)
+        O.adam_step(wc, mc, vc, g.astype(np.float64), 1e-3, 0.9, 0.999, 1e-8, t)
+    master = net.master.cpu().numpy()
+    np.testing.assert_allclose(master, wc, rtol=1e-5, atol=1e-7)
+    # the BF16 copy is the master rounded to nearest even
+    np.testing.assert_array_equal(net.w.cpu().numpy().view(np.uint16), CL.to_bf16_bits(master))
+
+
+def test_moments(gpu):
+    import torch
+
+    from paper_1912_12059_amd import closure as CL
+
+    Y = np.random.default_rng(9).normal([1.0, -3.0], [0.5, 2.0], (100003, 2)).astype(np.float32)
+    mean, std = CL.moments(torch.from_numpy(Y).cuda())
+    Y64 = Y.astype(np.float64)
+    np.testing.assert_allclose(mean, Y64.mean(0), rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(std, Y64.std(0), rtol=1e-9)
+
+
+NORM = dict(s0=1.06, k0=1.3, s1=0.9, k1=0.7, k2=0.02, k3=-0.003, g0=0.5, out_m=2.0, out_c=-3.0)
+
+
+@pytest.mark.parametrize("dim,N,nel", [(1, 3, (9,)), (2, 4, (5, 3)), (3, 3, (3, 4, 2)), (3, 4, (3, 3, 3))])
+def test_nudge_matches_oracle(O, gpu, dim, N, nel):
+    import torch
+
+    from paper_1912_12059_amd import inputs as I
+
+    hi = (1.0, 0.8, 1.2)
+    _, U = I.smooth_random(dim, N, nel, seed=11, hi=hi)
+    _, Ur = I.smooth_random(dim, N, nel, seed=12, hi=hi)
+    dt, tau, cmap = 1e-5, 4e-4, 10.0
+    s = gpu.Solver(dim=dim, N=N, nel=nel, hi=hi, alpha=200.0, kappa=1e-4)
+    s.set_state(U)
+    S = s.nelem * s.nnode
+    X = torch.empty((S, 4), dtype=torch.float32, device="cuda")
+    Y = torch.empty((S, 2), dtype=torch.float32, device="cuda")
+    Urd = torch.from_numpy(Ur.reshape(-1)).cuda()
+    gpu.nsk_closure_nudge(s.ctx, NORM, Urd.data_ptr(), dt, tau, cmap, X.data_ptr(), Y.data_ptr())
+    Ug = s.get_state().cpu().numpy()
+    P = O.Problem(dim=dim, N=N, nel=nel, hi=hi, alpha=200.0, kappa=1e-4)
+    Uc, Xc, Yc = O.closure_nudge(P, U, Ur, dt, tau, cmap, NORM)
+    np.testing.assert_allclose(Ug, Uc, rtol=1e-14, atol=1e-15)
+    Xg = X.cpu().numpy().astype(np.float64)
+    for k in range(4):
+        scale = np.abs(Xc[:, k]).max() + 1e-30
+        assert np.abs(Xg[:, k] - Xc[:, k]).max() <= 2e-6 * scale, k
+    Yg = Y.cpu().numpy().astype(np.float64)
+    for k in range(2):
+        assert np.abs(Yg[:, k] - Yc[:, k]).max() <= 2e-6 * np.abs(Yc[:, k]).max(), k
+    s.close()
+
+
+@pytest.mark.parametrize("dim,N,nel", [(2, 4, (6, 5)), (3, 4, (3, 4, 3)), (1, 5, (11,))])
+def test_closure_source_in_rhs(O, gpu, dim, N, nel):
+    import torch
+
+    from paper_1912_12059_amd import closure as CL
+    from paper_1912_12059_amd import inputs as I
+
+    _, U = I.smooth_random(dim, N, nel, seed=21)
+    w = CL.init_params(seed=4)
+    w[np.arange(NPARAM) % 7 == 0] += 0.05  # non-zero biases: outputs are not small differences
+    net = _net(gpu, w)
+    phys = dict(dim=dim, N=N, nel=nel, alpha=200.0, kappa=1e-4)
+    plain = gpu.Solver(**phys)
+    cl = CL.closure_solver(net, NORM, **phys)
+    Rp = plain.rhs(U).cpu().numpy()
+    Rc = cl.rhs(U).cpu().numpy()
+    P = O.Problem(dim=dim, N=N, nel=nel, alpha=200.0, kappa=1e-4)
+    Sc = O.closure_source(P, U, net.bf16_values(), NORM)
+    d = Rc - Rp
+    assert np.all(d[0] == 0.0)
+    # checks the wiring (component, direction n, scales), where a mistake is an
+    # O(1) error; the network's own precision is bounded by the forward tests
+    for v in range(1, dim + 2):
+        assert np.abs(d[v] - Sc[v]).max() <= 5e-2 * np.abs(Sc[v]).max() + 1e-12 * np.abs(Rp[v]).max(), v
+    plain.close()
+    cl.close()
+
+
+def test_closure_guards(gpu):
+    import torch
+
+    from paper_1912_12059_amd import nsk
+
+    s = gpu.Solver(dim=2, N=3, nel=(4, 4), alpha=200.0, closure=1)
+    U = torch.ones(s.U.numel(), dtype=torch.float64, device="cuda")
+    R = torch.empty_like(U)
+    assert nsk.load().nsk_rhs(s.ctx, U.data_ptr(), R.data_ptr(), 0.0) == nsk.NSK_EINVAL  # no network set
+    assert nsk.load().nsk_rk_step(s.ctx, 1e-6, 1) == nsk.NSK_EINVAL
+    s.close()
+    plain = gpu.Solver(dim=2, N=3, nel=(4, 4), alpha=200.0)
+    w = torch.zeros(NPARAM, dtype=torch.int16, device="cuda")
+    with pytest.raises(nsk.NskError):
+        nsk.nsk_closure_set(plain.ctx, w.data_ptr(), NORM)  # closure not enabled
+    plain.close()
+
+
+def test_trained_closure_gains_over_plain_alpha200(gpu):
+    """2D droplets, kappa = 1e-4: train on nudged alpha = 200 / 2000 pairs of
+    three droplet configurations, then run a held-out configuration at
+    alpha = 200 with and without the closure; both are judged against the
+    plain alpha = 2000 run at the same time."""
+    import torch
+
+    from paper_1912_12059_amd import closure as CL
+    from paper_1912_12059_amd import inputs as I
+
+    # 64^2: at 48^2 the plain alpha = 200 run is unstable at CFL 0.5 (its
+    # source and parabolic limits nearly coincide and the rule takes the min)
+    nel, N, kappa, tend = 64, 4, 1e-4, 0.01
+    mesh = dict(dim=2, N=N, nel=(nel, nel))
+    norm = CL.default_norm(kappa)
+
+    def ic(seed, r, sep, dy):
+        cen = ((0.5 - sep / 2, 0.5 - dy / 2), (0.5 + sep / 2, 0.5 + dy / 2))
+        _, U = I.droplets_2d(nel=nel, N=N, radius=r, centres=cen, seed=seed)
+        return torch.from_numpy(U.reshape(-1)).cuda()
+
+    Xs, Ys = [], []
+    for sd, r, sep, dy in ((2, 0.12, 0.28, 0.0), (3, 0.10, 0.26, 0.02), (4, 0.14, 0.32, 0.0)):
+        X, Y, info = CL.nudged_pairs(mesh, ic(sd, r, sep, dy), 2000.0, 200.0, kappa, tend, norm, record_every=20)
+        Xs.append(X)
+        Ys.append(Y)
+    X, Y = torch.cat(Xs), torch.cat(Ys)
+    _, std = CL.moments(Y)
+    norm.update(out_m=float(std[0]), out_c=float(std[1]))
+    net = CL.Network(seed=0)
+    net.train(X, Y, steps=3000, batch=16384, lr=2e-3, lr_final=2e-4, tscale=(1.0 / std[0], 1.0 / std[1]))
+    U0 = ic(11, 0.12, 0.28, 0.0)
+    ref = gpu.Solver(alpha=2000.0, kappa=kappa, **mesh)
+    ref.set_state(U0)
+    dt_ref = ref.dt_estimate(0.5)
+    M, nst = info["M"], info["steps"]
+    ref.rk_step(dt_ref, M * nst)
+    Ur = ref.get_state().cpu().numpy()
+    plain = gpu.Solver(alpha=200.0, kappa=kappa, **mesh)
+    plain.set_state(U0)
+    plain.rk_step(M * dt_ref, nst)
+    Up = plain.get_state().cpu().numpy()
+    cl = CL.closure_solver(net, norm, alpha=200.0, kappa=kappa, **mesh)
+    cl.set_state(U0)
+    cl.rk_step(M * dt_ref, nst)
+    Uc = cl.get_state().cpu().numpy()
+    U0h = U0.cpu().numpy().reshape(Ur.shape)
+    change = np.linalg.norm(Ur[0] - U0h[0])
+
+    def err(U):
+        return np.linalg.norm(U[0] - Ur[0]) / change, np.linalg.norm(U[1:3] - Ur[1:3]) / np.linalg.norm(Ur[1:3])
+
+    ep, ec = err(Up), err(Uc)
+    print(f"\nrho error / change: plain {ep[0]:.3e} closure {ec[0]:.3e};  momentum: plain {ep[1]:.3e} "
+          f"closure {ec[1]:.3e}")
+    assert np.all(np.isfinite(Uc))
+    assert ec[0] < 0.8 * ep[0]
+    assert ec[1] < ep[1]
