@@ -260,6 +260,131 @@ def run_batched(nsk, steps: int, warmup: int):
     }
 
 
+def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20):
+    """Closure form, kappa = 1e-4 (interface width 2 sqrt(kappa) = 0.02).
+    A network is trained here, from seeded initial weights, on nudged
+    alpha = 200 / 2000 pairs of two 3D collisions on [0,1]x[0,0.5]^2 with
+    48x24x24 elements, N = 4 (the element size of the full collision mesh),
+    R = 0.1, to t_end.  Accuracy: a held-out collision of the same size runs
+    to t_end at alpha = 2000, alpha = 200 and alpha = 200 with the closure;
+    errors are the L2 of rho against the alpha = 2000 run over the L2 of its
+    change.  Speed: the three runs are timed per step on the full
+    96x48x48 mesh; the effective rate counts the alpha = 2000 DOF-stages to
+    t_end over the time the run needs to reach t_end."""
+    import torch
+
+    from paper_1912_12059_amd import closure as CL
+    from paper_1912_12059_amd import inputs as I
+
+    kappa, N = 1e-4, 4
+    small = dict(dim=3, N=N, nel=(48, 24, 24), hi=(1.0, 0.5, 0.5))
+    norm = CL.default_norm(kappa)
+
+    def small_ic(We, b):
+        _, U = I.collision_3d(nel=small["nel"], N=N, We=We, radius=0.1, hi=small["hi"], impact=b, device="cuda:0")
+        return U.reshape(-1)
+
+    t0 = time.perf_counter()
+    Xs, Ys = [], []
+    for We, b in ((40.0, 0.0), (100.0, 0.05)):
+        X, Y, info = CL.nudged_pairs(small, small_ic(We, b), 2000.0, 200.0, kappa, tend, norm, record_every=100)
+        Xs.append(X)
+        Ys.append(Y)
+    X, Y = torch.cat(Xs), torch.cat(Ys)
+    del Xs, Ys
+    _, std = CL.moments(Y)
+    norm.update(out_m=float(std[0]), out_c=float(std[1]))
+    net = CL.Network(seed=0)
+    net.train(X, Y, steps=3000, batch=32768, lr=2e-3, lr_final=2e-4, tscale=(1.0 / std[0], 1.0 / std[1]))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    nsamp = X.shape[0]
+    del X, Y
+    print(f"[bench] closure trained on {nsamp} samples in {train_s:.1f} s", file=sys.stderr, flush=True)
+
+    # accuracy on a held-out collision
+    dt_ref, M, n_mod = info["dt_ref"], info["M"], info["steps"]
+    n_ref = M * n_mod
+    U0 = small_ic(70.0, 0.03)
+    ref = nsk.Solver(alpha=2000.0, kappa=kappa, **small)
+    ref.set_state(U0)
+    ref.rk_step(dt_ref, n_ref)
+    Ur = ref.get_state()
+    ref.close()
+    plain = nsk.Solver(alpha=200.0, kappa=kappa, **small)
+    plain.set_state(U0)
+    plain.rk_step(M * dt_ref, n_mod)
+    Up = plain.get_state()
+    plain.close()
+    cl = CL.closure_solver(net, norm, alpha=200.0, kappa=kappa, **small)
+    cl.set_state(U0)
+    cl.rk_step(M * dt_ref, n_mod)
+    Uc = cl.get_state()
+    cl.close()
+    U0r = U0.reshape(Ur.shape)
+    change = float(torch.linalg.vector_norm(Ur[0] - U0r[0]))
+
+    def err(U):
+        return float(torch.linalg.vector_norm(U[0] - Ur[0])) / change
+
+    # speed on the full mesh
+    w = WORKLOADS["3d-collision"]
+    full = dict(dim=3, N=N, nel=w["nel"], lo=w["lo"], hi=w["hi"])
+    _, Uf = I.collision_3d(nel=w["nel"], N=N, We=w["We"], lo=w["lo"], hi=w["hi"], device="cuda:0")
+    Uf = Uf.reshape(-1)
+    dofs = Uf.numel() // 5
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def ms_per_step(s, dt):
+        s.set_state(Uf)
+        nsk.nsk_autotune(s.ctx, 2)
+        s.rk_step(dt, 2)
+        s.set_state(Uf)
+        torch.cuda.synchronize()
+        e0.record(s.stream)
+        s.rk_step(dt, timing_steps)
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / timing_steps
+
+    sref = nsk.Solver(alpha=2000.0, kappa=kappa, **full)
+    ms_ref = ms_per_step(sref, dt_ref)
+    sref.close()
+    splain = nsk.Solver(alpha=200.0, kappa=kappa, **full)
+    ms_plain = ms_per_step(splain, M * dt_ref)
+    splain.close()
+    scl = CL.closure_solver(net, norm, alpha=200.0, kappa=kappa, **full)
+    scl.set_state(Uf)
+    nsk.nsk_autotune(scl.ctx, 2)
+    nsk.nsk_timing_enable(scl.ctx, 1)
+    ms_cl = ms_per_step(scl, M * dt_ref)
+    ms_lift, ms_rhs, nst, ms_cls = nsk.nsk_timing_read(scl.ctx)
+    nsk.nsk_timing_enable(scl.ctx, 0)
+    scl.close()
+    work = dofs * 5 * n_ref  # alpha = 2000 DOF-stages to t_end
+
+    def rate(ms, nsteps):
+        return work / (ms * nsteps * 1e-3)
+
+    return {
+        "workload": f"3d-collision {'x'.join(map(str, w['nel']))} N={N} kappa={kappa:g} t_end={n_ref * dt_ref:.4g}; "
+                    "accuracy on a held-out 48x24x24 collision (same element size), speed on the full mesh",
+        "alpha": 200.0, "alpha_ref": 2000.0, "dt_ref": dt_ref, "dt": M * dt_ref,
+        "steps_ref": n_ref, "steps": n_mod,
+        "ref_fp64": {"value": rate(ms_ref, n_ref), "ms_per_step": ms_ref},
+        "plain_alpha200": {"value": rate(ms_plain, n_mod), "ms_per_step": ms_plain,
+                           "l2_rel_rho_vs_ref": err(Up), "speedup_vs_ref": ms_ref * n_ref / (ms_plain * n_mod)},
+        "closure_alpha200": {"value": rate(ms_cl, n_mod), "ms_per_step": ms_cl,
+                             "l2_rel_rho_vs_ref": err(Uc), "speedup_vs_ref": ms_ref * n_ref / (ms_cl * n_mod),
+                             "closure_kernel_ms": ms_cls / max(nst, 1), "rhs_ms": ms_rhs / max(nst, 1),
+                             "lift_ms": ms_lift / max(nst, 1)},
+        "value_note": "effective DOF-stage/s: alpha=2000 DOF-stages to t_end / time to reach t_end",
+        "training": {"samples": nsamp, "seconds": train_s, "steps": 3000, "batch": 32768,
+                     "pairs": "nudged alpha=200 toward alpha=2000 (tau = 100 steps), collisions We=40 b=0 and "
+                              "We=100 b=0.05R on 48x24x24"},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +395,8 @@ def main() -> int:
                     help="form reported as value; the other one is measured beside it unless --no-forms")
     ap.add_argument("--no-forms", action="store_true", help="skip the second precision form and the batch")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched collision sweep")
+    ap.add_argument("--no-closure", action="store_true", help="skip the closure form")
+    ap.add_argument("--only-closure", action="store_true", help="run only the closure form (prints its block)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="auto", help="auto (autotuner) or 'variant,order', e.g. 0,4")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -294,6 +421,9 @@ def main() -> int:
 
     from paper_1912_12059_amd import nsk
 
+    if args.only_closure:
+        print(json.dumps({"closure": run_closure_form(nsk)}))
+        return 0
     w = WORKLOADS[args.workload]
     print(f"[bench] building {args.workload} state", file=sys.stderr, flush=True)
     m, U = build_state(args.workload)
@@ -383,6 +513,8 @@ def main() -> int:
     del forms
     if not args.no_forms and not args.no_batched and args.workload == "3d-collision":
         out.setdefault("forms", {})["batched"] = run_batched(nsk, 10, 2)
+    if not args.no_forms and not args.no_closure and args.workload == "3d-collision":
+        out.setdefault("forms", {})["closure"] = run_closure_form(nsk)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, sample, sub)

@@ -56,33 +56,34 @@ struct ClosureArgs {
 // ---- BF16 -----------------------------------------------------------------
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
 
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-  // round to nearest even
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return uint16_t(u >> 16);
-}
+// round to nearest even (the conversion lowers to v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 __device__ __forceinline__ float bf16_round(float f) { return bf16_to_f32(f32_to_bf16(f)); }
 
 // ---- GELU (erf form) --------------------------------------------------------
-// erf from Abramowitz & Stegun formula 7.1.26 (absolute error <= 1.5e-7),
-// far below the BF16 rounding of the activations.
-__device__ __forceinline__ float erf_as(float x) {
-  const float a = fabsf(x);
-  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * a);
-  const float poly =
-      t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
-  const float e = 1.0f - poly * __expf(-a * a);
-  return copysignf(e, x);
+// g(z) = z Phi(z), Phi the standard normal CDF (Phi(z) = (1 + erf(z/sqrt 2))/2).
+// Phi(z) - 1/2 ~ z Q(z^2) on |z| <= 3.7 (z clamped there), Q of degree 6
+// fitted by least squares at Chebyshev nodes (fit_erf.py): error <= 6.2e-5,
+// far below the 2^-9 rounding of the BF16 activations, in 10 instructions
+// and no transcendental one.
+__device__ __forceinline__ float phi_poly(float z) {
+  const float zc = fminf(fmaxf(z, -3.7f), 3.7f);
+  const float u = zc * zc;
+  float q = 4.179373891e-08f;
+  q = fmaf(q, u, -2.488350468e-06f);
+  q = fmaf(q, u, 6.416094105e-05f);
+  q = fmaf(q, u, -9.583462844e-04f);
+  q = fmaf(q, u, 9.417267311e-03f);
+  q = fmaf(q, u, -6.588417949e-02f);
+  q = fmaf(q, u, 3.987580534e-01f);
+  return fmaf(zc, q, 0.5f);
 }
 
-__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_f(float z) { return z * phi_poly(z); }
 
 __device__ __forceinline__ float gelu_df(float z) {
-  const float Phi = 0.5f * (1.0f + erf_as(z * 0.70710678118654752f));
-  return Phi + z * 0.39894228040143268f * __expf(-0.5f * z * z);
+  return phi_poly(z) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
 }
 
 // ---- element-local features ---------------------------------------------------
@@ -169,11 +170,17 @@ constexpr int kWPad = kMlpHid + 4;
 __device__ __forceinline__ void mlp_wave(const float4* sX, const uint16_t* sW, const float* sP, int slot0, float y[2]) {
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5, col = lane & 31;
-  // layer 1 in the B-operand layout: lane holds units 8s + 4 half + q of
-  // node col of column block jb
-  bf16x4 b1[2][8];
-#pragma unroll
+  y[0] = y[1] = 0.f;
+  // one 32-node column block at a time keeps the live accumulators and
+  // operands to 2 x 16 + 2 x 8 registers
+#pragma nounroll
   for (int jb = 0; jb < 2; ++jb) {
+    // the parameters are re-read from LDS in each block rather than held in
+    // registers across blocks
+    asm volatile("" ::: "memory");
+    // layer 1 in the B-operand layout: lane holds units 8s + 4 half + q of
+    // node col of this column block
+    bf16x4 bop[8];
     const float4 x = sX[slot0 + jb * 32 + col];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
@@ -182,77 +189,59 @@ __device__ __forceinline__ void mlp_wave(const float4* sX, const uint16_t* sW, c
         const int u = 8 * s + 4 * half + q;
         const float* w1 = sP + kCW1 + u * kMlpIn;
         const float z = sP[kCB1 + u] + w1[0] * x.x + w1[1] * x.y + w1[2] * x.z + w1[3] * x.w;
-        b1[jb][s][q] = bf16_bits(gelu_f(z));
+        bop[s][q] = bf16_bits(gelu_f(z));
       }
     }
-  }
-  // layers 2 and 3
-  f32x16 acc[2][2];
-  bf16x4 bnext[2][8];
-  const uint16_t* W = sW;
+    // layers 2 and 3
+    f32x16 acc[2];
 #pragma unroll
-  for (int layer = 0; layer < 2; ++layer) {
+    for (int layer = 0; layer < 2; ++layer) {
+      const uint16_t* W = sW + layer * kMlpHid * kWPad;
 #pragma unroll
-    for (int ib = 0; ib < 2; ++ib)
+      for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
-      for (int jb = 0; jb < 2; ++jb)
+        for (int r = 0; r < 16; ++r) acc[ib][r] = 0.f;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[ib][jb][r] = 0.f;
+      for (int s = 0; s < 8; ++s) {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-#pragma unroll
-      for (int ib = 0; ib < 2; ++ib) {
-        const bf16x4 a = *reinterpret_cast<const bf16x4*>(W + (ib * 32 + col) * kWPad + 8 * s + 4 * half);
-#pragma unroll
-        for (int jb = 0; jb < 2; ++jb) {
-          const bf16x4 b = layer == 0 ? b1[jb][s] : bnext[jb][s];
-          acc[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[ib][jb], 0, 0, 0);
+        for (int ib = 0; ib < 2; ++ib) {
+          const bf16x4 a = *reinterpret_cast<const bf16x4*>(W + (ib * 32 + col) * kWPad + 8 * s + 4 * half);
+          acc[ib] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bop[s], acc[ib], 0, 0, 0);
         }
       }
-    }
-    const float* bias = sP + (layer == 0 ? kCB2 : kCB3);
+      const float* bias = sP + (layer == 0 ? kCB2 : kCB3);
 #pragma unroll
-    for (int ib = 0; ib < 2; ++ib)
+      for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float bv = bias[ib * 32 + mfma_row(r, half)];
-#pragma unroll
-        for (int jb = 0; jb < 2; ++jb) acc[ib][jb][r] = gelu_f(acc[ib][jb][r] + bv);
-      }
-    if (layer == 0) {
-      // accumulator rows 8(r/4) + 4 half + r%4 of block ib are exactly the
-      // units of k-step 4 ib + r/4 of the next layer's B operand
-#pragma unroll
-      for (int jb = 0; jb < 2; ++jb)
+        for (int r = 0; r < 16; ++r) acc[ib][r] = gelu_f(acc[ib][r] + bias[ib * 32 + mfma_row(r, half)]);
+      if (layer == 0) {
+        // accumulator rows 8(r/4) + 4 half + r%4 of block ib are exactly the
+        // units of k-step 4 ib + r/4 of the next layer's B operand
 #pragma unroll
         for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
           for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) bnext[jb][4 * ib + s][q] = bf16_bits(acc[ib][jb][4 * s + q]);
-      W = sW + kMlpHid * kWPad;
+            for (int q = 0; q < 4; ++q) bop[4 * ib + s][q] = bf16_bits(acc[ib][4 * s + q]);
+      }
     }
-  }
-  // layer 4: FP32 dot over this lane's 32 units, then across the half-waves
-  float part[2][2];
-#pragma unroll
-  for (int jb = 0; jb < 2; ++jb)
+    // layer 4: FP32 dot over this lane's 32 units, then across the half-waves
+    float part[2];
 #pragma unroll
     for (int o = 0; o < 2; ++o) {
-      float s = 0.f;
+      float sum = 0.f;
 #pragma unroll
       for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) s += sP[kCW4 + o * kMlpHid + ib * 32 + mfma_row(r, half)] * acc[ib][jb][r];
-      part[jb][o] = s;
+        for (int r = 0; r < 16; ++r) sum += sP[kCW4 + o * kMlpHid + ib * 32 + mfma_row(r, half)] * acc[ib][r];
+      part[o] = sum + __shfl_xor(sum, 32, 64);
     }
-#pragma unroll
-  for (int jb = 0; jb < 2; ++jb)
-#pragma unroll
-    for (int o = 0; o < 2; ++o) part[jb][o] += __shfl_xor(part[jb][o], 32, 64);
-  // lane = half * 32 + col takes node slot0 + lane, i.e. column block half
-  y[0] = sP[kCB4 + 0] + (half ? part[1][0] : part[0][0]);
-  y[1] = sP[kCB4 + 1] + (half ? part[1][1] : part[0][1]);
+    // lane = half * 32 + col takes node slot0 + lane, i.e. column block half
+    if (half == jb) {
+      y[0] = sP[kCB4 + 0] + part[0];
+      y[1] = sP[kCB4 + 1] + part[1];
+    }
+  }
 }
 
 // Stage the parameters the network reads from LDS: W2, W3 as BF16 with
