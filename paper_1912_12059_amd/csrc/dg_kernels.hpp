@@ -387,7 +387,10 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
     for (int v = 0; v < NV; ++v) u64[v] = U[v * S + o];
 #pragma unroll
     for (int k = 0; k < NG; ++k) g[k] = R(G[(long long)k * S + o]);
-    if (st.mode == 1 && st.A != 0.0) {
+    // FP64: the register is read early (occupancy is held at 2 waves per
+    // SIMD by the LDS anyway); mixed precision reads it at the update,
+    // which keeps the kernel under 168 VGPRs (3 waves per SIMD)
+    if (!MIXED && st.mode == 1 && st.A != 0.0) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) du_old[v] = dU[v * S + o];
     }
@@ -534,6 +537,9 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
 #pragma unroll
       for (int v = 0; v < NV; ++v) Uout[v * S + o] = Rv[v];
     } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        if (MIXED) du_old[v] = st.A != 0.0 ? dU[v * S + o] : 0.0;
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const double du = st.A * du_old[v] + st.dt * Rv[v];
