@@ -29,6 +29,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace nsk {
 
 constexpr int kMaxNP = 7;  // N <= 6
@@ -39,6 +41,15 @@ template <int B>
 struct ipow<B, 0> { static constexpr int v = 1; };
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// f(std::integral_constant<int, 0>), ..., f(std::integral_constant<int, K-1>)
+template <int K, int I = 0, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < K) {
+    f(std::integral_constant<int, I>{});
+    static_for<K, I + 1>(f);
+  }
+}
 constexpr int round64(int x) { return ((x + 63) / 64) * 64; }
 
 template <int DIM, int NP>
@@ -257,17 +268,31 @@ __device__ __forceinline__ void lift_block(int L, int tid, const double* __restr
     sW[el][DIM][n] = R(U[(DIM + 1) * S + o]);
   }
 
+  // the next direction's neighbour states are fetched into registers while
+  // the current direction's face values are formed
+  double nbu[2][DIM + 2];
+  auto fetch_nb = [&](auto dc) {
+    constexpr int dd = decltype(dc)::value;
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) {  // unrolled: d-dependent index math is compile-time
+    for (int s = 0; s < 2; ++s) {
+      const long long on = (long long)info.nb[el][dd][s] * NN + n;
+#pragma unroll
+      for (int v = 0; v < DIM + 2; ++v) nbu[s][v] = U[v * S + on];
+    }
+  };
+  if (active) fetch_nb(std::integral_constant<int, 0>{});
+
+  static_for<DIM>([&](auto dc) {  // d-dependent index math is compile-time
+    constexpr int d = decltype(dc)::value;
     if (active) {
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        const long long on = (long long)info.nb[el][d][s] * NN + n;
-        const double irho = 1.0 / U[on];
+        const double irho = 1.0 / nbu[s][0];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) sNbW[el][s][k][n] = R(U[(1 + k) * S + on] * irho);
-        sNbW[el][s][DIM][n] = R(U[(DIM + 1) * S + on]);
+        for (int k = 0; k < DIM; ++k) sNbW[el][s][k][n] = R(nbu[s][1 + k] * irho);
+        sNbW[el][s][DIM][n] = R(nbu[s][DIM + 1]);
       }
+      if constexpr (d + 1 < DIM) fetch_nb(std::integral_constant<int, d + 1>{});
     }
     __syncthreads();
     if (tid < EPB * 2 * NF) {
@@ -301,7 +326,7 @@ __device__ __forceinline__ void lift_block(int L, int tid, const double* __restr
       }
     }
     __syncthreads();
-  }
+  });
 
   if (active) {
     R q[DIM][NL];
@@ -409,8 +434,29 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = R(0);
 
+  // Neighbour values of one direction (U and the direction's viscous
+  // components) in registers.  In FP64 the LDS holds the kernel at 2 waves
+  // per SIMD whatever its register count, so the next direction's values
+  // are fetched while the current one is computed; the mixed-precision
+  // kernel (3 waves per SIMD) fetches them when it stages them.
+  constexpr bool PREFETCH = !MIXED;
+  double nbv[2][NX];
+  auto fetch_nb = [&](auto dc) {
+    constexpr int dd = decltype(dc)::value;
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) {  // unrolled: d-dependent index math is compile-time
+    for (int s = 0; s < 2; ++s) {
+      const long long on = (long long)info.nb[el][dd][s] * NN + n;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) nbv[s][v] = U[v * S + on];
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) nbv[s][NV + j] = double(G[(long long)tau_index<DIM>(j, dd) * S + on]);
+      nbv[s][NV + DIM] = double(G[(long long)(NT + dd) * S + on]);
+    }
+  };
+  if (PREFETCH && active) fetch_nb(std::integral_constant<int, 0>{});
+
+  static_for<DIM>([&](auto dc) {  // d-dependent index math is compile-time
+    constexpr int d = decltype(dc)::value;
     if (active) {
       // own viscous components of direction d and the nodal total flux
 #pragma unroll
@@ -424,18 +470,14 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
 #pragma unroll
       for (int v = 0; v < NV; ++v) sF[el][v][n] = F[v];
       // the two neighbours, coalesced
+      if (!PREFETCH) fetch_nb(dc);
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        const long long on = (long long)info.nb[el][d][s] * NN + n;
-        const double rn = U[on];
-        if (MIXED) sRho64[MIXED ? el : 0][1 + s][MIXED ? n : 0] = rn;
-        sNb[el][s][0][n] = R(rn);
+        if (MIXED) sRho64[MIXED ? el : 0][1 + s][MIXED ? n : 0] = nbv[s][0];
 #pragma unroll
-        for (int v = 1; v < NV; ++v) sNb[el][s][v][n] = R(U[v * S + on]);
-#pragma unroll
-        for (int j = 0; j < DIM; ++j) sNb[el][s][NV + j][n] = R(G[(long long)tau_index<DIM>(j, d) * S + on]);
-        sNb[el][s][NV + DIM][n] = R(G[(long long)(NT + d) * S + on]);
+        for (int x = 0; x < NX; ++x) sNb[el][s][x][n] = R(nbv[s][x]);
       }
+      if constexpr (PREFETCH && d + 1 < DIM) fetch_nb(std::integral_constant<int, d + 1>{});
     }
     __syncthreads();
     if (tid < EPB * 2 * NF) {
@@ -519,7 +561,7 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
       }
     }
     __syncthreads();  // LDS reused by the next direction
-  }
+  });
 
   // source (FP64) and update
   if (active) {
