@@ -705,6 +705,12 @@ rhs_kernel_batch(const BatchInst* __restrict__ inst, const BatchItem* __restrict
 // 11 non-finite count, 12 max_e sum_d max(|v_d|+a)/h_d.
 // -------------------------------------------------------------------------
 constexpr int kDiagSlots = 13;
+
+__device__ __forceinline__ int elem_index_dir_diag(const MeshArgs& m, long long e, int d) {
+  if (d == 0) return int(e % m.nel[0]);
+  if (d == 1) return int((e / m.nel[0]) % m.nel[1]);
+  return int(e / ((long long)m.nel[0] * m.nel[1]));
+}
 constexpr int kDiagThreads = 256;
 
 __device__ __forceinline__ double vdw_W(double rho, double T) {
@@ -722,36 +728,40 @@ diag_partial_kernel(const double* __restrict__ U, const GT* __restrict__ G, doub
                     const double* __restrict__ wq1, MeshArgs msh, PhysArgs ph) {
   using Sh = Shape<DIM, NP>;
   constexpr int NN = Sh::NN, NV = Sh::NVAR, NT = Sh::NTAU;
+  constexpr int EPBD = (kDiagThreads / NN) > 0 ? kDiagThreads / NN : 1;  // whole elements per group
+  constexpr int SLOTS = EPBD * NN;
   __shared__ double red[kDiagSlots][kDiagThreads];
+  __shared__ double spd[DIM][kDiagThreads];  // per-node |v_d| + a
   const int tid = threadIdx.x;
   double acc[kDiagSlots];
   for (int k = 0; k < kDiagSlots; ++k) acc[k] = 0.0;
   acc[8] = INFINITY;
   acc[9] = -INFINITY;
   const long long S = msh.S;
-  // each thread walks whole elements so that the per-element wave-speed sum
-  // can be formed locally
-  for (int e = blockIdx.x * kDiagThreads + tid; e < msh.E; e += gridDim.x * kDiagThreads) {
-    int idx[3];
-    idx[0] = e % msh.nel[0];
-    idx[1] = (e / msh.nel[0]) % msh.nel[1];
-    idx[2] = e / (msh.nel[0] * msh.nel[1]);
-    double J = 1.0, hinv[DIM];
+  const int el = tid / NN, n = tid - (tid / NN) * NN;
+  int r = n;
+  double wn = 1.0;  // tensor-product quadrature weight of the node
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      const double h2 = msh.h2[d][idx[d]];
-      J *= 1.0 / h2;  // h/2
-      hinv[d] = 0.5 * h2;
-    }
-    double smax[DIM];
+  for (int d = 0; d < DIM; ++d) { wn *= wq1[r % NP]; r /= NP; }
+  // groups of whole elements, one thread per node (coalesced loads); the
+  // per-element directional maxima of the wave speed go through LDS
+  const long long ngroups = (msh.E + EPBD - 1) / EPBD;
+  for (long long grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const long long e = grp * EPBD + el;
+    const bool active = tid < SLOTS && e < msh.E;
+    double hinv[DIM];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) smax[d] = 0.0;
-    for (int n = 0; n < NN; ++n) {
-      const long long o = (long long)e * NN + n;
-      double wgt = J;
-      int r = n;
+    for (int d = 0; d < DIM; ++d) spd[d][tid] = 0.0;
+    if (active) {
+      const long long o = e * NN + n;
+      double J = 1.0;
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) { wgt *= wq1[r % NP]; r /= NP; }
+      for (int d = 0; d < DIM; ++d) {
+        const double h2 = msh.h2[d][elem_index_dir_diag(msh, e, d)];
+        J *= 1.0 / h2;  // h/2
+        hinv[d] = 0.5 * h2;
+      }
+      const double wgt = J * wn;
       double u[NV];
       bool finite = true;
 #pragma unroll
@@ -779,14 +789,22 @@ diag_partial_kernel(const double* __restrict__ U, const GT* __restrict__ G, doub
         for (int d = 0; d < DIM; ++d) {
           const double sp = fabs(u[1 + d] / rho) + a;
           acc[10] = fmax(acc[10], sp);
-          smax[d] = fmax(smax[d], sp);
+          spd[d][tid] = sp;
         }
       }
     }
-    double lam = 0.0;
+    __syncthreads();
+    if (active && n == 0) {
+      double lam = 0.0;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) lam += smax[d] * hinv[d];
-    acc[12] = fmax(acc[12], lam);
+      for (int d = 0; d < DIM; ++d) {
+        double m = 0.0;
+        for (int k = 0; k < NN; ++k) m = fmax(m, spd[d][el * NN + k]);
+        lam += m * hinv[d];
+      }
+      acc[12] = fmax(acc[12], lam);
+    }
+    __syncthreads();
   }
   for (int k = 0; k < kDiagSlots; ++k) red[k][tid] = acc[k];
   __syncthreads();

@@ -232,7 +232,8 @@ int nsk_create(const nsk_mesh* mesh, const nsk_params* params, nsk_ctx** out) {
   off = align256(off + sizeof(double) * kMaxNP);
   c->off_order = off;
   off = align256(off + sizeof(int) * (size_t)c->E);
-  long long blk = (c->E + kDiagThreads - 1) / kDiagThreads;
+  const int epbd = kDiagThreads / c->nn > 0 ? kDiagThreads / c->nn : 1;  // elements per diagnostics group
+  long long blk = (c->E + epbd - 1) / epbd;
   c->diag_blocks = (int)(blk < 1024 ? blk : 1024);
   c->off_part = off;
   off = align256(off + sizeof(double) * kDiagSlots * (size_t)c->diag_blocks);
