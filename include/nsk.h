@@ -262,11 +262,12 @@ int nsk_mlp_moments(const float* d_Y, long long n, int ncol, void* d_ws, double*
  * together with one shared parameter set and one shared time step.  The
  * states of all instances are packed into one device buffer; instance i
  * starts nsk_batch_state_offset(i) doubles into it and has the layout of a
- * single context.  Instances of one degree form a group; each stage runs one
- * lifting and one right-hand-side kernel per group over the group's list of
- * (instance, element block) items, either one workgroup per item or a
- * persistent grid walking the list in rounds, and two full steps (ten
- * stages) are captured into one HIP graph that nsk_batch_rk_step replays.
+ * single context.  Instances of one degree form a group, split into chunks
+ * of whole instances; each stage of a chunk runs one lifting and one
+ * right-hand-side kernel over the chunk's (instance, element block) items,
+ * either one workgroup per item or a persistent grid walking the list in
+ * rounds.  Two full steps (ten stages of every chunk, chunk after chunk)
+ * are captured into one HIP graph that nsk_batch_rk_step replays.
  * ------------------------------------------------------------------------ */
 typedef struct nsk_batch nsk_batch;
 
@@ -306,22 +307,38 @@ int nsk_batch_dt_estimate(nsk_batch* b, double cfl, double* dt_out);
  * ordinary step if nsteps is odd.  Asynchronous. */
 int nsk_batch_rk_step(nsk_batch* b, double dt, int nsteps);
 
-/* Autotuner per degree group: times `reps` evaluations of the group's two
- * kernels (right-hand side into scratch), first for each element order
- * 0..5 of nsk_set_tile applied to every member instance, then, with the
- * fastest order, for each elements-per-workgroup variant (0, 1) and grid
- * multiplier m in {0, 2, 4, 8} (m = 0: one workgroup per item; otherwise a
- * persistent grid of m workgroups per CU), and keeps the fastest per group.
- * ms_out (may be NULL, 14 doubles per group) receives the means: at
- * group*14 + variant*4 + multiplier index, and at group*14 + 8 + order.
- * Call between steps; waits for the stream. */
+/* Autotuner.  First every instance is tuned as by nsk_autotune (its
+ * elements-per-workgroup variant and element order, used when it runs as a
+ * chunk of its own).  Then per degree group, on the whole group as one
+ * chunk, it times `reps` evaluations of the batch kernels (right-hand side
+ * into scratch) for each variant (0, 1) and grid multiplier m in
+ * {0, 2, 4, 8} (m = 0: one workgroup per item; otherwise a persistent grid
+ * of m workgroups per CU), and last, with that shape, working-set budgets
+ * of 0 (the whole group as one chunk), 128, 256 and 512 MiB over ten
+ * consecutive stages: a group runs as chunks of whole instances whose
+ * state, state copy, register and lifted gradients fit the budget, and a
+ * graph replay runs the ten stages of one chunk back to back while its data
+ * is still in the caches.  A chunk of one instance runs the single-mesh
+ * kernels with the instance's own variant and order.  The fastest choices
+ * are kept.  ms_out (may be NULL, 12 doubles per group) receives the means
+ * per stage: at group*12 + variant*4 + multiplier index and at
+ * group*12 + 8 + budget index.  Call between steps; waits for the stream. */
 int nsk_batch_autotune(nsk_batch* b, int reps, double* ms_out);
 
+/* Sets the launch of group `group` (the order of nsk_batch_groups) by hand:
+ * elements-per-workgroup variant (0, 1) of the batch kernels and of every
+ * instance, grid multiplier (0, 2, 4, 8), element order (0..5) of its
+ * instances and working-set budget in MiB
+ * (>= 0, 0: no chunking).  Results do not depend on these choices.  Call
+ * between steps; waits for the stream. */
+int nsk_batch_set_group(nsk_batch* b, int group, int variant, int gridmul, int order, int chunk_mib);
+
 /* Describes up to max groups: polynomial degree, chosen variant, grid
- * multiplier (0: one workgroup per item) and element order of the member
- * instances.  Any output pointer may be NULL.  Returns the number of
- * groups. */
-int nsk_batch_groups(const nsk_batch* b, int* N_out, int* variant_out, int* gridmul_out, int* order_out, int max);
+ * multiplier (0: one workgroup per item), element order of the group's
+ * first instance and working-set budget in MiB (0: no chunking).  Any output
+ * pointer may be NULL.  Returns the number of groups. */
+int nsk_batch_groups(const nsk_batch* b, int* N_out, int* variant_out, int* gridmul_out, int* order_out,
+                     int* chunk_mib_out, int max);
 
 /* Static text for an NSK_* code. */
 const char* nsk_strerror(int code);

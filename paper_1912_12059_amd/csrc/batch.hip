@@ -24,7 +24,9 @@ namespace {
 
 // persistent grid = CUs * m; m = 0: one workgroup per item (no persistence)
 constexpr int kGridMults[4] = {0, 2, 4, 8};
-constexpr int kBatchTuneSlots = 8 + kOrders;  // timings per group in nsk_batch_autotune
+// working-set budget per chunk of instances (MiB; 0: the whole group at once)
+constexpr int kChunkMiB[4] = {0, 128, 256, 512};
+constexpr int kBatchTuneSlots = 8 + 4;  // timings per group in nsk_batch_autotune
 
 struct BatchGroup {
   int np = 0;                 // N + 1
@@ -34,6 +36,9 @@ struct BatchGroup {
   int nitems = 0;             // items for the current variant
   int variant = 0;            // elements-per-workgroup variant
   int gridmul = 0;            // grid = CUs * gridmul, 0: one workgroup per item
+  int chunk_mib = 0;          // working-set budget of a chunk of instances, 0: no chunking
+  std::vector<int> chunks;    // item index boundaries of the chunks (first 0, last nitems)
+  std::vector<int> chunk_inst;  // the instance of a one-instance chunk, else -1
 };
 
 }  // namespace
@@ -111,6 +116,35 @@ int upload_tables(nsk_batch* b) {
     }
     g.nitems = (int)items.size();
     if (items.size() > g.cap_items) return NSK_EINVAL;
+    // chunks of whole instances whose working set (state, its copy, the
+    // register and the lifted gradients) stays within the budget: a chunk
+    // runs all the stages of a graph replay back to back while that data
+    // is still in the caches
+    g.chunks.assign(1, 0);
+    g.chunk_inst.clear();
+    const size_t budget = (size_t)g.chunk_mib << 20;
+    size_t acc = 0;
+    int pos = 0, first = -1, count = 0;
+    for (int i : g.inst) {
+      const nsk_ctx* c = b->ctx[i];
+      const size_t gbytes = (size_t)c->S * (3 * sizeof(double) * (size_t)c->nvar +
+                                            (size_t)c->ng * (c->par.precision == 0 ? sizeof(double) : sizeof(float)));
+      const int nblk = (int)((c->E + epb - 1) / epb);
+      if (budget && pos > g.chunks.back() && acc + gbytes > budget) {
+        g.chunks.push_back(pos);
+        g.chunk_inst.push_back(count == 1 ? first : -1);
+        acc = 0;
+        count = 0;
+      }
+      if (count == 0) first = i;
+      ++count;
+      acc += gbytes;
+      pos += nblk;
+    }
+    if (g.chunks.back() != pos) {
+      g.chunks.push_back(pos);
+      g.chunk_inst.push_back(count == 1 ? first : -1);
+    }
     if (hipMemcpyAsync(b->work + g.off_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice,
                        b->stream) != hipSuccess)
       return NSK_EHIP;
@@ -120,62 +154,100 @@ int upload_tables(nsk_batch* b) {
   return NSK_OK;
 }
 
+// one stage of chunk k of group g through the batch kernels (items of the
+// group's elements-per-workgroup variant)
 template <int NP, int EPB, typename R, typename GT>
-int launch_group_e(nsk_batch* b, const BatchGroup& g, int parity, const StageArgs& st) {
+int launch_chunk_e(nsk_batch* b, const BatchGroup& g, int k, int parity, const StageArgs& st) {
   using Tl = Tile<3, NP, EPB>;
-  if (g.nitems == 0) return NSK_OK;
   const BasisArgs bas = basis_args(b->ctx[g.inst[0]]);
   const PhysArgs ph = phys_args(b->ctx[g.inst[0]]);
   const BatchInst* desc = reinterpret_cast<const BatchInst*>(b->work + b->off_desc) + parity * b->ninst;
-  const BatchItem* items = reinterpret_cast<const BatchItem*>(b->work + g.off_items);
+  const BatchItem* items = reinterpret_cast<const BatchItem*>(b->work + g.off_items) + g.chunks[k];
+  const int n = g.chunks[k + 1] - g.chunks[k];
+  if (n <= 0) return NSK_OK;
   if (g.gridmul == 0) {
-    hipLaunchKernelGGL((lift_kernel_batch1<3, NP, EPB, R, GT>), dim3(g.nitems), dim3(Tl::THREADS), 0, b->stream, desc,
-                       items, bas, ph);
-    hipLaunchKernelGGL((rhs_kernel_batch1<3, NP, EPB, R, GT>), dim3(g.nitems), dim3(Tl::THREADS), 0, b->stream, desc,
-                       items, bas, ph, st);
+    hipLaunchKernelGGL((lift_kernel_batch1<3, NP, EPB, R, GT>), dim3(n), dim3(Tl::THREADS), 0, b->stream, desc, items,
+                       bas, ph);
+    hipLaunchKernelGGL((rhs_kernel_batch1<3, NP, EPB, R, GT>), dim3(n), dim3(Tl::THREADS), 0, b->stream, desc, items,
+                       bas, ph, st);
   } else {
-    const int grid = std::min(g.nitems, b->ncu * g.gridmul);
+    const int grid = std::min(n, b->ncu * g.gridmul);
     hipLaunchKernelGGL((lift_kernel_batch<3, NP, EPB, R, GT>), dim3(grid), dim3(Tl::THREADS), 0, b->stream, desc,
-                       items, g.nitems, bas, ph);
+                       items, n, bas, ph);
     hipLaunchKernelGGL((rhs_kernel_batch<3, NP, EPB, R, GT>), dim3(grid), dim3(Tl::THREADS), 0, b->stream, desc,
-                       items, g.nitems, bas, ph, st);
+                       items, n, bas, ph, st);
   }
   return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
 }
 
+// one stage of a one-instance chunk: the single-mesh kernels with the
+// instance's own elements-per-workgroup variant, order and buffers as
+// arguments (no descriptor loads)
+template <int NP, int EPB, typename R, typename GT>
+int launch_single_e(nsk_batch* b, nsk_ctx* c, int parity, const StageArgs& st) {
+  using Tl = Tile<3, NP, EPB>;
+  double* U2 = reinterpret_cast<double*>(c->work + c->off_U2);
+  const double* Uin = parity ? U2 : c->U;
+  double* Uout = parity ? c->U : U2;
+  GT* G = reinterpret_cast<GT*>(c->work + c->off_G);
+  const BasisArgs bas = basis_args(c);
+  const MeshArgs m = mesh_args(c);
+  const PhysArgs ph = phys_args(c);
+  const unsigned blocks = (unsigned)((c->E + EPB - 1) / EPB);
+  hipLaunchKernelGGL((lift_kernel<3, NP, EPB, R, GT>), dim3(blocks), dim3(Tl::THREADS), 0, b->stream, Uin, G, bas, m,
+                     ph);
+  hipLaunchKernelGGL((rhs_kernel<3, NP, EPB, R, GT>), dim3(blocks), dim3(Tl::THREADS), 0, b->stream, Uin, G, Uout,
+                     c->dU, bas, m, ph, st);
+  return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
+}
+
 template <int NP, typename R, typename GT>
-int launch_group_t(nsk_batch* b, const BatchGroup& g, int parity, const StageArgs& st) {
-  if (g.variant == 1 && Epb<3, NP>::V1 != Epb<3, NP>::V0)
-    return launch_group_e<NP, Epb<3, NP>::V1, R, GT>(b, g, parity, st);
-  return launch_group_e<NP, Epb<3, NP>::V0, R, GT>(b, g, parity, st);
+int launch_group_t(nsk_batch* b, const BatchGroup& g, int chunk, int parity, const StageArgs& st) {
+  constexpr bool TWO = Epb<3, NP>::V1 != Epb<3, NP>::V0;
+  for (int k = 0; k + 1 < (int)g.chunks.size(); ++k) {
+    if (chunk >= 0 && chunk != k) continue;
+    int rc;
+    if (g.gridmul == 0 && g.chunk_inst[k] >= 0) {
+      nsk_ctx* c = b->ctx[g.chunk_inst[k]];
+      rc = (TWO && c->tile == 1) ? launch_single_e<NP, Epb<3, NP>::V1, R, GT>(b, c, parity, st)
+                                 : launch_single_e<NP, Epb<3, NP>::V0, R, GT>(b, c, parity, st);
+    } else {
+      rc = (TWO && g.variant == 1) ? launch_chunk_e<NP, Epb<3, NP>::V1, R, GT>(b, g, k, parity, st)
+                                   : launch_chunk_e<NP, Epb<3, NP>::V0, R, GT>(b, g, k, parity, st);
+    }
+    if (rc) return rc;
+  }
+  return NSK_OK;
 }
 
 template <typename R, typename GT>
-int launch_group_p(nsk_batch* b, const BatchGroup& g, int parity, const StageArgs& st) {
+int launch_group_p(nsk_batch* b, const BatchGroup& g, int chunk, int parity, const StageArgs& st) {
   switch (g.np) {
-    case 2: return launch_group_t<2, R, GT>(b, g, parity, st);
-    case 3: return launch_group_t<3, R, GT>(b, g, parity, st);
-    case 4: return launch_group_t<4, R, GT>(b, g, parity, st);
-    case 5: return launch_group_t<5, R, GT>(b, g, parity, st);
-    case 6: return launch_group_t<6, R, GT>(b, g, parity, st);
+    case 2: return launch_group_t<2, R, GT>(b, g, chunk, parity, st);
+    case 3: return launch_group_t<3, R, GT>(b, g, chunk, parity, st);
+    case 4: return launch_group_t<4, R, GT>(b, g, chunk, parity, st);
+    case 5: return launch_group_t<5, R, GT>(b, g, chunk, parity, st);
+    case 6: return launch_group_t<6, R, GT>(b, g, chunk, parity, st);
   }
   return NSK_EUNSUPPORTED;
 }
 
-int launch_group(nsk_batch* b, const BatchGroup& g, int parity, const StageArgs& st) {
-  if (b->par.precision == 0) return launch_group_p<double, double>(b, g, parity, st);
-  return launch_group_p<float, float>(b, g, parity, st);
+// one stage of one chunk of group g (chunk < 0: every chunk of the group)
+int launch_group(nsk_batch* b, const BatchGroup& g, int parity, const StageArgs& st, int chunk = -1) {
+  if (b->par.precision == 0) return launch_group_p<double, double>(b, g, chunk, parity, st);
+  return launch_group_p<float, float>(b, g, chunk, parity, st);
 }
 
-// two full steps: ten stages, parity alternating, state back in U at the end
+// two full steps, chunk by chunk: the ten stages (parity alternating, state
+// back in U at the end) of one chunk of instances run back to back
 int enqueue_two_steps(nsk_batch* b, double dt) {
-  for (int k = 0; k < 10; ++k) {
-    const StageArgs st{kRkA[k % 5], kRkB[k % 5], dt, 1};
-    for (const BatchGroup& g : b->groups) {
-      int rc = launch_group(b, g, k & 1, st);
-      if (rc) return rc;
-    }
-  }
+  for (const BatchGroup& g : b->groups)
+    for (int ch = 0; ch + 1 < (int)g.chunks.size(); ++ch)
+      for (int k = 0; k < 10; ++k) {
+        const StageArgs st{kRkA[k % 5], kRkB[k % 5], dt, 1};
+        int rc = launch_group(b, g, k & 1, st, ch);
+        if (rc) return rc;
+      }
   return NSK_OK;
 }
 
@@ -343,33 +415,19 @@ int nsk_batch_autotune(nsk_batch* b, int reps, double* ms_out) {
   if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return NSK_EHIP; }
   const StageArgs st{0.0, 0.0, 0.0, 0};  // right-hand side into the scratch state buffers
   int rc = NSK_OK;
+  // each instance's own variant and element order (used when it runs as a
+  // chunk of its own)
+  for (nsk_ctx* c : b->ctx) {
+    int v = 0, o = 0;
+    if ((rc = nsk_autotune(c, reps, &v, &o, nullptr)) != NSK_OK) break;
+  }
+  if (rc == NSK_OK) rc = upload_tables(b);
   for (size_t gi = 0; gi < b->groups.size() && rc == NSK_OK; ++gi) {
     BatchGroup& g = b->groups[gi];
-    // element order of the member instances, with the current launch shape
     double best = INFINITY;
-    int bo = b->ctx[g.inst[0]]->order;
-    for (int o = 0; o < kOrders && rc == NSK_OK; ++o) {
-      for (int i : g.inst)
-        if ((rc = upload_order(b->ctx[i], o)) != NSK_OK) break;
-      if (rc || (rc = upload_tables(b)) != NSK_OK) break;
-      float ms = 0.f;
-      if ((rc = launch_group(b, g, 0, st)) != NSK_OK) break;
-      if (hipEventRecord(e0, b->stream) != hipSuccess) { rc = NSK_EHIP; break; }
-      for (int r = 0; r < reps && rc == NSK_OK; ++r) rc = launch_group(b, g, 0, st);
-      if (rc || hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-        if (!rc) rc = NSK_EHIP;
-        break;
-      }
-      const double per = ms / reps;
-      if (ms_out) ms_out[gi * kBatchTuneSlots + 8 + o] = per;
-      if (per < best) { best = per; bo = o; }
-    }
-    for (int i : g.inst)
-      if (rc == NSK_OK) rc = upload_order(b->ctx[i], bo);
-    if (rc) break;
-    // elements per workgroup and grid
-    best = INFINITY;
+    // elements per workgroup and grid of the batch kernels, timed on the
+    // whole group as one chunk
+    g.chunk_mib = 0;
     int bv = g.variant, bm = g.gridmul;
     for (int v = 0; v < kTileVariants && rc == NSK_OK; ++v) {
       g.variant = v;
@@ -393,6 +451,34 @@ int nsk_batch_autotune(nsk_batch* b, int reps, double* ms_out) {
     }
     g.variant = bv;
     g.gridmul = bm;
+    if (rc) break;
+    // chunk budget, with the chosen order and launch shape
+    best = INFINITY;
+    int bc = g.chunk_mib;
+    for (int ci = 0; ci < 4 && rc == NSK_OK; ++ci) {
+      g.chunk_mib = kChunkMiB[ci];
+      if ((rc = upload_tables(b)) != NSK_OK) break;
+      // ten consecutive stages per chunk, as a graph replay runs them
+      auto sweep = [&]() {
+        int r2 = NSK_OK;
+        for (int ch = 0; ch + 1 < (int)g.chunks.size() && r2 == NSK_OK; ++ch)
+          for (int k = 0; k < 10 && r2 == NSK_OK; ++k) r2 = launch_group(b, g, 0, st, ch);
+        return r2;
+      };
+      if ((rc = sweep()) != NSK_OK) break;
+      if (hipEventRecord(e0, b->stream) != hipSuccess) { rc = NSK_EHIP; break; }
+      for (int r = 0; r < reps && rc == NSK_OK; ++r) rc = sweep();
+      float ms = 0.f;
+      if (rc || hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        if (!rc) rc = NSK_EHIP;
+        break;
+      }
+      const double per = ms / (10.0 * reps);  // per stage
+      if (ms_out) ms_out[gi * kBatchTuneSlots + 8 + ci] = per;
+      if (per < best) { best = per; bc = kChunkMiB[ci]; }
+    }
+    g.chunk_mib = bc;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -400,7 +486,26 @@ int nsk_batch_autotune(nsk_batch* b, int reps, double* ms_out) {
   return rc ? rc : rc2;
 }
 
-int nsk_batch_groups(const nsk_batch* b, int* np_out, int* variant_out, int* gridmul_out, int* order_out, int max) {
+int nsk_batch_set_group(nsk_batch* b, int group, int variant, int gridmul, int order, int chunk_mib) {
+  if (!b || group < 0 || group >= (int)b->groups.size()) return NSK_EINVAL;
+  if (variant < 0 || variant >= kTileVariants || order < 0 || order >= kOrders) return NSK_EINVAL;
+  if (gridmul != 0 && gridmul != 2 && gridmul != 4 && gridmul != 8) return NSK_EINVAL;
+  if (chunk_mib < 0) return NSK_EINVAL;
+  if (!b->bound) return NSK_EUNBOUND;
+  BatchGroup& g = b->groups[group];
+  g.variant = variant;
+  g.gridmul = gridmul;
+  g.chunk_mib = chunk_mib;
+  for (int i : g.inst) {
+    b->ctx[i]->tile = variant;
+    int rc = upload_order(b->ctx[i], order);
+    if (rc) return rc;
+  }
+  return upload_tables(b);
+}
+
+int nsk_batch_groups(const nsk_batch* b, int* np_out, int* variant_out, int* gridmul_out, int* order_out,
+                     int* chunk_mib_out, int max) {
   if (!b) return NSK_EINVAL;
   const int n = (int)b->groups.size();
   for (int i = 0; i < n && i < max; ++i) {
@@ -408,6 +513,7 @@ int nsk_batch_groups(const nsk_batch* b, int* np_out, int* variant_out, int* gri
     if (variant_out) variant_out[i] = b->groups[i].variant;
     if (gridmul_out) gridmul_out[i] = b->groups[i].gridmul;
     if (order_out) order_out[i] = b->ctx[b->groups[i].inst[0]]->order;
+    if (chunk_mib_out) chunk_mib_out[i] = b->groups[i].chunk_mib;
   }
   return n;
 }

@@ -117,7 +117,8 @@ def load() -> C.CDLL:
         L.nsk_batch_dt_estimate.argtypes = [vp, C.c_double, dp]
         L.nsk_batch_rk_step.argtypes = [vp, C.c_double, C.c_int]
         L.nsk_batch_autotune.argtypes = [vp, C.c_int, dp]
-        L.nsk_batch_groups.argtypes = [vp, ip, ip, ip, ip, C.c_int]
+        L.nsk_batch_groups.argtypes = [vp, ip, ip, ip, ip, ip, C.c_int]
+        L.nsk_batch_set_group.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
         L.nsk_timing_enable.argtypes = [vp, C.c_int]
         L.nsk_timing_read.argtypes = [vp, dp]
         fp = C.POINTER(C.c_float)
@@ -294,21 +295,25 @@ def nsk_batch_rk_step(b: int, dt: float, nsteps: int) -> None:
     _check("nsk_batch_rk_step", load().nsk_batch_rk_step(b, dt, nsteps))
 
 
-BATCH_TUNE_SLOTS = 14  # timings per group written by nsk_batch_autotune
+BATCH_TUNE_SLOTS = 12  # timings per group written by nsk_batch_autotune
 
 
 def nsk_batch_autotune(b: int, reps: int = 2) -> list:
-    ng = load().nsk_batch_groups(b, None, None, None, None, 0)
+    ng = load().nsk_batch_groups(b, None, None, None, None, None, 0)
     ms = (C.c_double * (BATCH_TUNE_SLOTS * max(ng, 1)))()
     _check("nsk_batch_autotune", load().nsk_batch_autotune(b, reps, ms))
     return list(ms)
 
 
+def nsk_batch_set_group(b: int, group: int, variant: int, gridmul: int, order: int, chunk_mib: int) -> None:
+    _check("nsk_batch_set_group", load().nsk_batch_set_group(b, group, variant, gridmul, order, chunk_mib))
+
+
 def nsk_batch_groups(b: int) -> list:
-    n = load().nsk_batch_groups(b, None, None, None, None, 0)
-    Ns, vs, gm, od = (C.c_int * n)(), (C.c_int * n)(), (C.c_int * n)(), (C.c_int * n)()
-    load().nsk_batch_groups(b, Ns, vs, gm, od, n)
-    return [{"N": Ns[i], "variant": vs[i], "gridmul": gm[i], "order": od[i]} for i in range(n)]
+    n = load().nsk_batch_groups(b, None, None, None, None, None, 0)
+    Ns, vs, gm, od, ch = ((C.c_int * n)() for _ in range(5))
+    load().nsk_batch_groups(b, Ns, vs, gm, od, ch, n)
+    return [{"N": Ns[i], "variant": vs[i], "gridmul": gm[i], "order": od[i], "chunk_mib": ch[i]} for i in range(n)]
 
 
 def nsk_closure_set(ctx: int, d_w: int, norm: dict) -> None:

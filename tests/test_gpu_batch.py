@@ -82,7 +82,8 @@ def test_batch_autotune_and_dt(gpu):
     ms = gpu.nsk_batch_autotune(b.b, 2)
     groups = gpu.nsk_batch_groups(b.b)
     assert sorted(g["N"] for g in groups) == [3, 4, 5]
-    assert all(g["variant"] in (0, 1) and g["gridmul"] in (0, 2, 4, 8) and 0 <= g["order"] < 6 for g in groups)
+    assert all(g["variant"] in (0, 1) and g["gridmul"] in (0, 2, 4, 8) and 0 <= g["order"] < 6
+               and g["chunk_mib"] in (0, 128, 256, 512) for g in groups)
     assert all(x > 0 for x in ms[: gpu.BATCH_TUNE_SLOTS * len(groups)])
     # the autotuner writes only scratch: states are untouched
     for i, U in enumerate(states):
@@ -111,4 +112,32 @@ def test_batch_instance_matches_oracle(O, gpu):
         for v in range(5):
             scale = np.abs(ref[v]).max()
             assert np.abs(got[v] - ref[v]).max() <= 1e-10 * scale, (i, v)
+    b.close()
+
+
+@pytest.mark.parametrize("gridmul", [0, 4])
+def test_batch_chunks_of_instances(gpu, gridmul):
+    """Instances whose working set exceeds the 64 MiB chunk budget run as
+    separate chunks, each through all the stages of a replay; the result
+    must still be the single runs' bits."""
+    meshes = [{"nel": (20, 20, 19), "N": 4, "hi": (1.0, 1.0, 0.95)},
+              {"nel": (19, 20, 20), "N": 4, "hi": (0.95, 1.0, 1.0)},
+              {"nel": (8, 6, 6), "N": 3, "hi": (1.0, 0.75, 0.75)}]
+    states = []
+    for k, m in enumerate(meshes):
+        _, U = I.smooth_random(3, m["N"], m["nel"], seed=200 + k, hi=m["hi"])
+        states.append(U)
+    # working set of the first two instances: (15 + 9) doubles x 0.95M nodes > 64 MiB
+    assert 24 * 8 * 20 * 20 * 19 * 125 > 64 << 20
+    b = gpu.Batch(meshes, precision=0, **PHYS)
+    for i, U in enumerate(states):
+        b.set_state(i, U)
+    groups = gpu.nsk_batch_groups(b.b)
+    for gi, g in enumerate(groups):
+        gpu.nsk_batch_set_group(b.b, gi, 0, gridmul, 3, 64)
+    assert all(g["chunk_mib"] == 64 and g["gridmul"] == gridmul for g in gpu.nsk_batch_groups(b.b))
+    b.rk_step(1e-6, 2)
+    for i, m in enumerate(meshes):
+        ref = _single(gpu, m, states[i], 1e-6, 2, 0)
+        assert np.array_equal(b.get_state(i).cpu().numpy().reshape(ref.shape), ref), i
     b.close()
