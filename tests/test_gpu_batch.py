@@ -141,3 +141,34 @@ def test_batch_chunks_of_instances(gpu, gridmul):
         ref = _single(gpu, m, states[i], 1e-6, 2, 0)
         assert np.array_equal(b.get_state(i).cpu().numpy().reshape(ref.shape), ref), i
     b.close()
+
+
+def test_batched_sweep_full_size_matches_single_runs(gpu):
+    """The 24-instance collision sweep at its full size (159M nodes, N in
+    {3, 4, 5}), mixed precision, autotuned: after one graph replay (two
+    steps) every instance equals its single run bit for bit."""
+    import torch
+
+    sweep = I.batched_sweep()
+    meshes = [{"nel": s["nel"], "N": s["N"], "lo": s["lo"], "hi": s["hi"]} for s in sweep]
+    b = gpu.Batch(meshes, precision=1, **PHYS)
+    init = []
+    for i, s in enumerate(sweep):
+        _, U = I.collision_3d(nel=s["nel"], N=s["N"], We=s["We"], radius=s["radius"], lo=s["lo"], hi=s["hi"],
+                              impact=s["impact"], device="cuda:0")
+        U = U.reshape(-1)
+        init.append(U)
+        b.set_state(i, U)
+    gpu.nsk_batch_autotune(b.b, 1)
+    dt = b.dt_estimate(0.5)
+    b.rk_step(dt, 2)
+    for i, m in enumerate(meshes):
+        s = gpu.Solver(dim=3, N=m["N"], nel=m["nel"], lo=m["lo"], hi=m["hi"], precision=1, **PHYS)
+        s.set_state(init[i])
+        s.rk_step(dt, 2)
+        ref = s.get_state().reshape(-1)
+        got = b.get_state(i)
+        assert torch.isfinite(got).all()
+        assert torch.equal(got, ref), i
+        s.close()
+    b.close()

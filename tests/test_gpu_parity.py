@@ -84,6 +84,22 @@ def test_rhs_parity_config_1d(O, gpu):
     _rhs_check(O, m, U, R, Rc, PHYS["alpha"])
 
 
+@pytest.mark.parametrize("alpha", [500.0, 2000.0])
+def test_rhs_parity_config_2d_full(O, gpu, alpha):
+    """The 2D droplet workload at its full size (96 x 96 elements, N = 4,
+    230,400 nodes): every node of the right-hand side against the oracle,
+    in the launch shape the autotuner picks."""
+    m, U = I.droplets_2d()
+    phys = dict(PHYS, alpha=alpha)
+    s = _solver(gpu, m, **phys)
+    s.set_state(U)
+    gpu.nsk_autotune(s.ctx, 2)
+    R = s.rhs(U).cpu().numpy()
+    Rc = O.rhs(_problem(O, m, **phys), U)
+    _rhs_check(O, m, U, R, Rc, alpha)
+    s.close()
+
+
 def test_trajectory_1d_config(O, gpu):
     """64 elements, N=3, alpha=500: the full 2000-step run."""
     m, U = I.slab_1d()
