@@ -57,6 +57,52 @@ static double sound(const or_prob* P, double r) {
   return sqrt(dp + P->alpha * r);
 }
 
+/* Convective numerical flux (fL, fR: physical fluxes of the two states).
+ * Rusanov: central flux minus lam (uR - uL)/2.  HLLC, written with the
+ * star states of the barotropic system: with the Davis speeds SL, SR and the
+ * HLL averages rho_hll, m_hll (normal momentum) and c_hll, the star state on
+ * side K is (rho_hll, m_hll, rho_hll v_t,K, c_hll); the contact moves with
+ * S* = F_hll[rho] / rho_hll and the flux is F_K + S_K (U*_K - U_K) with K the
+ * side of the contact that holds the face (K = L if S* >= 0). */
+static void convective_numflux(const or_prob* P, int dim, int d, const double* uL, const double* uR,
+                               const double* fL, const double* fR, double* Fc) {
+  const int nv = dim + 2;
+  if (P->flux == 0) {
+    double sL = fabs(uL[1 + d] / uL[0]) + sound(P, uL[0]);
+    double sR = fabs(uR[1 + d] / uR[0]) + sound(P, uR[0]);
+    double lam = sL > sR ? sL : sR;
+    for (int q = 0; q < nv; ++q) {
+      double diss = (q == dim + 1 && !P->diss_c) ? 0.0 : lam * (uR[q] - uL[q]);
+      Fc[q] = 0.5 * (fL[q] + fR[q]) - 0.5 * diss;
+    }
+    return;
+  }
+  double unL = uL[1 + d] / uL[0], unR = uR[1 + d] / uR[0];
+  double SL = unL - sound(P, uL[0]), SR = unR + sound(P, uR[0]);
+  if (unR - sound(P, uR[0]) < SL) SL = unR - sound(P, uR[0]);
+  if (unL + sound(P, uL[0]) > SR) SR = unL + sound(P, uL[0]);
+  if (SL >= 0.0 || SR <= 0.0) {
+    const double* f = SL >= 0.0 ? fL : fR;
+    for (int q = 0; q < nv; ++q) Fc[q] = f[q];
+    return;
+  }
+  /* HLL averages: (SR uR - SL uL - (fR - fL)) / (SR - SL) */
+  double hll[5];
+  for (int q = 0; q < nv; ++q) hll[q] = (SR * uR[q] - SL * uL[q] - (fR[q] - fL[q])) / (SR - SL);
+  /* HLL mass flux and contact speed */
+  double Fmass = fL[0] + SL * (hll[0] - uL[0]);
+  double Sstar = Fmass / hll[0];
+  const double* uK = Sstar >= 0.0 ? uL : uR;
+  const double* fK = Sstar >= 0.0 ? fL : fR;
+  double SK = Sstar >= 0.0 ? SL : SR;
+  double star[5];
+  star[0] = hll[0];
+  for (int j = 0; j < dim; ++j) star[1 + j] = j == d ? hll[1 + d] : hll[0] * uK[1 + j] / uK[0];
+  star[dim + 1] = hll[dim + 1];
+  for (int q = 0; q < nv; ++q) Fc[q] = fK[q] + SK * (star[q] - uK[q]);
+  if (!P->diss_c) Fc[dim + 1] = 0.0;
+}
+
 int or_rhs_strong(const or_prob* P, const double* U, double* R) {
   sgeo g;
   g.dim = P->dim;
@@ -169,9 +215,6 @@ int or_rhs_strong(const or_prob* P, const double* U, double* R) {
                     vL[q] = line_trace(&g, Fv + ((size_t)d * nv + q) * S, E3, I3, d, shL, 1);
                     vR[q] = line_trace(&g, Fv + ((size_t)d * nv + q) * S, E3, I3, d, shR, 0);
                   }
-                  double sL = fabs(uL[1 + d] / uL[0]) + sound(P, uL[0]);
-                  double sR = fabs(uR[1 + d] / uR[0]) + sound(P, uR[0]);
-                  double lam = sL > sR ? sL : sR;
                   double fL[5], fR[5];
                   fL[0] = uL[1 + d];
                   fR[0] = uR[1 + d];
@@ -180,10 +223,9 @@ int or_rhs_strong(const or_prob* P, const double* U, double* R) {
                     fR[1 + jj] = uR[1 + d] * uR[1 + jj] / uR[0] + (jj == d ? pressure_alpha(P, uR[0]) : 0.0);
                   }
                   fL[dim + 1] = fR[dim + 1] = 0.0;
-                  for (int q = 0; q < nv; ++q) {
-                    double diss = (q == dim + 1 && !P->diss_c) ? 0.0 : lam * (uR[q] - uL[q]);
-                    Fstar[side][q] = 0.5 * (fL[q] + fR[q]) - 0.5 * diss - 0.5 * (vL[q] + vR[q]);
-                  }
+                  double Fc[5];
+                  convective_numflux(P, dim, d, uL, uR, fL, fR, Fc);
+                  for (int q = 0; q < nv; ++q) Fstar[side][q] = Fc[q] - 0.5 * (vL[q] + vR[q]);
                 }
                 for (int q = 0; q < nv; ++q) {
                   const double* a = F + ((size_t)d * nv + q) * S;

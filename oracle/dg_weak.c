@@ -6,8 +6,8 @@
  *
  *   J U_t - int F . grad_xi(phi) + surface int (F.n)* phi = J S,
  *
- * with Gauss-Legendre collocation, a local Lax-Friedrichs (Rusanov) flux for
- * the convective part, BR1 lifting of the primitive variables (v, c) with the
+ * with Gauss-Legendre collocation, a local Lax-Friedrichs (Rusanov) or HLLC
+ * flux for the convective part, BR1 lifting of the primitive variables (v, c) with the
  * central flux, the arithmetic mean of the viscous fluxes on faces, and the
  * non-conservative source evaluated pointwise from the lifted gradient of c
  * (end of Sec. 3.1).  It also holds the time loop, the time-step rule and the
@@ -18,7 +18,7 @@
  *   2. BR1 lifting Q_d = dw/dx_d (volume part with Dhat, surface part with the
  *      central trace w* = (w- + w+)/2)
  *   3. nodal fluxes  F_d = Fc_d(U) - Fv_d(Q)
- *   4. face fluxes F*_d = Rusanov(U-, U+) - (Fv_d(Q-) + Fv_d(Q+))/2
+ *   4. face fluxes F*_d = Rusanov or HLLC(U-, U+) - (Fv_d(Q-) + Fv_d(Q+))/2
  *   5. R = sum_d (2/h_d) [Dhat F_d - (L+ F*_+ - L- F*_-)/w] + S
  */
 #include <math.h>
@@ -107,6 +107,63 @@ static double wave_speed(const or_prob* P, int d, const double* u) {
   return fabs(u[1 + d] / rho) + a;
 }
 
+/* Convective numerical flux in direction d.
+ * flux 0, Rusanov: (F(uL) + F(uR))/2 - lam (uR - uL)/2, lam the larger wave
+ *   speed of the two states (on c only if diss_c).
+ * flux 1, HLLC for the barotropic convective part (Toro's HLLC with the
+ *   contact speed taken from the HLL mass flux): Davis speeds
+ *   SL = min(vL - aL, vR - aR), SR = max(vL + aL, vR + aR) (v normal
+ *   velocity, a = sqrt(p_alpha'));  F = F(uL) if SL >= 0, F(uR) if SR <= 0;
+ *   otherwise the HLL flux (SR F(uL) - SL F(uR) + SL SR (uR - uL))/(SR - SL)
+ *   for mass and normal momentum, the mass flux times the tangential
+ *   velocity of the upwind side of the contact S* = F_hll[rho] / rho_hll for
+ *   the tangential momenta, and SL SR (cR - cL)/(SR - SL) for c (0 if not
+ *   diss_c). */
+static void numflux_conv(const or_prob* P, int dim, int d, const double* uL, const double* uR, double* Fs) {
+  const int nvar = dim + 2;
+  double fL[5], fR[5];
+  flux_conv(P, dim, d, uL, fL);
+  flux_conv(P, dim, d, uR, fR);
+  if (P->flux == 0) {
+    double lam = fmax(wave_speed(P, d, uL), wave_speed(P, d, uR));
+    for (int v = 0; v < nvar; ++v) {
+      double diss = (v == nvar - 1 && !P->diss_c) ? 0.0 : lam * (uR[v] - uL[v]);
+      Fs[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * diss;
+    }
+    return;
+  }
+  const double vL = uL[1 + d] / uL[0], vR = uR[1 + d] / uR[0];
+  const double aL = sqrt(or_dp(P->T, uL[0]) + P->alpha * uL[0]);
+  const double aR = sqrt(or_dp(P->T, uR[0]) + P->alpha * uR[0]);
+  const double SL = fmin(vL - aL, vR - aR), SR = fmax(vL + aL, vR + aR);
+  if (SL >= 0.0) {
+    for (int v = 0; v < nvar; ++v) Fs[v] = fL[v];
+    return;
+  }
+  if (SR <= 0.0) {
+    for (int v = 0; v < nvar; ++v) Fs[v] = fR[v];
+    return;
+  }
+  const double w = 1.0 / (SR - SL);
+  const double Fm = (SR * fL[0] - SL * fR[0] + SL * SR * (uR[0] - uL[0])) * w;
+  const double rho_hll = (SR * uR[0] - SL * uL[0] - (fR[0] - fL[0])) * w;
+  const double Sstar = Fm / rho_hll;
+  Fs[0] = Fm;
+  for (int j = 0; j < dim; ++j) {
+    if (j == d)
+      Fs[1 + j] = (SR * fL[1 + j] - SL * fR[1 + j] + SL * SR * (uR[1 + j] - uL[1 + j])) * w;
+    else
+      Fs[1 + j] = Fm * (Sstar >= 0.0 ? uL[1 + j] / uL[0] : uR[1 + j] / uR[0]);
+  }
+  Fs[dim + 1] = P->diss_c ? SL * SR * (uR[dim + 1] - uL[dim + 1]) * w : 0.0;
+}
+
+int or_numflux(const or_prob* P, int d, const double* uL, const double* uR, double* F) {
+  if (!P || P->dim < 1 || P->dim > 3 || d < 0 || d >= P->dim) return -1;
+  numflux_conv(P, P->dim, d, uL, uR, F);
+  return 0;
+}
+
 int or_rhs_weak(const or_prob* P, const double* U, double* R, double* Qout) {
   or_geom g;
   if (or_geom_init(&g, P)) return -1;
@@ -148,21 +205,16 @@ int or_rhs_weak(const or_prob* P, const double* U, double* R, double* Qout) {
     for (long e = 0; e < g.E; ++e) {
       long eR = or_neighbor(&g, e, d, +1);
       for (int f = 0; f < g.nf; ++f) {
-        double uL[5], uR[5], fL[5], fR[5], vL[5], vR[5];
+        double uL[5], uR[5], fL[5], vL[5], vR[5];
         for (int v = 0; v < nvar; ++v) {
           uL[v] = trace(&g, U + v * S, e, d, 1, f);
           uR[v] = trace(&g, U + v * S, eR, d, 0, f);
           vL[v] = trace(&g, Fv + ((size_t)d * nvar + v) * S, e, d, 1, f);
           vR[v] = trace(&g, Fv + ((size_t)d * nvar + v) * S, eR, d, 0, f);
         }
-        flux_conv(P, dim, d, uL, fL);
-        flux_conv(P, dim, d, uR, fR);
-        double lam = fmax(wave_speed(P, d, uL), wave_speed(P, d, uR));
-        for (int v = 0; v < nvar; ++v) {
-          double diss = (v == nvar - 1 && !P->diss_c) ? 0.0 : lam * (uR[v] - uL[v]);
-          Fs[(((size_t)d * nvar + v) * g.E + e) * g.nf + f] =
-              0.5 * (fL[v] + fR[v]) - 0.5 * diss - 0.5 * (vL[v] + vR[v]);
-        }
+        numflux_conv(P, dim, d, uL, uR, fL);
+        for (int v = 0; v < nvar; ++v)
+          Fs[(((size_t)d * nvar + v) * g.E + e) * g.nf + f] = fL[v] - 0.5 * (vL[v] + vR[v]);
       }
     }
   }

@@ -72,7 +72,8 @@ typedef struct {
   double eps;              /* viscosity 1/Re                                  */
   double kappa;            /* eps^2 gamma: coefficient of the Laplacian of c  */
   double alpha, beta;      /* relaxation parameters                           */
-  int diss_c;              /* 1: Rusanov dissipation also on c                */
+  int diss_c;              /* 1: dissipation of the numerical flux also on c  */
+  int flux;                /* 0: Rusanov, 1: HLLC (barotropic form)           */
 } or_prob;
 
 /* Optional forcing added to the right-hand side at time t (manufactured
@@ -87,6 +88,9 @@ int or_nnode(const or_prob* P);
  * Q (optional, may be NULL) receives the lifted gradients, layout
  * Q[d][k][elem][node] with k over (v_1..v_dim, c).  Returns 0 on success. */
 int or_rhs_weak(const or_prob* P, const double* U, double* R, double* Q);
+/* Convective numerical flux of the weak form between the point states uL, uR
+ * (nvar values each) in direction d (for tests). */
+int or_numflux(const or_prob* P, int d, const double* uL, const double* uR, double* F);
 /* The same semi-discretisation written in strong form (independent code). */
 int or_rhs_strong(const or_prob* P, const double* U, double* R);
 

@@ -70,6 +70,7 @@ class _Prob(C.Structure):
         ("alpha", C.c_double),
         ("beta", C.c_double),
         ("diss_c", C.c_int),
+        ("flux", C.c_int),
     ]
 
 
@@ -97,6 +98,7 @@ def _declare(L):
     L.or_dt.restype = C.c_double
     L.or_diagnostics.argtypes = [C.POINTER(_Prob), _dp, _dp]
     L.or_node_coords.argtypes = [C.POINTER(_Prob), _dp]
+    L.or_numflux.argtypes = [C.POINTER(_Prob), C.c_int, _dp, _dp, _dp]
     L.or_gelu.argtypes = [C.c_double]
     L.or_gelu.restype = C.c_double
     L.or_gelu_d.argtypes = [C.c_double]
@@ -219,6 +221,7 @@ class Problem:
     alpha: float = 500.0
     beta: float = 1e-3
     diss_c: int = 1
+    flux: int = 0  # 0: Rusanov, 1: HLLC
     xbreaks: list | None = None  # optional per-direction breakpoints
     _keep: list = field(default_factory=list, repr=False)
 
@@ -254,6 +257,7 @@ class Problem:
                 p.xb[d] = _ptr(xb)
         p.T, p.eps, p.kappa, p.alpha, p.beta = self.T, self.eps, self.kappa, self.alpha, self.beta
         p.diss_c = self.diss_c
+        p.flux = self.flux
         return p
 
 
@@ -274,6 +278,17 @@ def rhs(P: Problem, U, return_Q: bool = False):
         raise RuntimeError("or_rhs_weak failed")
     R = R.reshape(P.shape())
     return (R, Q) if return_Q else R
+
+
+def numflux(P: Problem, d: int, uL, uR) -> np.ndarray:
+    """Convective numerical flux of the weak form between two point states."""
+    uL = np.ascontiguousarray(uL, dtype=np.float64)
+    uR = np.ascontiguousarray(uR, dtype=np.float64)
+    F = np.zeros(P.nvar)
+    pc = P.c()
+    if lib().or_numflux(C.byref(pc), d, _ptr(uL), _ptr(uR), _ptr(F)) != 0:
+        raise RuntimeError("or_numflux failed")
+    return F
 
 
 def rhs_strong(P: Problem, U):

@@ -36,13 +36,14 @@ def _term_scale(O, P, U):
 @pytest.mark.parametrize("dim", [1, 2, 3])
 @pytest.mark.parametrize("N", [1, 3, 5])
 @pytest.mark.parametrize("uniform", [True, False])
-def test_free_stream(O, dim, N, uniform):
+@pytest.mark.parametrize("flux", [0, 1])
+def test_free_stream(O, dim, N, uniform, flux):
     g = np.random.Generator(np.random.PCG64(dim * 10 + N))
     nel = (4, 3, 3)[:dim]
     xb = None if uniform else [np.sort(np.concatenate([[0.0, 1.0], g.uniform(0.05, 0.95, nel[d] - 1)]))
                                for d in range(dim)]
     m = I.Mesh(dim, N, nel, xbreaks=xb)
-    P = _prob(O, m, alpha=500.0, beta=1e-3, eps=1e-3, kappa=1e-5)
+    P = _prob(O, m, alpha=500.0, beta=1e-3, eps=1e-3, kappa=1e-5, flux=flux)
     U = np.zeros(P.shape())
     U[0] = 1.3
     for d in range(dim):
@@ -54,9 +55,13 @@ def test_free_stream(O, dim, N, uniform):
 
 @pytest.mark.parametrize("dim,N,nel", [(1, 3, (9,)), (2, 4, (5, 4)), (3, 2, (3, 4, 3)), (3, 4, (3, 3, 2))])
 @pytest.mark.parametrize("diss_c", [0, 1])
-def test_weak_equals_strong(O, dim, N, nel, diss_c):
+@pytest.mark.parametrize("flux", [0, 1])
+def test_weak_equals_strong(O, dim, N, nel, diss_c, flux):
+    """The weak form writes HLLC as HLL mass/normal-momentum fluxes plus the
+    upwinded tangential momentum; the strong form writes it with star
+    states.  The two are the same flux algebraically."""
     m, U = I.smooth_random(dim, N, nel, seed=dim + N)
-    P = _prob(O, m, alpha=500.0, beta=1e-3, eps=1e-3, kappa=1e-5, diss_c=diss_c)
+    P = _prob(O, m, alpha=500.0, beta=1e-3, eps=1e-3, kappa=1e-5, diss_c=diss_c, flux=flux)
     R = O.rhs(P, U)
     Rs = O.rhs_strong(P, U)
     assert np.abs(R - Rs).max() <= 1e-13 * _term_scale(O, P, U)
@@ -199,10 +204,10 @@ def _mms(dim):
     return sp.lambdify((t,) + X, f, "numpy"), sp.lambdify((t,) + X, [rho] + m + [c], "numpy")
 
 
-def _mms_error(O, dim, N, E, tend):
+def _mms_error(O, dim, N, E, tend, flux=0):
     ff, uu = _mms(dim)
     m = I.Mesh(dim, N, (E,) * dim)
-    P = _prob(O, m, **MMS)
+    P = _prob(O, m, flux=flux, **MMS)
     X = I.node_coords(m)
 
     def ev(fn, t):
@@ -226,6 +231,13 @@ def _mms_error(O, dim, N, E, tend):
 ])
 def test_mms_design_order(O, dim, N, Es):
     errs = [_mms_error(O, dim, N, E, 0.05) for E in Es]
+    eoc = [np.log(errs[i] / errs[i + 1]) / np.log(Es[i + 1] / Es[i]) for i in range(len(errs) - 1)]
+    assert eoc[-1] >= N + 0.5, (errs, eoc)
+
+
+@pytest.mark.parametrize("dim,N,Es", [(1, 3, (4, 8, 16)), (2, 2, (4, 8, 16))])
+def test_mms_design_order_hllc(O, dim, N, Es):
+    errs = [_mms_error(O, dim, N, E, 0.05, flux=1) for E in Es]
     eoc = [np.log(errs[i] / errs[i + 1]) / np.log(Es[i + 1] / Es[i]) for i in range(len(errs) - 1)]
     assert eoc[-1] >= N + 0.5, (errs, eoc)
 
