@@ -136,14 +136,15 @@ def cpu_baseline(name: str, sample, sub, budget_s: float = 20.0):
     }
 
 
-def run_form(nsk, m, U0, w, precision: int, steps: int, warmup: int, tile: str):
-    """Time `steps` LSRK4(5) steps of one precision form from the resident
-    state U0 (torch, device).  Returns timings, the stage-kernel means from
-    HIP events on the bound stream, and the final state (device)."""
+def run_form(nsk, m, U0, w, precision: int, steps: int, warmup: int, tile: str, flux: int = 0):
+    """Time `steps` LSRK4(5) steps of one form (precision, numerical flux)
+    from the resident state U0 (torch, device).  Returns timings, the
+    stage-kernel means from HIP events on the bound stream, and the final
+    state (device)."""
     import torch
 
     s = nsk.Solver(dim=m.dim, N=m.N, nel=tuple(m.nel), lo=tuple(m.lo), hi=tuple(m.hi), alpha=w["alpha"],
-                   beta=1e-3, eps=1e-3, kappa=1e-5, precision=precision)
+                   beta=1e-3, eps=1e-3, kappa=1e-5, precision=precision, flux=flux)
     s.set_state(U0)
     dt = s.dt_estimate(0.5)
     if tile == "auto":
@@ -510,6 +511,21 @@ def main() -> int:
                       "l2_note": f"relative L2 of rho, mixed vs FP64 GPU run, same initial state and dt, "
                                  f"after {args.steps} steps"},
         }
+    if len(forms) == 2:
+        # the HLLC flux (FP64) on the same workload
+        hl = run_form(nsk, m, U0, w, 0, args.steps, args.warmup, args.tile, flux=1)
+        rh = f64["final"][0].reshape(-1)
+        out["forms"]["hllc_fp64"] = {
+            "value": dofs * 5 * args.steps / (hl["ms"] * 1e-3), "ms_per_step": hl["ms"] / args.steps,
+            "rhs_ms": hl["ms_rhs"], "lift_ms": hl["ms_lift"],
+            "roofline_frac": dofs * (bytes_per_node(m.dim, True, False)["rhs"]
+                                     + 4 * bytes_per_node(m.dim, False, False)["rhs"]) / 5.0
+                             / (hl["ms_rhs"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "l2_rel_rho_vs_rusanov": float(torch.linalg.vector_norm(hl["final"][0].reshape(-1) - rh)
+                                           / torch.linalg.vector_norm(rh)),
+            "tile": {"variant": hl["variant"], "order": hl["order"]},
+        }
+        del hl
     del forms
     if not args.no_forms and not args.no_batched and args.workload == "3d-collision":
         out.setdefault("forms", {})["batched"] = run_batched(nsk, 10, 2)

@@ -12,7 +12,7 @@
  * (Sec. 2.1), tau = eps (grad v + grad v^T - 2/3 div v I) and
  * kappa = eps^2 gamma (the coefficient of the Laplacian of c).
  * The discretisation (Sec. 3.1): DGSEM on Gauss-Legendre nodes, weak form,
- * Rusanov (local Lax-Friedrichs) convective flux, BR1 lifting of the
+ * Rusanov (local Lax-Friedrichs) or HLLC convective flux, BR1 lifting of the
  * primitive variables (v, c) with central fluxes, arithmetic mean of the
  * viscous face fluxes, pointwise non-conservative source from the lifted
  * gradient of c, and the five-stage fourth-order 2N-storage Runge-Kutta
@@ -70,8 +70,8 @@ typedef struct {
   double kappa;   /* eps^2 gamma, coefficient of the Laplacian of c         */
   double alpha;   /* relaxation parameter, > 6 (1 - T) (hyperbolicity)     */
   double beta;    /* parabolic relaxation parameter (> 0)                   */
-  int flux;       /* 0 = Rusanov (the only flux built)                      */
-  int diss_c;     /* 1 = Rusanov dissipation also on c, 0 = not on c        */
+  int flux;       /* 0 = Rusanov, 1 = HLLC (barotropic form)                */
+  int diss_c;     /* 1 = numerical-flux dissipation also on c, 0 = not on c */
   int precision;  /* 0 = FP64 throughout; 1 = mixed (FP32 volume/surface)   */
   int closure;    /* 1: add the learned closure source (nsk_closure_set)   */
 } nsk_params;
@@ -271,9 +271,9 @@ int nsk_mlp_moments(const float* d_Y, long long n, int ncol, void* d_ws, double*
  * ------------------------------------------------------------------------ */
 typedef struct nsk_batch nsk_batch;
 
-/* meshes[0..ninst-1] must all be 3D and params->closure 0 (NSK_EUNSUPPORTED
- * otherwise); the validation rules of nsk_create apply per instance.  Host
- * only. */
+/* meshes[0..ninst-1] must all be 3D, params->closure 0 and params->flux 0
+ * (Rusanov) (NSK_EUNSUPPORTED otherwise); the validation rules of
+ * nsk_create apply per instance.  Host only. */
 int nsk_batch_create(const nsk_mesh* meshes, int ninst, const nsk_params* params, nsk_batch** out);
 
 /* Frees the batch and its instance contexts (waits for the bound stream). */

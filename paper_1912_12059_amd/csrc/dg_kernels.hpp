@@ -102,7 +102,8 @@ struct PhysArgs {
   double T, eps, kappa, alpha, beta;
   double kb;         // kappa / beta
   double ab;         // alpha / beta
-  int diss_c;        // Rusanov dissipation on c
+  int diss_c;        // numerical-flux dissipation on c
+  int flux;          // 0: Rusanov, 1: HLLC
   double rho_lo64, rho_hi64;  // mixed precision: FP64 EoS inside this band
 };
 
@@ -370,7 +371,7 @@ __device__ __forceinline__ void lift_block(int L, int tid, const double* __restr
 // and S = (0, alpha rho grad c, (alpha/beta)(rho - c)); then
 //   dU <- A dU + dt R,  U <- U + B dU.
 // -------------------------------------------------------------------------
-template <int DIM, int NP, int EPB, typename R, typename GT>
+template <int DIM, int NP, int EPB, typename R, typename GT, int FLUX = 0>
 __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restrict__ U, const GT* __restrict__ G,
                                           double* __restrict__ Uout, double* __restrict__ dU, const BasisArgs& bas,
                                           const MeshArgs& msh, const PhysArgs& ph, const StageArgs& st) {
@@ -439,7 +440,7 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
   // per SIMD whatever its register count, so the next direction's values
   // are fetched while the current one is computed; the mixed-precision
   // kernel (3 waves per SIMD) fetches them when it stages them.
-  constexpr bool PREFETCH = !MIXED;
+  constexpr bool PREFETCH = !MIXED && FLUX == 0;  // the HLLC face code needs the registers
   double nbv[2][NX];
   auto fetch_nb = [&](auto dc) {
     constexpr int dd = decltype(dc)::value;
@@ -526,16 +527,51 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
         p_alpha_sound_guarded<R>(rL, ph, paL, aL);
         p_alpha_sound_guarded<R>(rR, ph, paR, aR);
         const R irL = R(1) / uL[0], irR = R(1) / uR[0];
-        const R sL = fabs(uL[1 + d] * irL) + aL;
-        const R sR = fabs(uR[1 + d] * irR) + aR;
-        const R lam = sL > sR ? sL : sR;
-        R FL[NV], FR[NV];
+        R FL[NV], FR[NV], Fc[NV];
         conv_flux<DIM, R>(d, uL, irL, paL, FL);
         conv_flux<DIM, R>(d, uR, irR, paR, FR);
+        if constexpr (FLUX == 0) {
+          // Rusanov: central flux minus the larger wave speed times the jump
+          const R sL = fabs(uL[1 + d] * irL) + aL;
+          const R sR = fabs(uR[1 + d] * irR) + aR;
+          const R lam = sL > sR ? sL : sR;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const R diss = (v == NV - 1 && !ph.diss_c) ? R(0) : lam * (uR[v] - uL[v]);
+            Fc[v] = R(0.5) * (FL[v] + FR[v]) - R(0.5) * diss;
+          }
+        } else {
+          // HLLC of the barotropic convective part: Davis speeds; HLL flux for
+          // mass and normal momentum; tangential momenta carried by the mass
+          // flux with the velocity of the upwind side of the contact
+          // S* = F_hll[rho] / rho_hll; HLL dissipation alone on c
+          const R vnL = uL[1 + d] * irL, vnR = uR[1 + d] * irR;
+          const R SL = fmin(vnL - aL, vnR - aR), SR = fmax(vnL + aL, vnR + aR);
+          if (SL >= R(0)) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Fc[v] = FL[v];
+          } else if (SR <= R(0)) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Fc[v] = FR[v];
+          } else {
+            const R w = R(1) / (SR - SL);
+            const R Fm = (SR * FL[0] - SL * FR[0] + SL * SR * (uR[0] - uL[0])) * w;
+            const R rh = (SR * uR[0] - SL * uL[0] - (FR[0] - FL[0])) * w;
+            const bool left = Fm / rh >= R(0);
+            Fc[0] = Fm;
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) {
+              if (j == d)
+                Fc[1 + j] = (SR * FL[1 + j] - SL * FR[1 + j] + SL * SR * (uR[1 + j] - uL[1 + j])) * w;
+              else
+                Fc[1 + j] = Fm * (left ? uL[1 + j] * irL : uR[1 + j] * irR);
+            }
+            Fc[NV - 1] = ph.diss_c ? SL * SR * (uR[NV - 1] - uL[NV - 1]) * w : R(0);
+          }
+        }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          const R diss = (v == NV - 1 && !ph.diss_c) ? R(0) : lam * (uR[v] - uL[v]);
-          R Fs = R(0.5) * (FL[v] + FR[v]) - R(0.5) * diss;
+          R Fs = Fc[v];
           if (v >= 1 && v <= DIM) Fs -= R(0.5) * (vL[v - 1] + vR[v - 1]);
           if (v == NV - 1) Fs -= R(0.5) * kb * (vL[DIM] + vR[DIM]);
           sFs[le][s][v][f] = Fs;
@@ -601,12 +637,12 @@ lift_kernel(const double* __restrict__ U, GT* __restrict__ G, BasisArgs bas, Mes
   lift_block<DIM, NP, EPB, R, GT>(remap_block(blockIdx.x, gridDim.x, msh.nxcd), threadIdx.x, U, G, bas, msh, ph);
 }
 
-template <int DIM, int NP, int EPB, typename R, typename GT>
+template <int DIM, int NP, int EPB, typename R, typename GT, int FLUX = 0>
 __global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
 rhs_kernel(const double* __restrict__ U, const GT* __restrict__ G, double* __restrict__ Uout,
            double* __restrict__ dU, BasisArgs bas, MeshArgs msh, PhysArgs ph, StageArgs st) {
-  rhs_block<DIM, NP, EPB, R, GT>(remap_block(blockIdx.x, gridDim.x, msh.nxcd), threadIdx.x, U, G, Uout, dU, bas, msh,
-                                 ph, st);
+  rhs_block<DIM, NP, EPB, R, GT, FLUX>(remap_block(blockIdx.x, gridDim.x, msh.nxcd), threadIdx.x, U, G, Uout, dU, bas,
+                                       msh, ph, st);
 }
 
 // -------------------------------------------------------------------------

@@ -174,7 +174,7 @@ int check_params(const nsk_params* p) {
   // model II is hyperbolic only for alpha > -min W''(rho) = 6 (1 - T), the
   // minimum of the reduced Van-der-Waals W'' being taken at rho = 1
   if (!(p->alpha > 6.0 * (1.0 - p->T))) return NSK_EINVAL;
-  if (p->flux != 0 || (p->closure != 0 && p->closure != 1)) return NSK_EINVAL;
+  if ((p->flux != 0 && p->flux != 1) || (p->closure != 0 && p->closure != 1)) return NSK_EINVAL;
   if (p->precision != 0 && p->precision != 1) return NSK_EINVAL;
   if (p->diss_c != 0 && p->diss_c != 1) return NSK_EINVAL;
   return NSK_OK;
@@ -265,6 +265,7 @@ PhysArgs phys_args(const nsk_ctx* c) {
   p.kb = c->par.kappa / c->par.beta;
   p.ab = c->par.alpha / c->par.beta;
   p.diss_c = c->par.diss_c;
+  p.flux = c->par.flux;
   p.rho_lo64 = c->rho_lo64;
   p.rho_hi64 = c->rho_hi64;
   return p;

@@ -66,8 +66,12 @@ int launch_stage_e(nsk_ctx* c, const double* Uin, double* Uout, double* dU, cons
     sta.closure = Sc;
   }
   if (ev) (void)hipEventRecord(ev[2], c->stream);
-  hipLaunchKernelGGL((rhs_kernel<DIM, NP, EPB, R, GT>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream, Uin, G, Uout,
-                     dU, b, m, p, sta);
+  if (c->par.flux == 1)
+    hipLaunchKernelGGL((rhs_kernel<DIM, NP, EPB, R, GT, 1>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream, Uin, G,
+                       Uout, dU, b, m, p, sta);
+  else
+    hipLaunchKernelGGL((rhs_kernel<DIM, NP, EPB, R, GT, 0>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream, Uin, G,
+                       Uout, dU, b, m, p, sta);
   if (ev) (void)hipEventRecord(ev[3], c->stream);
   return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
 }

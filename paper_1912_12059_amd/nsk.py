@@ -375,6 +375,7 @@ class Solver:
     beta: float = 1e-3
     diss_c: int = 1
     precision: int = 0
+    flux: int = 0
     closure: int = 0
     xbreaks: list | None = None
     device: str = "cuda:0"
@@ -386,7 +387,7 @@ class Solver:
 
         mesh, keep = make_mesh(self.dim, self.N, self.nel, self.lo, self.hi, self.xbreaks)
         params = make_params(self.T, self.eps, self.kappa, self.alpha, self.beta, self.diss_c, self.precision,
-                             closure=self.closure)
+                             flux=self.flux, closure=self.closure)
         self.ctx = nsk_create(mesh, params)
         del keep
         n = nsk_state_size(self.ctx)

@@ -66,7 +66,7 @@ def test_create_rejects_bad_mesh(bad):
 
 @pytest.mark.parametrize("bad", [
     dict(T=0.0), dict(T=1.0), dict(alpha=0.0), dict(alpha=0.9), dict(T=0.5, alpha=2.9), dict(beta=0.0), dict(beta=-1.0), dict(eps=-1e-3),
-    dict(kappa=-1.0), dict(precision=2), dict(flux=1), dict(closure=2), dict(diss_c=2),
+    dict(kappa=-1.0), dict(precision=2), dict(flux=2), dict(closure=2), dict(diss_c=2),
     dict(alpha=float("nan")),
 ])
 def test_create_rejects_bad_params(bad):

@@ -1,0 +1,81 @@
+"""HLLC flux (flux = 1) on the GPU against the FP64 oracle: right-hand side
+within the round-off bound of the Rusanov tests (the HLLC flux is
+continuous where it switches branches, so different rounding on the two
+sides cannot open a gap), trajectories, launch-shape independence and the
+mixed-precision form."""
+import numpy as np
+import pytest
+
+from paper_1912_12059_amd import inputs as I
+from test_gpu_parity import PHYS, TRAJ_TOL, _problem, _relerr_per_var, _rhs_check, _solver
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dim,N,nel", [(1, 3, (9,)), (2, 4, (7, 5)), (3, 3, (4, 3, 5)), (3, 4, (3, 4, 3))])
+@pytest.mark.parametrize("diss_c", [0, 1])
+def test_hllc_rhs_parity(O, gpu, dim, N, nel, diss_c):
+    m, U = I.smooth_random(dim, N, nel, seed=70 + dim + N, vmax=0.5)
+    phys = dict(PHYS, diss_c=diss_c)
+    s = _solver(gpu, m, flux=1, **phys)
+    R = s.rhs(U).cpu().numpy()
+    Rc = O.rhs(_problem(O, m, flux=1, **phys), U)
+    _rhs_check(O, m, U, R, Rc, PHYS["alpha"])
+    s.close()
+
+
+def test_hllc_rhs_parity_collision(O, gpu):
+    """Moving droplets: contacts with both signs of S* inside the interfaces."""
+    m, U = I.collision_3d(nel=(12, 6, 6), N=4, We=100.0, hi=(2.0, 1.0, 1.0), impact=0.1)
+    phys = dict(PHYS, alpha=1000.0)
+    s = _solver(gpu, m, flux=1, **phys)
+    R = s.rhs(U).cpu().numpy()
+    Rc = O.rhs(_problem(O, m, flux=1, **phys), U)
+    _rhs_check(O, m, U, R, Rc, phys["alpha"])
+    s.close()
+
+
+def test_hllc_trajectory_1d_config(O, gpu):
+    m, U = I.slab_1d()
+    s = _solver(gpu, m, flux=1, **PHYS)
+    s.set_state(U)
+    dt = s.dt_estimate(0.5)
+    s.rk_step(dt, 500)
+    got = s.get_state().cpu().numpy()
+    ref = O.run(_problem(O, m, flux=1, **PHYS), U, dt, 500)
+    assert _relerr_per_var(got, ref) <= TRAJ_TOL
+    s.close()
+
+
+@pytest.mark.parametrize("dim,N,nel", [(2, 4, (13, 11)), (3, 4, (5, 5, 3))])
+def test_hllc_launch_shapes_bitwise_identical(gpu, dim, N, nel):
+    m, U = I.smooth_random(dim, N, nel, seed=90 + N)
+    outs = []
+    for variant in (0, 1):
+        for order in (0, 2, 5):
+            s = _solver(gpu, m, flux=1, **PHYS)
+            gpu.nsk_set_tile(s.ctx, variant, order)
+            s.set_state(U)
+            s.rk_step(1e-6, 3)
+            outs.append(s.get_state().cpu().numpy())
+            s.close()
+    assert np.all(np.isfinite(outs[0]))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_hllc_mixed_precision(O, gpu):
+    """Mixed precision with HLLC: 100 steps of a small collision against the
+    FP64 oracle, the bound of the Rusanov mixed test."""
+    m, U = I.collision_3d(nel=(12, 6, 6), N=4, We=100.0, hi=(2.0, 1.0, 1.0))
+    phys = dict(PHYS, alpha=1000.0)
+    s = _solver(gpu, m, flux=1, precision=1, **phys)
+    s.set_state(U)
+    dt = s.dt_estimate(0.5)
+    s.rk_step(dt, 100)
+    got = s.get_state().cpu().numpy()
+    ref = O.run(_problem(O, m, flux=1, **phys), U, dt, 100)
+    rel = np.linalg.norm(got[0] - ref[0]) / np.linalg.norm(ref[0])
+    print(f"\nHLLC mixed vs FP64 oracle, rel L2(rho) after 100 steps: {rel:.3e}")
+    assert rel <= 1e-6
+    s.close()
