@@ -206,12 +206,15 @@ typedef struct {
 /* Sets the network of a context created with params.closure = 1.  d_w_bf16
  * is a device pointer to NSK_MLP_NPARAM BF16 values that the caller keeps
  * valid and unchanged while the context steps (it is read, not copied).
- * Each stage then runs one closure kernel (features + network, FP32 result
- * in the workspace) before the right-hand-side kernel, which adds the source
- * in FP64.  NSK_EINVAL if the context has closure = 0, an argument is NULL,
+ * A closure kernel (features + network, FP32 result in the workspace) then
+ * runs before the right-hand-side kernel, which adds the source in FP64:
+ * in every stage (every_stage = 1), or in the first stage of each
+ * nsk_rk_step step only, its source serving the step's five stages
+ * (every_stage = 0; nsk_rhs always evaluates it).  NSK_EINVAL if the
+ * context has closure = 0, an argument is NULL, every_stage is not 0 or 1,
  * a scale is not finite or g0 <= 0.  nsk_rhs, nsk_rk_step and nsk_autotune
  * of a closure context return NSK_EINVAL until a network is set.  Host only. */
-int nsk_closure_set(nsk_ctx* ctx, const uint16_t* d_w_bf16, const nsk_closure_norm* norm);
+int nsk_closure_set(nsk_ctx* ctx, const uint16_t* d_w_bf16, const nsk_closure_norm* norm, int every_stage);
 
 /* One nudging step on the bound state of any context (training pairs):
  * with the reference state d_Uref (layout of the state, device) mapped into

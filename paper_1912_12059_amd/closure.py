@@ -205,9 +205,10 @@ def nudged_pairs(mesh: dict, U0, alpha_ref: float, alpha: float, kappa: float, t
     return X, Y, info
 
 
-def closure_solver(net: Network, norm: dict, **kw) -> "nsk.Solver":
-    """A Solver with the closure switched on and this network set."""
+def closure_solver(net: Network, norm: dict, every_stage: int = 1, **kw) -> "nsk.Solver":
+    """A Solver with the closure switched on and this network set, evaluated
+    in every stage or once per step (every_stage = 0)."""
     s = nsk.Solver(closure=1, **kw)
-    nsk.nsk_closure_set(s.ctx, net.w_ptr, norm)
+    nsk.nsk_closure_set(s.ctx, net.w_ptr, norm, every_stage)
     s._closure_net = net  # keep the parameters alive while the solver steps
     return s

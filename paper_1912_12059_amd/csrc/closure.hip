@@ -311,9 +311,10 @@ int launch_nudge_np(nsk_ctx* c, const ClosureArgs& ca, const double* Ur, double 
 
 extern "C" {
 
-int nsk_closure_set(nsk_ctx* c, const uint16_t* d_w_bf16, const nsk_closure_norm* norm) {
-  if (!c || !d_w_bf16 || !norm) return NSK_EINVAL;
+int nsk_closure_set(nsk_ctx* c, const uint16_t* d_w_bf16, const nsk_closure_norm* norm, int every_stage) {
+  if (!c || !d_w_bf16 || !norm || (every_stage != 0 && every_stage != 1)) return NSK_EINVAL;
   if (c->par.closure != 1 || !norm_ok(norm)) return NSK_EINVAL;
+  c->cl_every_stage = every_stage;
   const float q[9] = {norm->s0, norm->k0, norm->s1, norm->k1, norm->k2, norm->k3, norm->g0, norm->out_m, norm->out_c};
   std::memcpy(c->cl_norm, q, sizeof(q));
   c->cl_w = d_w_bf16;

@@ -158,6 +158,8 @@ struct nsk_ctx {
   // learned closure: caller-owned BF16 parameters and the feature/output scaling
   const uint16_t* cl_w = nullptr;
   float cl_norm[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  int cl_every_stage = 1;  // 0: the closure source of a step's first stage serves all five
+  int cl_stage = 0;        // stage index within the step being enqueued (0..4), -1 outside a step
   // optional kernel timing
   std::vector<hipEvent_t> events;  // 4 per timed stage
   int timed = 0;                   // stages recorded since the last read

@@ -58,11 +58,15 @@ int launch_stage_e(nsk_ctx* c, const double* Uin, double* Uout, double* dU, cons
   if (ev) (void)hipEventRecord(ev[1], c->stream);
   StageArgs sta = st;
   if (c->par.closure == 1) {
+    // the source of the step's first stage is reused in the later stages
+    // when the context evaluates the closure once per step
+    const bool fresh = c->cl_every_stage || c->cl_stage <= 0;
     using CS = ClosureShape<DIM, NP>;
     float* Sc = reinterpret_cast<float*>(c->work + c->off_cl);
     const unsigned cblocks = (unsigned)((c->E + CS::EPB - 1) / CS::EPB);
-    hipLaunchKernelGGL((closure_kernel<DIM, NP>), dim3(cblocks), dim3(kClosureThreads), 0, c->stream, Uin, Sc,
-                       mesh_args(c), closure_args_of(c));
+    if (fresh)
+      hipLaunchKernelGGL((closure_kernel<DIM, NP>), dim3(cblocks), dim3(kClosureThreads), 0, c->stream, Uin, Sc,
+                         mesh_args(c), closure_args_of(c));
     sta.closure = Sc;
   }
   if (ev) (void)hipEventRecord(ev[2], c->stream);
@@ -365,7 +369,9 @@ int nsk_rk_step(nsk_ctx* c, double dt, int nsteps) {
   for (int step = 0; step < nsteps; ++step) {
     for (int s = 0; s < 5; ++s) {
       StageArgs st{kRkA[s], kRkB[s], dt, 1};
+      c->cl_stage = s;
       int rc = dispatch(c, 0, state_buf(c, c->cur), state_buf(c, 1 - c->cur), c->dU, st);
+      c->cl_stage = -1;
       if (rc) return rc;
       c->cur = 1 - c->cur;
     }

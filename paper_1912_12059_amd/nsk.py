@@ -122,7 +122,7 @@ def load() -> C.CDLL:
         L.nsk_timing_enable.argtypes = [vp, C.c_int]
         L.nsk_timing_read.argtypes = [vp, dp]
         fp = C.POINTER(C.c_float)
-        L.nsk_closure_set.argtypes = [vp, vp, C.POINTER(nsk_closure_norm)]
+        L.nsk_closure_set.argtypes = [vp, vp, C.POINTER(nsk_closure_norm), C.c_int]
         L.nsk_closure_nudge.argtypes = [vp, C.POINTER(nsk_closure_norm), vp, C.c_double, C.c_double, C.c_double, vp,
                                         vp]
         L.nsk_mlp_forward.argtypes = [vp, vp, C.c_longlong, vp, vp]
@@ -316,9 +316,9 @@ def nsk_batch_groups(b: int) -> list:
     return [{"N": Ns[i], "variant": vs[i], "gridmul": gm[i], "order": od[i], "chunk_mib": ch[i]} for i in range(n)]
 
 
-def nsk_closure_set(ctx: int, d_w: int, norm: dict) -> None:
+def nsk_closure_set(ctx: int, d_w: int, norm: dict, every_stage: int = 1) -> None:
     nm = _norm_struct(norm)
-    _check("nsk_closure_set", load().nsk_closure_set(ctx, d_w, C.byref(nm)))
+    _check("nsk_closure_set", load().nsk_closure_set(ctx, d_w, C.byref(nm), every_stage))
 
 
 def _norm_struct(norm: dict) -> nsk_closure_norm:

@@ -125,6 +125,8 @@ def test_closure_host_side_checks():
             nsk.nsk_closure_set(cl, fake, dict(norm, g0=0.0))
         with pytest.raises(nsk.NskError):
             nsk.nsk_closure_set(cl, fake, dict(norm, k2=float("inf")))
+        with pytest.raises(nsk.NskError):
+            nsk.nsk_closure_set(cl, fake, norm, 2)  # every_stage must be 0 or 1
         with pytest.raises(nsk.NskError) as e:
             nsk.nsk_closure_nudge(cl, norm, fake, 1e-6, 1e-4, 10.0, 0, 0)
         assert e.value.code == nsk.NSK_EUNBOUND

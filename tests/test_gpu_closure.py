@@ -183,6 +183,42 @@ def test_closure_source_in_rhs(O, gpu, dim, N, nel):
     cl.close()
 
 
+def test_closure_once_per_step(gpu):
+    """With a source that does not depend on the state (c output only,
+    constant), evaluating the closure once per step must give the bits of
+    evaluating it in every stage; with a state-dependent network the two
+    modes differ."""
+    from paper_1912_12059_amd import closure as CL
+    from paper_1912_12059_amd import inputs as I
+
+    _, U = I.smooth_random(2, 4, (6, 5), seed=31)
+    phys = dict(dim=2, N=4, nel=(6, 5), alpha=200.0, kappa=1e-4)
+    w = CL.init_params(seed=9)
+    o4 = NPARAM - 2 - 128
+    w[o4:o4 + 128] = 0.0              # W4 = 0
+    w[NPARAM - 2:] = (0.0, 0.75)      # b4: no momentum source, constant c source
+    outs = {}
+    for mode in (1, 0):
+        net = _net(gpu, w)
+        s = CL.closure_solver(net, NORM, every_stage=mode, **phys)
+        s.set_state(U)
+        s.rk_step(2e-6, 3)
+        outs[mode] = s.get_state().cpu().numpy()
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
+    w2 = CL.init_params(seed=9)
+    w2[np.arange(NPARAM) % 7 == 0] += 0.05
+    res = {}
+    for mode in (1, 0):
+        net = _net(gpu, w2)
+        s = CL.closure_solver(net, NORM, every_stage=mode, **phys)
+        s.set_state(U)
+        s.rk_step(2e-6, 3)
+        res[mode] = s.get_state().cpu().numpy()
+        s.close()
+    assert np.all(np.isfinite(res[0])) and not np.array_equal(res[0], res[1])
+
+
 def test_closure_guards(gpu):
     import torch
 
@@ -247,15 +283,21 @@ def test_trained_closure_gains_over_plain_alpha200(gpu):
     cl.set_state(U0)
     cl.rk_step(M * dt_ref, nst)
     Uc = cl.get_state().cpu().numpy()
+    cl.close()
+    cl1 = CL.closure_solver(net, norm, every_stage=0, alpha=200.0, kappa=kappa, **mesh)
+    cl1.set_state(U0)
+    cl1.rk_step(M * dt_ref, nst)
+    Uc1 = cl1.get_state().cpu().numpy()
+    cl1.close()
     U0h = U0.cpu().numpy().reshape(Ur.shape)
     change = np.linalg.norm(Ur[0] - U0h[0])
 
     def err(U):
         return np.linalg.norm(U[0] - Ur[0]) / change, np.linalg.norm(U[1:3] - Ur[1:3]) / np.linalg.norm(Ur[1:3])
 
-    ep, ec = err(Up), err(Uc)
-    print(f"\nrho error / change: plain {ep[0]:.3e} closure {ec[0]:.3e};  momentum: plain {ep[1]:.3e} "
-          f"closure {ec[1]:.3e}")
-    assert np.all(np.isfinite(Uc))
-    assert ec[0] < 0.8 * ep[0]
-    assert ec[1] < ep[1]
+    ep, ec, ec1 = err(Up), err(Uc), err(Uc1)
+    print(f"\nrho error / change: plain {ep[0]:.3e} closure {ec[0]:.3e} (once per step {ec1[0]:.3e});  "
+          f"momentum: plain {ep[1]:.3e} closure {ec[1]:.3e} (once per step {ec1[1]:.3e})")
+    assert np.all(np.isfinite(Uc)) and np.all(np.isfinite(Uc1))
+    assert ec[0] < 0.8 * ep[0] and ec1[0] < 0.8 * ep[0]
+    assert ec[1] < ep[1] and ec1[1] < ep[1]
