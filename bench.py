@@ -262,6 +262,63 @@ def run_batched(nsk, steps: int, warmup: int):
     }
 
 
+def run_batched_small(nsk, steps: int = 20, n: int = 64):
+    """Launch-bound case beside the sweep: n small collisions (8x8x8
+    elements, N = 3, 32,768 nodes each) in mixed precision, batched (one
+    graph replay per two steps) against the same instances run one after
+    another."""
+    import torch
+
+    from paper_1912_12059_amd import inputs as I
+
+    mesh = {"nel": (8, 8, 8), "N": 3, "lo": (0.0, 0.0, 0.0), "hi": (1.0, 1.0, 1.0)}
+    meshes = [dict(mesh) for _ in range(n)]
+    init = []
+    for i in range(n):
+        _, U = I.collision_3d(nel=(8, 8, 8), N=3, We=5.0 + 2.0 * i, radius=0.1, hi=(1.0, 1.0, 1.0),
+                              impact=0.001 * i, device="cuda:0")
+        init.append(U.reshape(-1))
+    dofs = init[0].numel() // 5
+    b = nsk.Batch(meshes, alpha=1000.0, beta=1e-3, eps=1e-3, kappa=1e-5, precision=1)
+    for i, u in enumerate(init):
+        b.set_state(i, u)
+    dt = b.dt_estimate(0.5)
+    nsk.nsk_batch_autotune(b.b, 2)
+    b.rk_step(dt, 2)
+    for i, u in enumerate(init):
+        b.set_state(i, u)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(b.stream)
+    b.rk_step(dt, steps)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1)
+    b.close()
+    solvers = [nsk.Solver(dim=3, N=3, nel=(8, 8, 8), alpha=1000.0, beta=1e-3, eps=1e-3, kappa=1e-5, precision=1)
+               for _ in range(n)]
+    for s, u in zip(solvers, init):
+        s.set_state(u)
+        nsk.nsk_autotune(s.ctx, 2)
+        s.set_state(u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for s in solvers:
+        s.rk_step(dt, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_s = e0.elapsed_time(e1)
+    wall_s = (time.perf_counter() - t0) * 1e3
+    for s in solvers:
+        s.close()
+    work = n * dofs * 5 * steps
+    return {"instances": n, "mesh": "8x8x8 N=3", "dofs": n * dofs, "steps": steps,
+            "value": work / (ms_b * 1e-3), "unit": "DOF-stage/s",
+            "sequential_value": work / (ms_s * 1e-3), "speedup_vs_sequential": ms_s / ms_b,
+            "sequential_host_ms": wall_s}
+
+
 def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20):
     """Closure form, kappa = 1e-4 (interface width 2 sqrt(kappa) = 0.02).
     A network is trained here, from seeded initial weights, on nudged
@@ -558,6 +615,7 @@ def main() -> int:
     del forms
     if not args.no_forms and not args.no_batched and args.workload == "3d-collision":
         out.setdefault("forms", {})["batched"] = run_batched(nsk, 10, 2)
+        out["forms"]["batched_small"] = run_batched_small(nsk)
     if not args.no_forms and not args.no_closure and args.workload == "3d-collision":
         out.setdefault("forms", {})["closure"] = run_closure_form(nsk)
     if not args.no_cpu_baseline:
