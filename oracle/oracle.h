@@ -110,6 +110,19 @@ int or_diagnostics(const or_prob* P, const double* U, double* out);
 /* Nodal coordinates (for tests): X[d][elem][node]. */
 int or_node_coords(const or_prob* P, double* X);
 
+/* ---------------- original NSK equations (Sec. 2.2) ------------------------ */
+/* State U = (rho, rho v): dim+1 variables, layout as above.  Uses dim, N, nel,
+ * xb, T, eps and kappa of the problem (alpha, beta, diss_c, flux unused).
+ * Right-hand side with the Korteweg stress, two BR1 liftings and the global
+ * Lax-Friedrichs flux; Q (optional) receives the lifted gradients
+ * Q[d][k][elem][node], k over (v_1..v_dim, rho), lap (optional) the lifted
+ * Laplacian of rho. */
+int or_nsk_rhs(const or_prob* P, const double* U, double* R, double* Q, double* lap);
+int or_nsk_run(const or_prob* P, double* U, double dt, int nsteps, double t0, or_forcing_fn f, void* user);
+double or_nsk_lf_speed(const or_prob* P, const double* U);
+double or_nsk_dt(const or_prob* P, const double* U, double cfl);
+int or_nsk_diagnostics(const or_prob* P, const double* U, double* out);
+
 /* ---------------- learned closure (no counterpart in the paper) ------------ */
 #define OR_MLP_IN 4
 #define OR_MLP_HIDDEN 64

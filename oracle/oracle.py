@@ -18,7 +18,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
-SOURCES = ["basis.c", "thermo.c", "lsrk.c", "dg_weak.c", "dg_strong.c", "mlp.c", "closure.c"]
+SOURCES = ["basis.c", "thermo.c", "lsrk.c", "dg_weak.c", "dg_strong.c", "nsk_orig.c", "mlp.c", "closure.c"]
 
 
 def build(force: bool = True) -> str:
@@ -99,6 +99,13 @@ def _declare(L):
     L.or_diagnostics.argtypes = [C.POINTER(_Prob), _dp, _dp]
     L.or_node_coords.argtypes = [C.POINTER(_Prob), _dp]
     L.or_numflux.argtypes = [C.POINTER(_Prob), C.c_int, _dp, _dp, _dp]
+    L.or_nsk_rhs.argtypes = [C.POINTER(_Prob), _dp, _dp, _dp, _dp]
+    L.or_nsk_run.argtypes = [C.POINTER(_Prob), _dp, C.c_double, C.c_int, C.c_double, FORCING, C.c_void_p]
+    L.or_nsk_lf_speed.argtypes = [C.POINTER(_Prob), _dp]
+    L.or_nsk_lf_speed.restype = C.c_double
+    L.or_nsk_dt.argtypes = [C.POINTER(_Prob), _dp, C.c_double]
+    L.or_nsk_dt.restype = C.c_double
+    L.or_nsk_diagnostics.argtypes = [C.POINTER(_Prob), _dp, _dp]
     L.or_gelu.argtypes = [C.c_double]
     L.or_gelu.restype = C.c_double
     L.or_gelu_d.argtypes = [C.c_double]
@@ -222,6 +229,7 @@ class Problem:
     beta: float = 1e-3
     diss_c: int = 1
     flux: int = 0  # 0: Rusanov, 1: HLLC
+    model: int = 0  # 0: relaxation model II, 1: original NSK (state rho, rho v)
     xbreaks: list | None = None  # optional per-direction breakpoints
     _keep: list = field(default_factory=list, repr=False)
 
@@ -240,7 +248,7 @@ class Problem:
 
     @property
     def nvar(self) -> int:
-        return self.dim + 2
+        return self.dim + 2 if self.model == 0 else self.dim + 1
 
     def shape(self):
         return (self.nvar, self.nelem, self.nnode)
@@ -269,9 +277,20 @@ def _state(P: Problem, U) -> np.ndarray:
 
 
 def rhs(P: Problem, U, return_Q: bool = False):
-    """Weak-form DGSEM right-hand side (or_rhs_weak)."""
+    """Weak-form DGSEM right-hand side (or_rhs_weak; or_nsk_rhs for the
+    original NSK equations, where return_Q also returns the lifted Laplacian
+    of rho)."""
     U = _state(P, U)
     R = np.zeros_like(U)
+    if P.model == 1:
+        Q = np.zeros((P.dim, P.dim + 1, P.nelem, P.nnode)) if return_Q else None
+        lap = np.zeros((P.nelem, P.nnode)) if return_Q else None
+        pc = P.c()
+        if lib().or_nsk_rhs(C.byref(pc), _ptr(U), _ptr(R), _ptr(Q) if return_Q else None,
+                            _ptr(lap) if return_Q else None) != 0:
+            raise RuntimeError("or_nsk_rhs failed")
+        R = R.reshape(P.shape())
+        return (R, Q, lap) if return_Q else R
     Q = np.zeros((P.dim, P.dim + 1, P.nelem, P.nnode)) if return_Q else None
     pc = P.c()
     if lib().or_rhs_weak(C.byref(pc), _ptr(U), _ptr(R), _ptr(Q) if return_Q else None) != 0:
@@ -315,7 +334,8 @@ def run(P: Problem, U, dt: float, nsteps: int, t0: float = 0.0, forcing=None):
             arr[:] = np.ascontiguousarray(forcing(t), dtype=np.float64).ravel()
 
         cb = FORCING(_f)
-    if lib().or_run(C.byref(pc), _ptr(U), dt, nsteps, t0, cb, None) != 0:
+    fn = lib().or_nsk_run if P.model == 1 else lib().or_run
+    if fn(C.byref(pc), _ptr(U), dt, nsteps, t0, cb, None) != 0:
         raise RuntimeError("or_run failed")
     return U.reshape(P.shape())
 
@@ -323,7 +343,16 @@ def run(P: Problem, U, dt: float, nsteps: int, t0: float = 0.0, forcing=None):
 def dt(P: Problem, U, cfl: float) -> float:
     U = _state(P, U)
     pc = P.c()
+    if P.model == 1:
+        return lib().or_nsk_dt(C.byref(pc), _ptr(U), cfl)
     return lib().or_dt(C.byref(pc), _ptr(U), cfl)
+
+
+def lf_speed(P: Problem, U) -> float:
+    """Global Lax-Friedrichs speed of the original NSK path (or_nsk_lf_speed)."""
+    U = _state(P, U)
+    pc = P.c()
+    return lib().or_nsk_lf_speed(C.byref(pc), _ptr(U))
 
 
 DIAG_KEYS = ["mass", "e_kin", "e_total", "l2_rho_minus_c", "rho_min", "rho_max", "max_wavespeed", "nonfinite"]
@@ -333,7 +362,8 @@ def diagnostics(P: Problem, U) -> dict:
     U = _state(P, U)
     out = np.zeros(16)
     pc = P.c()
-    if lib().or_diagnostics(C.byref(pc), _ptr(U), _ptr(out)) != 0:
+    fn = lib().or_nsk_diagnostics if P.model == 1 else lib().or_diagnostics
+    if fn(C.byref(pc), _ptr(U), _ptr(out)) != 0:
         raise RuntimeError("or_diagnostics failed")
     return {
         "mass": out[: P.nvar].copy(),
