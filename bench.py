@@ -137,15 +137,15 @@ def cpu_baseline(name: str, sample, sub, budget_s: float = 20.0):
     }
 
 
-def run_form(nsk, m, U0, w, precision: int, steps: int, warmup: int, tile: str, flux: int = 0):
-    """Time `steps` LSRK4(5) steps of one form (precision, numerical flux)
-    from the resident state U0 (torch, device).  Returns timings, the
+def run_form(nsk, m, U0, w, precision: int, steps: int, warmup: int, tile: str, flux: int = 0, model: int = 0):
+    """Time `steps` LSRK4(5) steps of one form (precision, numerical flux,
+    model) from the resident state U0 (torch, device).  Returns timings, the
     stage-kernel means from HIP events on the bound stream, and the final
     state (device)."""
     import torch
 
     s = nsk.Solver(dim=m.dim, N=m.N, nel=tuple(m.nel), lo=tuple(m.lo), hi=tuple(m.hi), alpha=w["alpha"],
-                   beta=1e-3, eps=1e-3, kappa=1e-5, precision=precision, flux=flux)
+                   beta=1e-3, eps=1e-3, kappa=1e-5, precision=precision, flux=flux, model=model)
     s.set_state(U0)
     dt = s.dt_estimate(0.5)
     if tile == "auto":
@@ -170,13 +170,56 @@ def run_form(nsk, m, U0, w, precision: int, steps: int, warmup: int, tile: str, 
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
-    ms_lift, ms_rhs, nst, _ = nsk.nsk_timing_read(s.ctx)
+    ms_lift, ms_rhs, nst, ms_mid = nsk.nsk_timing_read(s.ctx)
     nsk.nsk_timing_enable(s.ctx, 0)
     diag = s.diagnostics()
     final = s.get_state()
     s.close()
-    return {"ms": ms, "wall": wall, "ms_lift": ms_lift / max(nst, 1), "ms_rhs": ms_rhs / max(nst, 1), "dt": dt,
-            "variant": variant, "order": order, "tune_ms": tune_ms, "diag": diag, "final": final}
+    return {"ms": ms, "wall": wall, "ms_lift": ms_lift / max(nst, 1), "ms_rhs": ms_rhs / max(nst, 1),
+            "ms_mid": ms_mid / max(nst, 1), "dt": dt, "variant": variant, "order": order, "tune_ms": tune_ms,
+            "diag": diag, "final": final}
+
+
+def nsk_bytes_per_node(dim: int, stage_first: bool) -> dict:
+    """Algorithmic HBM bytes per node of each kernel of one stage of the
+    original NSK path (FP64, nvar = dim + 1 words of state).
+    lift: read U, write G (tau and grad rho: dim(dim+1)/2 + dim).
+    lap : read grad rho, tau and rho, write Sigma (dim(dim+1)/2).
+    rhs : read U and Sigma, read dU (not in the first stage), write U, dU."""
+    nvar = dim + 1
+    nt = dim * (dim + 1) // 2
+    lift = 8 * (nvar + nt + dim)
+    lap = 8 * (dim + nt + 1 + nt)
+    rhs = 8 * (nvar + nt) + (0 if stage_first else 8 * nvar) + 16 * nvar
+    return {"lift": lift, "lap": lap, "rhs": rhs}
+
+
+def run_nsk_form(nsk, m, U0, w, steps: int, warmup: int, tile: str, ref: dict):
+    """The original NSK equations (Korteweg stress, second lifting, global
+    Lax-Friedrichs flux) on the same workload, FP64: rate, kernel times and
+    roofline fractions, and the simulated time per wall-clock second against
+    the relaxation model (ref: the FP64 model II run)."""
+    nsk_U0 = U0.reshape(m.nvar, -1)[: m.dim + 1].contiguous()
+    r = run_form(nsk, m, nsk_U0, w, 0, steps, warmup, tile, flux=2, model=1)
+    dofs = m.nelem * m.nnode
+    b1, b = nsk_bytes_per_node(m.dim, True), nsk_bytes_per_node(m.dim, False)
+    rhs_bytes = dofs * (b1["rhs"] + 4 * b["rhs"]) / 5.0
+    frac = lambda nbytes, ms: nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS if ms > 0 else None
+    ms_step = r["ms"] / steps
+    return {
+        "value": dofs * 5 * steps / (r["ms"] * 1e-3), "unit": "DOF-stage/s", "ms_per_step": ms_step,
+        "lift_ms": r["ms_lift"], "lap_and_reduce_ms": r["ms_mid"], "rhs_ms": r["ms_rhs"],
+        "rhs_roofline_frac": frac(rhs_bytes, r["ms_rhs"]),
+        "lift_roofline_frac": frac(dofs * b["lift"], r["ms_lift"]),
+        "lap_roofline_frac": frac(dofs * b["lap"], r["ms_mid"]),
+        "stage_bytes_per_node": b["lift"] + b["lap"] + b["rhs"],
+        "dt": r["dt"], "dt_model2_alpha": {"alpha": w["alpha"], "dt": ref["dt"]},
+        "sim_time_per_wall_s": r["dt"] / (ms_step * 1e-3),
+        "sim_time_per_wall_s_model2": ref["dt"] / (ref["ms"] / steps * 1e-3),
+        "status_after": r["diag"]["status"],
+        "tile": {"variant": r["variant"], "order": r["order"]},
+        "physics": "kappa=1e-5, eps=1e-3, no alpha/beta; state (rho, rho v) of the same collision",
+    }
 
 
 def run_batched(nsk, steps: int, warmup: int):
@@ -612,6 +655,7 @@ def main() -> int:
             "tile": {"variant": hl["variant"], "order": hl["order"]},
         }
         del hl
+        out["forms"]["nsk_original_fp64"] = run_nsk_form(nsk, m, U0, w, args.steps, args.warmup, args.tile, f64)
     del forms
     if not args.no_forms and not args.no_batched and args.workload == "3d-collision":
         out.setdefault("forms", {})["batched"] = run_batched(nsk, 10, 2)

@@ -18,10 +18,21 @@
  * gradient of c, and the five-stage fourth-order 2N-storage Runge-Kutta
  * scheme of Carpenter and Kennedy.
  *
+ * The original NSK equations (Sec. 2.2, model = 1): U = (rho, rho v) with
+ *   Fc_i = (rho v_i, rho v_i v + p e_i),  Fv_i = (0, Sigma_{.i}),
+ *   Sigma = tau + kappa ((rho lap rho + |grad rho|^2/2) I - grad rho (x) grad rho)
+ * (the Korteweg stress, whose divergence is kappa rho grad lap rho), no
+ * source.  grad rho comes from the BR1 lifting of (v, rho), lap rho from a
+ * second BR1 lifting of the lifted gradient (end of Sec. 3.1); the
+ * convective face flux is the global Lax-Friedrichs flux with one speed for
+ * the whole grid, max over nodes and directions of |v_d| + sqrt(max(p', 0)),
+ * recomputed at every evaluation; the second-order face flux is the mean of
+ * the traces of the nodal Sigma.
+ *
  * Mesh: periodic tensor-product grid of axis-aligned box elements.
  *
  * Data layout of every state array (device memory, double):
- *   U[var][elem][node], var = 0 rho, 1..dim rho v_d, dim+1 c;
+ *   U[var][elem][node], var = 0 rho, 1..dim rho v_d, dim+1 c (model 0 only);
  *   elem = ex + nel0 (ey + nel1 ez); node = i + (N+1)(j + (N+1) k)
  *   with i, j, k the Gauss-node indices along x, y, z.
  *
@@ -70,10 +81,14 @@ typedef struct {
   double kappa;   /* eps^2 gamma, coefficient of the Laplacian of c         */
   double alpha;   /* relaxation parameter, > 6 (1 - T) (hyperbolicity)     */
   double beta;    /* parabolic relaxation parameter (> 0)                   */
-  int flux;       /* 0 = Rusanov, 1 = HLLC (barotropic form)                */
+  int flux;       /* 0 = Rusanov, 1 = HLLC (barotropic form), 2 = global
+                     Lax-Friedrichs (model 1 only)                          */
   int diss_c;     /* 1 = numerical-flux dissipation also on c, 0 = not on c */
   int precision;  /* 0 = FP64 throughout; 1 = mixed (FP32 volume/surface)   */
   int closure;    /* 1: add the learned closure source (nsk_closure_set)   */
+  int model;      /* 0 = relaxation model II (Sec. 2.3); 1 = the original
+                     NSK equations (Sec. 2.2): flux must be 2, precision 0,
+                     closure 0; alpha, beta and diss_c are not used          */
 } nsk_params;
 
 typedef struct {
@@ -91,14 +106,17 @@ typedef struct {
  * memory is touched).  Rejects dim outside 1..3, N outside 1..6, nel < 1,
  * (NSK_EUNSUPPORTED for dim = 3 with N = 6, whose element tile exceeds 64 KB
  * of LDS),
- * non-increasing breakpoints, T outside (0,1), alpha <= 6 (1 - T), beta <= 0,
- * eps < 0, kappa < 0.  *out is set on success. */
+ * non-increasing breakpoints, T outside (0,1), eps < 0, kappa < 0, model
+ * outside 0..1, and for model 0 alpha <= 6 (1 - T), beta <= 0 or flux
+ * outside 0..1; for model 1 flux != 2, precision != 0 or closure != 0.
+ * *out is set on success. */
 int nsk_create(const nsk_mesh* mesh, const nsk_params* params, nsk_ctx** out);
 
 /* Frees the host context (waits for the bound stream first). */
 void nsk_destroy(nsk_ctx* ctx);
 
-/* Number of doubles in one state array: (dim+2) * elements * (N+1)^dim. */
+/* Number of doubles in one state array: nvar * elements * (N+1)^dim with
+ * nvar = dim+2 (model 0) or dim+1 (model 1). */
 size_t nsk_state_size(const nsk_ctx* ctx);
 
 /* Bytes of device workspace nsk_bind expects (second state buffer, lifted
@@ -127,7 +145,12 @@ int nsk_rhs(nsk_ctx* ctx, const double* d_U, double* d_R, double t);
  *                  1/((2N+1)^2 max_e sum_d max(eps, kappa/beta)/h_d^2),
  *                  z_R beta/alpha)
  * with a = sqrt(p'(rho) + alpha rho) and z_R the negative-real-axis
- * stability limit of the Runge-Kutta scheme.  Waits for the stream. */
+ * stability limit of the Runge-Kutta scheme.  Model 1:
+ *   dt = cfl * min(1/((2N+1) lam max_e sum_d 1/h_d),
+ *                  1/((2N+1)^2 eps max_e sum_d 1/h_d^2),
+ *                  (1/4)/((2N+1)^2 sqrt(kappa rho_max) max_e sum_d 1/h_d^2))
+ * with lam the global Lax-Friedrichs speed (the last bound is that of the
+ * capillary modes, frequencies sqrt(kappa rho) k^2).  Waits for the stream. */
 int nsk_dt_estimate(nsk_ctx* ctx, double cfl, double* dt_out);
 
 /* Advances the bound state by nsteps steps of size dt (five stages each).
@@ -135,7 +158,10 @@ int nsk_dt_estimate(nsk_ctx* ctx, double cfl, double* dt_out);
 int nsk_rk_step(nsk_ctx* ctx, double dt, int nsteps);
 
 /* Diagnostics of the bound state (quadrature over all elements, with the
- * lifted gradient of c in the capillary energy).  Waits for the stream.
+ * lifted gradient of c in the capillary energy).  Model 1: e_total is the
+ * NSK energy int (rho |v|^2/2 + W + kappa |grad rho|^2/2) with the lifted
+ * gradient of rho, l2_rho_minus_c is 0 and max_wavespeed is the global
+ * Lax-Friedrichs speed.  Waits for the stream.
  * host_out->status is NSK_ENONPHYS, and so is the return value, if any value
  * is non-finite or rho leaves (0, 3). */
 int nsk_diagnostics(nsk_ctx* ctx, nsk_diag* host_out);
@@ -171,7 +197,8 @@ int nsk_set_params(nsk_ctx* ctx, const nsk_params* params);
  * until the next read).  nsk_timing_read waits for the stream and returns
  * out[0] = summed ms of the lifting kernel, out[1] = summed ms of the
  * right-hand-side/update kernel, out[2] = number of stages timed, out[3] =
- * summed ms of the closure kernel, then clears the record.
+ * summed ms of the closure kernel (model 0) or of the speed reduction and
+ * second lifting (model 1), then clears the record.
  * nsk_timing_enable(ctx, 0) stops recording and releases the events. */
 int nsk_timing_enable(nsk_ctx* ctx, int enable);
 int nsk_timing_read(nsk_ctx* ctx, double out[4]);
@@ -274,8 +301,8 @@ int nsk_mlp_moments(const float* d_Y, long long n, int ncol, void* d_ws, double*
  * ------------------------------------------------------------------------ */
 typedef struct nsk_batch nsk_batch;
 
-/* meshes[0..ninst-1] must all be 3D, params->closure 0 and params->flux 0
- * (Rusanov) (NSK_EUNSUPPORTED otherwise); the validation rules of
+/* meshes[0..ninst-1] must all be 3D, params->model 0, params->closure 0 and
+ * params->flux 0 (Rusanov) (NSK_EUNSUPPORTED otherwise); the validation rules of
  * nsk_create apply per instance.  Host only. */
 int nsk_batch_create(const nsk_mesh* meshes, int ninst, const nsk_params* params, nsk_batch** out);
 

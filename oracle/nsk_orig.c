@@ -125,7 +125,9 @@ double or_nsk_lf_speed(const or_prob* P, const double* U) {
   return lam;
 }
 
-int or_nsk_rhs(const or_prob* P, const double* U, double* R, double* Qout, double* lapout) {
+/* The right-hand side with the global LF speed lam given (the speed of a
+ * larger grid of which U is a part); or_nsk_rhs uses the speed of U. */
+int or_nsk_rhs_lam(const or_prob* P, const double* U, double lam, double* R, double* Qout, double* lapout) {
   or_geom g;
   if (nsk_geom(&g, P)) return -1;
   const int dim = g.dim, nvar = g.nvar, nl = g.nlift, nn = g.nnode;
@@ -134,7 +136,6 @@ int or_nsk_rhs(const or_prob* P, const double* U, double* R, double* Qout, doubl
   double* Q = malloc(sizeof(double) * dim * nl * S);
   double* lap = malloc(sizeof(double) * S);
   gradients(&g, U, Q, lap);
-  const double lam = or_nsk_lf_speed(P, U);
 
   /* Step 4: nodal total flux and its second-order part */
   double* F = malloc(sizeof(double) * dim * nvar * S);
@@ -206,6 +207,10 @@ int or_nsk_rhs(const or_prob* P, const double* U, double* R, double* Qout, doubl
   if (lapout) memcpy(lapout, lap, sizeof(double) * S);
   free(Q); free(lap); free(F); free(Fv); free(Fs);
   return 0;
+}
+
+int or_nsk_rhs(const or_prob* P, const double* U, double* R, double* Qout, double* lapout) {
+  return or_nsk_rhs_lam(P, U, or_nsk_lf_speed(P, U), R, Qout, lapout);
 }
 
 int or_nsk_run(const or_prob* P, double* U, double dt, int nsteps, double t0, or_forcing_fn fn, void* user) {

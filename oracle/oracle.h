@@ -118,6 +118,8 @@ int or_node_coords(const or_prob* P, double* X);
  * Q[d][k][elem][node], k over (v_1..v_dim, rho), lap (optional) the lifted
  * Laplacian of rho. */
 int or_nsk_rhs(const or_prob* P, const double* U, double* R, double* Q, double* lap);
+/* The same with the global Lax-Friedrichs speed lam given by the caller. */
+int or_nsk_rhs_lam(const or_prob* P, const double* U, double lam, double* R, double* Q, double* lap);
 int or_nsk_run(const or_prob* P, double* U, double dt, int nsteps, double t0, or_forcing_fn f, void* user);
 double or_nsk_lf_speed(const or_prob* P, const double* U);
 double or_nsk_dt(const or_prob* P, const double* U, double cfl);

@@ -100,6 +100,7 @@ def _declare(L):
     L.or_node_coords.argtypes = [C.POINTER(_Prob), _dp]
     L.or_numflux.argtypes = [C.POINTER(_Prob), C.c_int, _dp, _dp, _dp]
     L.or_nsk_rhs.argtypes = [C.POINTER(_Prob), _dp, _dp, _dp, _dp]
+    L.or_nsk_rhs_lam.argtypes = [C.POINTER(_Prob), _dp, C.c_double, _dp, _dp, _dp]
     L.or_nsk_run.argtypes = [C.POINTER(_Prob), _dp, C.c_double, C.c_int, C.c_double, FORCING, C.c_void_p]
     L.or_nsk_lf_speed.argtypes = [C.POINTER(_Prob), _dp]
     L.or_nsk_lf_speed.restype = C.c_double
@@ -276,18 +277,23 @@ def _state(P: Problem, U) -> np.ndarray:
     return U
 
 
-def rhs(P: Problem, U, return_Q: bool = False):
+def rhs(P: Problem, U, return_Q: bool = False, lf_speed: float | None = None):
     """Weak-form DGSEM right-hand side (or_rhs_weak; or_nsk_rhs for the
     original NSK equations, where return_Q also returns the lifted Laplacian
-    of rho)."""
+    of rho and lf_speed, if given, replaces the global Lax-Friedrichs speed
+    of U: or_nsk_rhs_lam)."""
     U = _state(P, U)
     R = np.zeros_like(U)
     if P.model == 1:
         Q = np.zeros((P.dim, P.dim + 1, P.nelem, P.nnode)) if return_Q else None
         lap = np.zeros((P.nelem, P.nnode)) if return_Q else None
         pc = P.c()
-        if lib().or_nsk_rhs(C.byref(pc), _ptr(U), _ptr(R), _ptr(Q) if return_Q else None,
-                            _ptr(lap) if return_Q else None) != 0:
+        qp, lp = (_ptr(Q) if return_Q else None), (_ptr(lap) if return_Q else None)
+        if lf_speed is None:
+            rc = lib().or_nsk_rhs(C.byref(pc), _ptr(U), _ptr(R), qp, lp)
+        else:
+            rc = lib().or_nsk_rhs_lam(C.byref(pc), _ptr(U), float(lf_speed), _ptr(R), qp, lp)
+        if rc != 0:
             raise RuntimeError("or_nsk_rhs failed")
         R = R.reshape(P.shape())
         return (R, Q, lap) if return_Q else R

@@ -103,7 +103,7 @@ struct PhysArgs {
   double kb;         // kappa / beta
   double ab;         // alpha / beta
   int diss_c;        // numerical-flux dissipation on c
-  int flux;          // 0: Rusanov, 1: HLLC
+  int flux;          // 0: Rusanov, 1: HLLC, 2: global Lax-Friedrichs
   double rho_lo64, rho_hi64;  // mixed precision: FP64 EoS inside this band
 };
 
@@ -111,6 +111,7 @@ struct StageArgs {
   double A, B, dt;   // low-storage coefficients of the stage and step size
   int mode;          // 0: write R; 1: Runge-Kutta stage update
   const float* closure = nullptr;  // learned closure source [dim+1][elem][node], or none
+  const double* lf = nullptr;      // global Lax-Friedrichs speed (original NSK path)
 };
 
 // -------------------------------------------------------------------------
@@ -224,27 +225,61 @@ __device__ __forceinline__ int face_of(int d, int n) {
   return (n % sd) + sd * (n / (sd * NP));
 }
 
-// Convective flux of model II in direction d; irho = 1/rho.
-template <int DIM, typename R>
+// Convective flux in direction d; irho = 1/rho; NV = DIM + 2 (model II, c
+// not convected) or DIM + 1 (original NSK).
+template <int DIM, typename R, int NV = DIM + 2>
 __device__ __forceinline__ void conv_flux(int d, const R* u, R irho, R pa, R* F) {
   const R vd = u[1 + d] * irho;
   F[0] = u[1 + d];
 #pragma unroll
   for (int j = 0; j < DIM; ++j) F[1 + j] = vd * u[1 + j] + (j == d ? pa : R(0));
-  F[DIM + 1] = R(0);
+  if constexpr (NV == DIM + 2) F[DIM + 1] = R(0);
+}
+
+// Original NSK path: the speed of the global Lax-Friedrichs flux at a node,
+// max_d |v_d| + sqrt(max(p', 0)) (the sound speed is imaginary inside the
+// spinodal interval).
+template <int DIM>
+__device__ __forceinline__ double lf_node_speed(const double* u, double T) {
+  const double rho = u[0], q = 1.0 / (3.0 - rho);
+  const double dp = 24.0 * T * q * q - 6.0 * rho;
+  const double a = dp > 0.0 ? sqrt(dp) : 0.0;
+  double m = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) m = fmax(m, fabs(u[1 + d] / rho));
+  return m + a;
+}
+
+// Maximum of v over the workgroup, written by thread 0 to *out (all threads
+// call it).
+template <int THREADS>
+__device__ __forceinline__ void block_max_store(double v, double* red, double* out, int tid) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) {
+    double m = red[0];
+    for (int w = 1; w < (THREADS + 63) / 64; ++w) m = fmax(m, red[w]);
+    *out = m;
+  }
 }
 
 // -------------------------------------------------------------------------
-// Lifting: G = (tau, grad c) from the BR1 gradients of (v, c):
+// Lifting: G = (tau, grad s) from the BR1 gradients of (v, s), s = c for
+// model II (MODEL 0) and s = rho for the original NSK path (MODEL 1):
 //   q_d,i = (2/h_d) [ (L+_i w*_+ - L-_i w*_-) / omega_i - sum_l Dhat_il w_l ]
 // along each d-line, w* = (w_left + w_right) / 2 on the faces.
 // -------------------------------------------------------------------------
-template <int DIM, int NP, int EPB, typename R, typename GT>
+template <int DIM, int NP, int EPB, typename R, typename GT, int MODEL = 0>
 __device__ __forceinline__ void lift_block(int L, int tid, const double* __restrict__ U, GT* __restrict__ G,
-                                           const BasisArgs& bas, const MeshArgs& msh, const PhysArgs& ph) {
+                                           const BasisArgs& bas, const MeshArgs& msh, const PhysArgs& ph,
+                                           double* __restrict__ lfpart = nullptr) {
   using Sh = Shape<DIM, NP>;
   constexpr int NN = Sh::NN, NF = Sh::NF, NL = Sh::NLIFT;
-  __shared__ R sW[EPB][NL][NN];             // nodal primitives (v, c)
+  constexpr int NV = MODEL == 1 ? DIM + 1 : DIM + 2;  // conserved variables
+  constexpr int SI = MODEL == 1 ? 0 : DIM + 1;        // the lifted scalar: rho or c
+  __shared__ R sW[EPB][NL][NN];             // nodal primitives (v, s)
   __shared__ R sNbW[EPB][2][NL][NN];        // primitives of the two neighbours in direction d
   __shared__ R sWs[EPB][DIM][2][NL][NF];    // central face values w*
   __shared__ R sD[NP][NP];
@@ -261,24 +296,33 @@ __device__ __forceinline__ void lift_block(int L, int tid, const double* __restr
   const int e = el < EPB ? info.e[el] : -1;
   const bool active = e >= 0;
 
+  double lfs = 0.0;  // global Lax-Friedrichs speed at this node (MODEL 1)
   if (active) {
     const long long o = (long long)e * NN + n;
-    const double irho = 1.0 / U[o];
+    double u[NV];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) sW[el][d][n] = R(U[(1 + d) * S + o] * irho);
-    sW[el][DIM][n] = R(U[(DIM + 1) * S + o]);
+    for (int v = 0; v < NV; ++v) u[v] = U[v * S + o];
+    const double irho = 1.0 / u[0];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) sW[el][d][n] = R(u[1 + d] * irho);
+    sW[el][DIM][n] = R(u[SI]);
+    if constexpr (MODEL == 1) lfs = lf_node_speed<DIM>(u, ph.T);
+  }
+  if constexpr (MODEL == 1) {
+    __shared__ double sRed[(Tile<DIM, NP, EPB>::THREADS + 63) / 64];
+    if (lfpart) block_max_store<Tile<DIM, NP, EPB>::THREADS>(lfs, sRed, lfpart + L, tid);
   }
 
   // the next direction's neighbour states are fetched into registers while
   // the current direction's face values are formed
-  double nbu[2][DIM + 2];
+  double nbu[2][NV];
   auto fetch_nb = [&](auto dc) {
     constexpr int dd = decltype(dc)::value;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const long long on = (long long)info.nb[el][dd][s] * NN + n;
 #pragma unroll
-      for (int v = 0; v < DIM + 2; ++v) nbu[s][v] = U[v * S + on];
+      for (int v = 0; v < NV; ++v) nbu[s][v] = U[v * S + on];
     }
   };
   if (active) fetch_nb(std::integral_constant<int, 0>{});
@@ -291,7 +335,7 @@ __device__ __forceinline__ void lift_block(int L, int tid, const double* __restr
         const double irho = 1.0 / nbu[s][0];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) sNbW[el][s][k][n] = R(nbu[s][1 + k] * irho);
-        sNbW[el][s][DIM][n] = R(nbu[s][DIM + 1]);
+        sNbW[el][s][DIM][n] = R(nbu[s][SI]);
       }
       if constexpr (d + 1 < DIM) fetch_nb(std::integral_constant<int, d + 1>{});
     }
@@ -365,19 +409,120 @@ __device__ __forceinline__ void lift_block(int L, int tid, const double* __restr
 }
 
 // -------------------------------------------------------------------------
+// Original NSK path, second BR1 lifting (end of Sec. 3.1): with g = grad rho
+// from the first lifting (G slots NTAU..NTAU+DIM-1),
+//   lap_i = sum_d (2/h_d) [ (L+_i g*_+ - L-_i g*_-) / omega_i - sum_l Dhat_il g_d,l ],
+// g* = (g_left + g_right) / 2 the central face values of g_d on the d-faces;
+// then the viscous stress in G's tau slots becomes the full second-order
+// stress Sigma = eps tau + kappa ((rho lap + |g|^2/2) I - g g^T) (the
+// Korteweg stress of Sec. 2.2 in conservative form).  The gradient slots are
+// only read, so neighbouring workgroups see the first lifting's values.
+// -------------------------------------------------------------------------
+template <int DIM, int NP, int EPB>
+__device__ __forceinline__ void lap_block(int L, int tid, const double* __restrict__ U, double* __restrict__ G,
+                                          const BasisArgs& bas, const MeshArgs& msh, const PhysArgs& ph) {
+  using Sh = Shape<DIM, NP>;
+  constexpr int NN = Sh::NN, NF = Sh::NF, NT = Sh::NTAU;
+  __shared__ double sg[EPB][NN];          // own g_d
+  __shared__ double sNb[EPB][2][NN];      // g_d of the two neighbours in direction d
+  __shared__ double sgs[EPB][2][NF];      // central face values on the two d-faces
+  __shared__ double sD[NP][NP];
+  __shared__ double sLm[NP], sLp[NP], sIw[NP];
+  __shared__ ElemInfo<DIM, EPB> info;
+
+  const long long S = msh.S;
+  if (tid < NP * NP) sD[tid / NP][tid % NP] = bas.Dhat[tid / NP][tid % NP];
+  if (tid < NP) { sLm[tid] = bas.Lm[tid]; sLp[tid] = bas.Lp[tid]; sIw[tid] = bas.invw[tid]; }
+  elem_info<DIM, EPB>(info, msh, L, tid);
+  __syncthreads();
+
+  const int el = tid / NN, n = tid - (tid / NN) * NN;
+  const int e = el < EPB ? info.e[el] : -1;
+  const bool active = e >= 0;
+  const long long o = (long long)(active ? e : 0) * NN + n;
+
+  double g[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) g[d] = active ? G[(long long)(NT + d) * S + o] : 0.0;
+  double lap = 0.0;
+
+  static_for<DIM>([&](auto dc) {
+    constexpr int d = decltype(dc)::value;
+    if (active) {
+      sg[el][n] = g[d];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) sNb[el][s][n] = G[(long long)(NT + d) * S + (long long)info.nb[el][d][s] * NN + n];
+    }
+    __syncthreads();
+    if (tid < EPB * 2 * NF) {
+      const int f = tid % NF;
+      const int s = (tid / NF) & 1;
+      const int le = tid / (2 * NF);
+      if (info.e[le] >= 0) {
+        const int base = face_base<NP>(d, f);
+        const int sd = dstride<NP>(d);
+        double own = 0.0, oth = 0.0;
+#pragma unroll
+        for (int l = 0; l < NP; ++l) {
+          const int node = base + l * sd;
+          own += (s ? sLp[l] : sLm[l]) * sg[le][node];
+          oth += (s ? sLm[l] : sLp[l]) * sNb[le][s][node];
+        }
+        sgs[le][s][f] = 0.5 * (own + oth);
+      }
+    }
+    __syncthreads();
+    if (active) {
+      const int sd = dstride<NP>(d);
+      const int i = (n / sd) % NP;
+      const int f = face_of<NP>(d, n);
+      double vol = 0.0;
+#pragma unroll
+      for (int l = 0; l < NP; ++l) vol += sD[i][l] * sg[el][n + (l - i) * sd];
+      const double surf = (sLp[i] * sgs[el][1][f] - sLm[i] * sgs[el][0][f]) * sIw[i];
+      lap += info.h2[el][d] * (surf - vol);
+    }
+    __syncthreads();  // LDS reused by the next direction
+  });
+
+  if (active) {
+    const double rho = U[o];
+    double g2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) g2 += g[d] * g[d];
+    const double iso = ph.kappa * (rho * lap + 0.5 * g2);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int b = a; b < DIM; ++b) {
+        const long long ot = (long long)tau_index<DIM>(a, b) * S + o;
+        double t = G[ot] - ph.kappa * g[a] * g[b];
+        if (a == b) t += iso;
+        G[ot] = t;
+      }
+  }
+}
+
+// -------------------------------------------------------------------------
 // Right-hand side and fused Runge-Kutta stage:
 //   R_i = sum_d (2/h_d) [ sum_l Dhat_il F_d,l - (L+_i F*_+ - L-_i F*_-) / omega_i ] + S_i
-// with F_d = Fc_d(U) - Fv_d(G), F* = Rusanov(U-, U+) - (Fv(G-) + Fv(G+)) / 2
-// and S = (0, alpha rho grad c, (alpha/beta)(rho - c)); then
+// with F_d = Fc_d(U) - Fv_d(G), F* = Rusanov, HLLC or global LF (U-, U+)
+// - (Fv(G-) + Fv(G+)) / 2 and S = (0, alpha rho grad c, (alpha/beta)(rho - c))
+// (model II); the original NSK path (MODEL 1) has U = (rho, m), the
+// second-order stress Sigma in G's tau slots and no source; then
 //   dU <- A dU + dt R,  U <- U + B dU.
 // -------------------------------------------------------------------------
-template <int DIM, int NP, int EPB, typename R, typename GT, int FLUX = 0>
+template <int DIM, int NP, int EPB, typename R, typename GT, int FLUX = 0, int MODEL = 0>
 __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restrict__ U, const GT* __restrict__ G,
                                           double* __restrict__ Uout, double* __restrict__ dU, const BasisArgs& bas,
                                           const MeshArgs& msh, const PhysArgs& ph, const StageArgs& st) {
   using Sh = Shape<DIM, NP>;
-  constexpr int NN = Sh::NN, NF = Sh::NF, NV = Sh::NVAR, NT = Sh::NTAU, NG = Sh::NG;
-  constexpr int NX = NV + DIM + 1;          // per node: U and the viscous flux components of direction d
+  constexpr int NN = Sh::NN, NF = Sh::NF, NT = Sh::NTAU;
+  constexpr int NV = MODEL == 1 ? DIM + 1 : DIM + 2;   // conserved variables
+  constexpr int NG = MODEL == 1 ? NT : Sh::NG;         // G slots read: Sigma, or (tau, grad c)
+  constexpr int NVX = MODEL == 1 ? DIM : DIM + 1;      // viscous flux components of one direction
+  constexpr int NX = NV + NVX;              // per node: U and the viscous flux components of direction d
+  static_assert(MODEL == 0 || FLUX == 2, "the original NSK path uses the global Lax-Friedrichs flux");
   constexpr bool MIXED = sizeof(R) != sizeof(double);
   constexpr int R64E = MIXED ? EPB : 1, R64N = MIXED ? NN : 1;
   __shared__ R sOwn[EPB][NX][NN];           // own U and (tau_{.d}, dc/dx_d)
@@ -402,6 +547,7 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
   const R kb = R(ph.kb);
 
   double rho64 = 0.0, c64 = 0.0;
+  const R lam_g = FLUX == 2 ? R(*st.lf) : R(0);  // global Lax-Friedrichs speed
   double u64[NV], du_old[NV];
   R u[NV], g[NG];
 #pragma unroll
@@ -421,7 +567,7 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
       for (int v = 0; v < NV; ++v) du_old[v] = dU[v * S + o];
     }
     rho64 = u64[0];
-    c64 = u64[DIM + 1];
+    if constexpr (MODEL == 0) c64 = u64[DIM + 1];
 #pragma unroll
     for (int v = 0; v < NV; ++v) { u[v] = R(u64[v]); sOwn[el][v][n] = u[v]; }
     if (MIXED) sRho64[MIXED ? el : 0][0][MIXED ? n : 0] = rho64;
@@ -440,7 +586,7 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
   // per SIMD whatever its register count, so the next direction's values
   // are fetched while the current one is computed; the mixed-precision
   // kernel (3 waves per SIMD) fetches them when it stages them.
-  constexpr bool PREFETCH = !MIXED && FLUX == 0;  // the HLLC face code needs the registers
+  constexpr bool PREFETCH = !MIXED && FLUX != 1;  // the HLLC face code needs the registers
   double nbv[2][NX];
   auto fetch_nb = [&](auto dc) {
     constexpr int dd = decltype(dc)::value;
@@ -451,7 +597,7 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
       for (int v = 0; v < NV; ++v) nbv[s][v] = U[v * S + on];
 #pragma unroll
       for (int j = 0; j < DIM; ++j) nbv[s][NV + j] = double(G[(long long)tau_index<DIM>(j, dd) * S + on]);
-      nbv[s][NV + DIM] = double(G[(long long)(NT + dd) * S + on]);
+      if constexpr (MODEL == 0) nbv[s][NV + DIM] = double(G[(long long)(NT + dd) * S + on]);
     }
   };
   if (PREFETCH && active) fetch_nb(std::integral_constant<int, 0>{});
@@ -462,12 +608,12 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
       // own viscous components of direction d and the nodal total flux
 #pragma unroll
       for (int j = 0; j < DIM; ++j) sOwn[el][NV + j][n] = g[tau_index<DIM>(j, d)];
-      sOwn[el][NV + DIM][n] = g[NT + d];
+      if constexpr (MODEL == 0) sOwn[el][NV + DIM][n] = g[NT + d];
       R F[NV];
-      conv_flux<DIM, R>(d, u, irho, pa, F);
+      conv_flux<DIM, R, NV>(d, u, irho, pa, F);
 #pragma unroll
       for (int j = 0; j < DIM; ++j) F[1 + j] -= g[tau_index<DIM>(j, d)];
-      F[DIM + 1] -= kb * g[NT + d];
+      if constexpr (MODEL == 0) F[DIM + 1] -= kb * g[NT + d];
 #pragma unroll
       for (int v = 0; v < NV; ++v) sF[el][v][n] = F[v];
       // the two neighbours, coalesced
@@ -489,11 +635,11 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
         const int base = face_base<NP>(d, f);
         const int sd = dstride<NP>(d);
         double ro64 = 0.0, rn64 = 0.0;   // density traces in FP64 (EoS guard)
-        R uo[NV], un[NV], vo[DIM + 1], vn[DIM + 1];
+        R uo[NV], un[NV], vo[NVX], vn[NVX];
 #pragma unroll
         for (int v = 0; v < NV; ++v) { uo[v] = R(0); un[v] = R(0); }
 #pragma unroll
-        for (int k = 0; k <= DIM; ++k) { vo[k] = R(0); vn[k] = R(0); }
+        for (int k = 0; k < NVX; ++k) { vo[k] = R(0); vn[k] = R(0); }
 #pragma unroll
         for (int l = 0; l < NP; ++l) {
           const int node = base + l * sd;
@@ -511,26 +657,36 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
             un[v] += Ln * sNb[le][s][v][node];
           }
 #pragma unroll
-          for (int k = 0; k <= DIM; ++k) {
+          for (int k = 0; k < NVX; ++k) {
             vo[k] += Lo * sOwn[le][NV + k][node];
             vn[k] += Ln * sNb[le][s][NV + k][node];
           }
         }
         // left/right in direction d: on side + this element is the left state
-        R uL[NV], uR[NV], vL[DIM + 1], vR[DIM + 1];
+        R uL[NV], uR[NV], vL[NVX], vR[NVX];
 #pragma unroll
         for (int v = 0; v < NV; ++v) { uL[v] = s ? uo[v] : un[v]; uR[v] = s ? un[v] : uo[v]; }
 #pragma unroll
-        for (int k = 0; k <= DIM; ++k) { vL[k] = s ? vo[k] : vn[k]; vR[k] = s ? vn[k] : vo[k]; }
+        for (int k = 0; k < NVX; ++k) { vL[k] = s ? vo[k] : vn[k]; vR[k] = s ? vn[k] : vo[k]; }
         const double rL = s ? ro64 : rn64, rR = s ? rn64 : ro64;
-        R paL, paR, aL, aR;
-        p_alpha_sound_guarded<R>(rL, ph, paL, aL);
-        p_alpha_sound_guarded<R>(rR, ph, paR, aR);
+        R paL, paR, aL = R(0), aR = R(0);
+        if constexpr (FLUX == 2) {
+          // the global Lax-Friedrichs flux needs no local sound speed
+          paL = p_alpha_guarded<R>(rL, ph);
+          paR = p_alpha_guarded<R>(rR, ph);
+        } else {
+          p_alpha_sound_guarded<R>(rL, ph, paL, aL);
+          p_alpha_sound_guarded<R>(rR, ph, paR, aR);
+        }
         const R irL = R(1) / uL[0], irR = R(1) / uR[0];
         R FL[NV], FR[NV], Fc[NV];
-        conv_flux<DIM, R>(d, uL, irL, paL, FL);
-        conv_flux<DIM, R>(d, uR, irR, paR, FR);
-        if constexpr (FLUX == 0) {
+        conv_flux<DIM, R, NV>(d, uL, irL, paL, FL);
+        conv_flux<DIM, R, NV>(d, uR, irR, paR, FR);
+        if constexpr (FLUX == 2) {
+          // global Lax-Friedrichs: one dissipation speed for the whole grid
+#pragma unroll
+          for (int v = 0; v < NV; ++v) Fc[v] = R(0.5) * (FL[v] + FR[v]) - R(0.5) * lam_g * (uR[v] - uL[v]);
+        } else if constexpr (FLUX == 0) {
           // Rusanov: central flux minus the larger wave speed times the jump
           const R sL = fabs(uL[1 + d] * irL) + aL;
           const R sR = fabs(uR[1 + d] * irR) + aR;
@@ -573,7 +729,9 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
         for (int v = 0; v < NV; ++v) {
           R Fs = Fc[v];
           if (v >= 1 && v <= DIM) Fs -= R(0.5) * (vL[v - 1] + vR[v - 1]);
-          if (v == NV - 1) Fs -= R(0.5) * kb * (vL[DIM] + vR[DIM]);
+          if constexpr (MODEL == 0) {
+            if (v == NV - 1) Fs -= R(0.5) * kb * (vL[DIM] + vR[DIM]);
+          }
           sFs[le][s][v][f] = Fs;
         }
       }
@@ -604,12 +762,16 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
     double Rv[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) Rv[v] = double(acc[v]);
+    if constexpr (MODEL == 0) {
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) Rv[1 + d] += ph.alpha * rho64 * double(g[NT + d]);
-    Rv[DIM + 1] += ph.ab * (rho64 - c64);
-    if (st.closure) {
+      for (int d = 0; d < DIM; ++d) Rv[1 + d] += ph.alpha * rho64 * double(g[NT + d]);
+      Rv[DIM + 1] += ph.ab * (rho64 - c64);
+    }
+    if constexpr (MODEL == 0) {
+      if (st.closure) {
 #pragma unroll
-      for (int d = 0; d <= DIM; ++d) Rv[1 + d] += double(st.closure[d * S + o]);
+        for (int d = 0; d <= DIM; ++d) Rv[1 + d] += double(st.closure[d * S + o]);
+      }
     }
     if (st.mode == 0) {
 #pragma unroll
@@ -637,12 +799,42 @@ lift_kernel(const double* __restrict__ U, GT* __restrict__ G, BasisArgs bas, Mes
   lift_block<DIM, NP, EPB, R, GT>(remap_block(blockIdx.x, gridDim.x, msh.nxcd), threadIdx.x, U, G, bas, msh, ph);
 }
 
-template <int DIM, int NP, int EPB, typename R, typename GT, int FLUX = 0>
+template <int DIM, int NP, int EPB, typename R, typename GT, int FLUX = 0, int MODEL = 0>
 __global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
 rhs_kernel(const double* __restrict__ U, const GT* __restrict__ G, double* __restrict__ Uout,
            double* __restrict__ dU, BasisArgs bas, MeshArgs msh, PhysArgs ph, StageArgs st) {
-  rhs_block<DIM, NP, EPB, R, GT, FLUX>(remap_block(blockIdx.x, gridDim.x, msh.nxcd), threadIdx.x, U, G, Uout, dU, bas,
-                                       msh, ph, st);
+  rhs_block<DIM, NP, EPB, R, GT, FLUX, MODEL>(remap_block(blockIdx.x, gridDim.x, msh.nxcd), threadIdx.x, U, G, Uout,
+                                              dU, bas, msh, ph, st);
+}
+
+// Original NSK path: the first lifting, which also writes the workgroup's
+// maximum of the global Lax-Friedrichs speed to lfpart[logical block] (when
+// lfpart is set) ...
+template <int DIM, int NP, int EPB>
+__global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
+nsk_lift_kernel(const double* __restrict__ U, double* __restrict__ G, BasisArgs bas, MeshArgs msh, PhysArgs ph,
+                double* __restrict__ lfpart) {
+  lift_block<DIM, NP, EPB, double, double, 1>(remap_block(blockIdx.x, gridDim.x, msh.nxcd), threadIdx.x, U, G, bas,
+                                              msh, ph, lfpart);
+}
+
+// ... the second lifting ...
+template <int DIM, int NP, int EPB>
+__global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
+lap_kernel(const double* __restrict__ U, double* __restrict__ G, BasisArgs bas, MeshArgs msh, PhysArgs ph) {
+  lap_block<DIM, NP, EPB>(remap_block(blockIdx.x, gridDim.x, msh.nxcd), threadIdx.x, U, G, bas, msh, ph);
+}
+
+// ... and the maximum of the n partial speeds into out[0] (one workgroup).
+constexpr int kMaxReduceThreads = 1024;
+template <int THREADS>
+__global__ void __launch_bounds__(THREADS)
+max_reduce_kernel(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double red[THREADS / 64];
+  const int tid = threadIdx.x;
+  double m = 0.0;
+  for (int i = tid; i < n; i += THREADS) m = fmax(m, part[i]);
+  block_max_store<THREADS>(m, red, out, tid);
 }
 
 // -------------------------------------------------------------------------
@@ -758,12 +950,13 @@ __device__ __forceinline__ double diag_combine(int k, double a, double b) {
   return k == 8 ? fmin(a, b) : ((k == 9 || k == 10 || k == 12) ? fmax(a, b) : a + b);
 }
 
-template <int DIM, int NP, typename GT>
+template <int DIM, int NP, typename GT, int MODEL = 0>
 __global__ void __launch_bounds__(kDiagThreads)
 diag_partial_kernel(const double* __restrict__ U, const GT* __restrict__ G, double* __restrict__ part,
                     const double* __restrict__ wq1, MeshArgs msh, PhysArgs ph) {
   using Sh = Shape<DIM, NP>;
-  constexpr int NN = Sh::NN, NV = Sh::NVAR, NT = Sh::NTAU;
+  constexpr int NN = Sh::NN, NT = Sh::NTAU;
+  constexpr int NV = MODEL == 1 ? DIM + 1 : DIM + 2;
   constexpr int EPBD = (kDiagThreads / NN) > 0 ? kDiagThreads / NN : 1;  // whole elements per group
   constexpr int SLOTS = EPBD * NN;
   __shared__ double red[kDiagSlots][kDiagThreads];
@@ -806,7 +999,9 @@ diag_partial_kernel(const double* __restrict__ U, const GT* __restrict__ G, doub
         if (!isfinite(u[v])) { acc[11] += 1.0; finite = false; }
         acc[v] += wgt * u[v];
       }
-      const double rho = u[0], c = u[DIM + 1];
+      // model II: c and its lifted gradient; original NSK: the lifted
+      // gradient of rho in the same slots, no relaxation energy
+      const double rho = u[0], c = MODEL == 0 ? u[NV - 1] : rho;
       double ek = 0.0, gc2 = 0.0;
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
@@ -820,7 +1015,13 @@ diag_partial_kernel(const double* __restrict__ U, const GT* __restrict__ G, doub
       if (finite) {
         acc[8] = fmin(acc[8], rho);
         acc[9] = fmax(acc[9], rho);
-        const double a = sound_speed<double>(rho, ph.T, ph.alpha);
+        double a;
+        if constexpr (MODEL == 1) {
+          const double q = 1.0 / (3.0 - rho), dp = 24.0 * ph.T * q * q - 6.0 * rho;
+          a = dp > 0.0 ? sqrt(dp) : 0.0;
+        } else {
+          a = sound_speed<double>(rho, ph.T, ph.alpha);
+        }
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
           const double sp = fabs(u[1 + d] / rho) + a;

@@ -143,6 +143,7 @@ struct nsk_ctx {
   // workspace layout (byte offsets)
   size_t off_U2 = 0, off_G = 0, off_h2[3] = {0, 0, 0}, off_wq = 0, off_order = 0, off_part = 0, off_out = 0;
   size_t off_cl = 0;  // closure source [dim+1][elem][node], FP32 (closure contexts only)
+  size_t off_lf = 0;  // original NSK path: global LF speed, then per-workgroup partial maxima
   size_t ws_bytes = 0;
   int diag_blocks = 0;
   int tile = 0;      // elements-per-workgroup variant
@@ -170,9 +171,16 @@ namespace {
 int check_params(const nsk_params* p) {
   if (!p) return NSK_EINVAL;
   if (!(p->T > 0.0 && p->T < 1.0)) return NSK_EINVAL;
-  if (!(p->alpha > 0.0) || !(p->beta > 0.0) || !(p->eps >= 0.0) || !(p->kappa >= 0.0)) return NSK_EINVAL;
-  if (!std::isfinite(p->alpha) || !std::isfinite(p->beta) || !std::isfinite(p->eps) || !std::isfinite(p->kappa))
+  if (!(p->eps >= 0.0) || !(p->kappa >= 0.0) || !std::isfinite(p->eps) || !std::isfinite(p->kappa))
     return NSK_EINVAL;
+  if (p->model == 1) {
+    // original NSK equations: global Lax-Friedrichs flux, FP64, no closure
+    if (p->flux != 2 || p->precision != 0 || p->closure != 0) return NSK_EINVAL;
+    return NSK_OK;
+  }
+  if (p->model != 0) return NSK_EINVAL;
+  if (!(p->alpha > 0.0) || !(p->beta > 0.0)) return NSK_EINVAL;
+  if (!std::isfinite(p->alpha) || !std::isfinite(p->beta)) return NSK_EINVAL;
   // model II is hyperbolic only for alpha > -min W''(rho) = 6 (1 - T), the
   // minimum of the reduced Van-der-Waals W'' being taken at rho = 1
   if (!(p->alpha > 6.0 * (1.0 - p->T))) return NSK_EINVAL;
@@ -262,10 +270,13 @@ PhysArgs phys_args(const nsk_ctx* c) {
   p.T = c->par.T;
   p.eps = c->par.eps;
   p.kappa = c->par.kappa;
-  p.alpha = c->par.alpha;
+  // the original NSK path has the plain Van-der-Waals pressure (alpha = 0)
+  // and no relaxation terms
+  const bool nsk = c->par.model == 1;
+  p.alpha = nsk ? 0.0 : c->par.alpha;
   p.beta = c->par.beta;
-  p.kb = c->par.kappa / c->par.beta;
-  p.ab = c->par.alpha / c->par.beta;
+  p.kb = nsk ? 0.0 : c->par.kappa / c->par.beta;
+  p.ab = nsk ? 0.0 : c->par.alpha / c->par.beta;
   p.diss_c = c->par.diss_c;
   p.flux = c->par.flux;
   p.rho_lo64 = c->rho_lo64;

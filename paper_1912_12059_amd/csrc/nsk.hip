@@ -11,6 +11,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/nsk.h"
@@ -43,8 +44,39 @@ ClosureArgs closure_args_of(const nsk_ctx* c) {
   return a;
 }
 
+// Original NSK path: first lifting (with the per-workgroup maxima of the
+// global Lax-Friedrichs speed), their reduction, the second lifting, then the
+// right-hand side with the global Lax-Friedrichs flux.
+template <int DIM, int NP, int EPB>
+int launch_stage_nsk(nsk_ctx* c, const double* Uin, double* Uout, double* dU, const StageArgs& st) {
+  using Tl = Tile<DIM, NP, EPB>;
+  const BasisArgs b = basis_args(c);
+  const MeshArgs m = mesh_args(c);
+  const PhysArgs p = phys_args(c);
+  double* G = reinterpret_cast<double*>(c->work + c->off_G);
+  double* lf = reinterpret_cast<double*>(c->work + c->off_lf);  // [0]: speed, [1..blocks]: partial maxima
+  const unsigned blocks = (unsigned)((c->E + EPB - 1) / EPB);
+  hipEvent_t* ev = stage_events(c, st);
+  if (ev) (void)hipEventRecord(ev[0], c->stream);
+  hipLaunchKernelGGL((nsk_lift_kernel<DIM, NP, EPB>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream, Uin, G, b, m, p,
+                     lf + 1);
+  if (ev) (void)hipEventRecord(ev[1], c->stream);
+  hipLaunchKernelGGL(max_reduce_kernel<kMaxReduceThreads>, dim3(1), dim3(kMaxReduceThreads), 0, c->stream, lf + 1, (int)blocks, lf);
+  hipLaunchKernelGGL((lap_kernel<DIM, NP, EPB>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream, Uin, G, b, m, p);
+  if (ev) (void)hipEventRecord(ev[2], c->stream);
+  StageArgs sta = st;
+  sta.lf = lf;
+  hipLaunchKernelGGL((rhs_kernel<DIM, NP, EPB, double, double, 2, 1>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream,
+                     Uin, G, Uout, dU, b, m, p, sta);
+  if (ev) (void)hipEventRecord(ev[3], c->stream);
+  return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
+}
+
 template <int DIM, int NP, int EPB, typename R, typename GT>
 int launch_stage_e(nsk_ctx* c, const double* Uin, double* Uout, double* dU, const StageArgs& st) {
+  if constexpr (std::is_same<R, double>::value) {
+    if (c->par.model == 1) return launch_stage_nsk<DIM, NP, EPB>(c, Uin, Uout, dU, st);
+  }
   using Tl = Tile<DIM, NP, EPB>;
   const BasisArgs b = basis_args(c);
   const MeshArgs m = mesh_args(c);
@@ -97,13 +129,27 @@ int launch_diag_t(nsk_ctx* c, const double* Uin) {
   GT* G = reinterpret_cast<GT*>(c->work + c->off_G);
   const unsigned blocks = (unsigned)((c->E + EPB - 1) / EPB);
   using R = GT;
-  hipLaunchKernelGGL((lift_kernel<DIM, NP, EPB, R, GT>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream, Uin, G, b, m,
-                     p);
   double* part = reinterpret_cast<double*>(c->work + c->off_part);
   double* out = reinterpret_cast<double*>(c->work + c->off_out);
   const double* wq = reinterpret_cast<const double*>(c->work + c->off_wq);
-  hipLaunchKernelGGL((diag_partial_kernel<DIM, NP, GT>), dim3(c->diag_blocks), dim3(kDiagThreads), 0, c->stream, Uin,
-                     G, part, wq, m, p);
+  bool done = false;
+  if constexpr (std::is_same<GT, double>::value) {
+    if (c->par.model == 1) {
+      // the lifted gradient of rho for the capillary energy; the speed is
+      // reduced by the diagnostics kernel itself
+      hipLaunchKernelGGL((nsk_lift_kernel<DIM, NP, EPB>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream, Uin, G, b, m,
+                         p, nullptr);
+      hipLaunchKernelGGL((diag_partial_kernel<DIM, NP, GT, 1>), dim3(c->diag_blocks), dim3(kDiagThreads), 0,
+                         c->stream, Uin, G, part, wq, m, p);
+      done = true;
+    }
+  }
+  if (!done) {
+    hipLaunchKernelGGL((lift_kernel<DIM, NP, EPB, R, GT>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream, Uin, G, b,
+                       m, p);
+    hipLaunchKernelGGL((diag_partial_kernel<DIM, NP, GT>), dim3(c->diag_blocks), dim3(kDiagThreads), 0, c->stream,
+                       Uin, G, part, wq, m, p);
+  }
   hipLaunchKernelGGL(diag_final_kernel<kDiagSlots>, dim3(1), dim3(kDiagThreads), 0, c->stream, part, c->diag_blocks,
                      out);
   return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
@@ -191,7 +237,7 @@ int nsk_create(const nsk_mesh* mesh, const nsk_params* params, nsk_ctx** out) {
   c->np = mesh->N + 1;
   c->nn = 1;
   for (int d = 0; d < c->dim; ++d) c->nn *= c->np;
-  c->nvar = c->dim + 2;
+  c->nvar = c->dim + (c->par.model == 1 ? 1 : 2);
   c->ng = c->dim * (c->dim + 1) / 2 + c->dim;
   c->E = 1;
   for (int d = 0; d < 3; ++d) {
@@ -250,6 +296,12 @@ int nsk_create(const nsk_mesh* mesh, const nsk_params* params, nsk_ctx** out) {
   if (c->par.closure == 1) {
     c->off_cl = off;
     off = align256(off + sizeof(float) * (size_t)(c->dim + 1) * c->S);
+  }
+  if (c->par.model == 1) {
+    // global LF speed and one partial maximum per lifting workgroup (at
+    // most one workgroup per element)
+    c->off_lf = off;
+    off = align256(off + sizeof(double) * (size_t)(c->E + 1));
   }
   c->ws_bytes = off;
   // default launch shape: tiled work order in 3D, natural order otherwise
@@ -413,6 +465,24 @@ int nsk_dt_estimate(nsk_ctx* c, double cfl, double* dt_out) {
   if (rc) return rc;
   if (h[11] > 0.0) return NSK_ENONPHYS;
   const double N2 = 2.0 * c->N + 1.0;
+  if (c->par.model == 1) {
+    // original NSK: convective bound with the global LF speed, viscous bound,
+    // and the bound of the capillary modes (frequencies sqrt(kappa rho) k^2)
+    double s1 = 0.0, s2 = 0.0;  // max_e sum_d 1/h_d and 1/h_d^2
+    for (int d = 0; d < c->dim; ++d) {
+      double m = 0.0;
+      for (double x : c->h2[d]) m = std::fmax(m, 0.5 * x);
+      s1 += m;
+      s2 += m * m;
+    }
+    const double lam = h[10], rmax = h[9];
+    double dt = INFINITY;
+    if (lam > 0.0) dt = std::fmin(dt, 1.0 / (N2 * lam * s1));
+    if (c->par.eps > 0.0) dt = std::fmin(dt, 1.0 / (N2 * N2 * c->par.eps * s2));
+    if (c->par.kappa > 0.0) dt = std::fmin(dt, 0.25 / (N2 * N2 * std::sqrt(c->par.kappa * rmax) * s2));
+    *dt_out = cfl * dt;
+    return NSK_OK;
+  }
   const double lam_c = h[12];
   double lam_v = 0.0;
   const double lv = std::fmax(c->par.eps, c->par.kappa / c->par.beta);
@@ -490,8 +560,9 @@ int nsk_set_params(nsk_ctx* c, const nsk_params* p) {
   if (!c) return NSK_EINVAL;
   int rc = check_params(p);
   if (rc) return rc;
-  // the workspace layout depends on the precision and the closure flag
-  if (p->precision != c->par.precision || p->closure != c->par.closure) return NSK_EINVAL;
+  // the workspace layout depends on the model, the precision and the closure flag
+  if (p->model != c->par.model || p->precision != c->par.precision || p->closure != c->par.closure)
+    return NSK_EINVAL;
   c->par = *p;
   spinodal_band(c->par.T, c->rho_lo64, c->rho_hi64);
   return NSK_OK;

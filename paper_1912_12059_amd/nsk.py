@@ -50,6 +50,7 @@ class nsk_params(C.Structure):
         ("diss_c", C.c_int),
         ("precision", C.c_int),
         ("closure", C.c_int),
+        ("model", C.c_int),
     ]
 
 
@@ -165,10 +166,15 @@ def make_mesh(dim, N, nel, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), xbreaks=None)
     return m, keep
 
 
-def make_params(T=0.85, eps=1e-3, kappa=1e-5, alpha=500.0, beta=1e-3, diss_c=1, precision=0, flux=0, closure=0):
+def make_params(T=0.85, eps=1e-3, kappa=1e-5, alpha=500.0, beta=1e-3, diss_c=1, precision=0, flux=0, closure=0,
+                model=0):
+    """model 0: relaxation model II; model 1: the original NSK equations
+    (flux 2, the global Lax-Friedrichs flux, is then the default)."""
     p = nsk_params()
     p.T, p.eps, p.kappa, p.alpha, p.beta = T, eps, kappa, alpha, beta
-    p.flux, p.diss_c, p.precision, p.closure = flux, diss_c, precision, closure
+    if model == 1 and flux == 0:
+        flux = 2
+    p.flux, p.diss_c, p.precision, p.closure, p.model = flux, diss_c, precision, closure, model
     return p
 
 
@@ -377,6 +383,7 @@ class Solver:
     precision: int = 0
     flux: int = 0
     closure: int = 0
+    model: int = 0  # 0: relaxation model II, 1: original NSK (state rho, rho v)
     xbreaks: list | None = None
     device: str = "cuda:0"
     stream: object = None
@@ -387,11 +394,11 @@ class Solver:
 
         mesh, keep = make_mesh(self.dim, self.N, self.nel, self.lo, self.hi, self.xbreaks)
         params = make_params(self.T, self.eps, self.kappa, self.alpha, self.beta, self.diss_c, self.precision,
-                             flux=self.flux, closure=self.closure)
+                             flux=self.flux, closure=self.closure, model=self.model)
         self.ctx = nsk_create(mesh, params)
         del keep
         n = nsk_state_size(self.ctx)
-        self.nvar = self.dim + 2
+        self.nvar = self.dim + (1 if self.model == 1 else 2)
         self.nnode = (self.N + 1) ** self.dim
         self.nelem = n // (self.nvar * self.nnode)
         dev = torch.device(self.device)

@@ -148,3 +148,43 @@ def test_closure_host_side_checks():
     finally:
         nsk.nsk_destroy(plain)
         nsk.nsk_destroy(cl)
+
+
+def test_nsk_model_host_side_checks():
+    """Original NSK path (model 1): state (rho, rho v), global Lax-Friedrichs
+    flux only, FP64 only, no closure, alpha and beta unused; the batched form
+    and the parameter changes that alter the workspace layout are refused."""
+    m, keep = _ok_mesh()
+    p = nsk.make_params(model=1, alpha=0.0, beta=0.0)
+    assert p.flux == 2
+    ctx = nsk.nsk_create(m, p)
+    try:
+        assert nsk.nsk_state_size(ctx) == 4 * 24 * 125
+        plain = nsk.nsk_create(m, nsk.make_params())
+        # the LF speed and its per-workgroup partial maxima live in the workspace
+        assert nsk.nsk_workspace_bytes(ctx) >= 8 * (24 + 1)
+        nsk.nsk_destroy(plain)
+        with pytest.raises(nsk.NskError):
+            nsk.nsk_set_params(ctx, nsk.make_params())  # model 0: other state layout
+        nsk.nsk_set_params(ctx, nsk.make_params(model=1, eps=2e-3, kappa=1e-4))
+    finally:
+        nsk.nsk_destroy(ctx)
+    for bad in (dict(flux=0), dict(flux=1), dict(precision=1), dict(closure=1), dict(kappa=-1.0),
+                dict(eps=float("nan"))):
+        q = nsk.make_params(model=1)
+        for k, v in bad.items():
+            setattr(q, k, v)
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_create(m, q)
+        assert e.value.code == nsk.NSK_EINVAL, bad
+    q = nsk.make_params()
+    q.model = 2
+    with pytest.raises(nsk.NskError):
+        nsk.nsk_create(m, q)
+    q = nsk.make_params(flux=2)  # the global LF flux is not a model II flux
+    with pytest.raises(nsk.NskError):
+        nsk.nsk_create(m, q)
+    bm, bkeep = nsk.make_mesh(3, 3, (2, 2, 2))
+    with pytest.raises(nsk.NskError) as e:
+        nsk.nsk_batch_create([bm], nsk.make_params(model=1))
+    assert e.value.code == nsk.NSK_EUNSUPPORTED

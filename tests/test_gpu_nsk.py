@@ -1,0 +1,232 @@
+"""GPU parity of the original NSK path (model 1: Korteweg stress, second BR1
+lifting, global Lax-Friedrichs flux) against the CPU oracle, through the C
+ABI.
+
+Right-hand sides: per variable, |R_gpu - R_cpu| <= RHS_ULPS ulps of the
+largest term summed into R (tests/tolerances.py, term_scales_nsk, which adds
+the round-off growth of the two liftings through the third-order term).
+Trajectories: relative max-norm difference per variable <= 1e-10."""
+import numpy as np
+import pytest
+
+from paper_1912_12059_amd import inputs as I
+from tolerances import RHS_ULPS, rhs_err_ulps, term_scales_nsk
+
+pytestmark = pytest.mark.gpu
+
+TRAJ_TOL = 1e-10
+PHYS = dict(T=0.85, eps=1e-3, kappa=1e-4)
+
+
+def _problem(O, m, **kw):
+    nel = tuple(m.nel) + (1,) * (3 - len(m.nel))
+    lo = tuple(m.lo) + (0.0,) * (3 - len(m.lo))
+    hi = tuple(m.hi) + (1.0,) * (3 - len(m.hi))
+    return O.Problem(dim=m.dim, N=m.N, nel=nel, lo=lo, hi=hi, xbreaks=m.xbreaks, model=1, **kw)
+
+
+def _solver(gpu, m, **kw):
+    return gpu.Solver(dim=m.dim, N=m.N, nel=tuple(m.nel), lo=tuple(m.lo) + (0.0,) * 3,
+                      hi=tuple(m.hi) + (1.0,) * 3, xbreaks=m.xbreaks, model=1, flux=2, **kw)
+
+
+def _nsk_state(U):
+    """(rho, m) of a model II state (drops c)."""
+    return np.ascontiguousarray(U[:-1])
+
+
+def _rhs_check(O, P, U, R, Rc, kw):
+    ulps = rhs_err_ulps(R, Rc, term_scales_nsk(O, P, U, kw["kappa"], kw["eps"]))
+    assert ulps <= RHS_ULPS, f"{ulps:.1f} ulps of the term scale"
+
+
+def _relerr_per_var(a, b):
+    a = np.asarray(a).reshape(b.shape)
+    out = []
+    for v in range(b.shape[0]):
+        scale = np.max(np.abs(b[v]))
+        out.append(np.max(np.abs(a[v] - b[v])) / (scale if scale > 0 else 1.0))
+    return max(out)
+
+
+@pytest.mark.parametrize("dim,N,nel", [
+    (1, 1, (7,)), (1, 3, (64,)), (1, 6, (5,)),
+    (2, 2, (5, 4)), (2, 4, (7, 6)), (2, 5, (3, 4)),
+    (3, 1, (4, 3, 5)), (3, 2, (5, 3, 2)), (3, 3, (4, 3, 3)), (3, 4, (3, 4, 3)), (3, 5, (3, 2, 3)),
+])
+def test_nsk_rhs_parity_smooth(O, gpu, dim, N, nel):
+    m, U = I.smooth_random(dim, N, nel, seed=111 + dim * 7 + N)
+    U = _nsk_state(U)
+    s = _solver(gpu, m, **PHYS)
+    R = s.rhs(U).cpu().numpy()
+    P = _problem(O, m, **PHYS)
+    _rhs_check(O, P, U, R, O.rhs(P, U), PHYS)
+    s.close()
+
+
+@pytest.mark.parametrize("kappa", [0.0, 1e-5, 1e-3])
+def test_nsk_rhs_parity_nonuniform(O, gpu, kappa):
+    g = np.random.Generator(np.random.PCG64(5))
+    nel = (6, 5, 4)
+    xb = []
+    for d in range(3):
+        x = np.linspace(0.0, 1.0, nel[d] + 1)
+        x[1:-1] += g.uniform(-0.25, 0.25, nel[d] - 1) / nel[d]
+        xb.append(x)
+    m, U = I.smooth_random(3, 3, nel, seed=9, xbreaks=xb)
+    U = _nsk_state(U)
+    kw = dict(PHYS, kappa=kappa)
+    s = _solver(gpu, m, **kw)
+    R = s.rhs(U).cpu().numpy()
+    P = _problem(O, m, **kw)
+    _rhs_check(O, P, U, R, O.rhs(P, U), kw)
+    s.close()
+
+
+def test_nsk_rhs_parity_droplets_2d(O, gpu):
+    """The two-droplet 2D geometry (96x96 elements, N=4) as an NSK state."""
+    m, U = I.droplets_2d()
+    U = _nsk_state(U)
+    kw = dict(PHYS, kappa=1e-5)
+    s = _solver(gpu, m, **kw)
+    R = s.rhs(U).cpu().numpy()
+    P = _problem(O, m, **kw)
+    _rhs_check(O, P, U, R, O.rhs(P, U), kw)
+    s.close()
+
+
+def test_nsk_trajectory_1d(O, gpu):
+    """The 1D slab (64 elements, N=3) as an NSK state, 400 steps at the
+    rule's time step."""
+    m, U = I.slab_1d()
+    U = _nsk_state(U)
+    P = _problem(O, m, **PHYS)
+    dt = O.dt(P, U, 0.5)
+    s = _solver(gpu, m, **PHYS)
+    s.set_state(U)
+    dt_gpu = s.dt_estimate(0.5)
+    assert abs(dt_gpu - dt) <= 1e-12 * dt
+    s.rk_step(dt, 400)
+    got = s.get_state().cpu().numpy()
+    ref = O.run(P, U, dt, 400)
+    assert _relerr_per_var(got, ref) <= TRAJ_TOL
+
+
+def test_nsk_trajectory_3d_collision_small(O, gpu):
+    """3D head-on collision geometry on 12x6x6 elements, N=4, 10 steps."""
+    m, U = I.collision_3d(nel=(12, 6, 6), N=4, We=100.0)
+    U = _nsk_state(U)
+    P = _problem(O, m, **PHYS)
+    dt = O.dt(P, U, 0.5)
+    s = _solver(gpu, m, **PHYS)
+    s.set_state(U)
+    assert abs(s.dt_estimate(0.5) - dt) <= 1e-12 * dt
+    s.rk_step(dt, 10)
+    got = s.get_state().cpu().numpy()
+    ref = O.run(P, U, dt, 10)
+    assert _relerr_per_var(got, ref) <= TRAJ_TOL
+
+
+def test_nsk_diagnostics_parity(O, gpu):
+    m, U = I.smooth_random(2, 4, (6, 5), seed=121)
+    U = _nsk_state(U)
+    s = _solver(gpu, m, **PHYS)
+    s.set_state(U)
+    d = s.diagnostics()
+    dc = O.diagnostics(_problem(O, m, **PHYS), U)
+    np.testing.assert_allclose(d["mass"], dc["mass"], rtol=1e-13, atol=1e-15)
+    for k in ("e_kin", "e_total", "rho_min", "rho_max", "max_wavespeed"):
+        assert d[k] == pytest.approx(dc[k], rel=1e-12), k
+    assert d["l2_rho_minus_c"] == 0.0
+    assert d["nonfinite"] == 0 and d["status"] == 0
+
+
+def test_nsk_conserves_mass_and_momentum_gpu(O, gpu):
+    """Mass and momentum are conserved by the scheme (all terms in divergence
+    form); over 200 steps they drift by round-off only.  The state lies in the
+    liquid phase: a state across the spinodal interval separates into phases
+    whose interfaces (width 2 sqrt(kappa)) this coarse grid cannot resolve."""
+    m, U = I.smooth_random(3, 3, (5, 4, 3), seed=3, rho_range=(1.6, 1.9))
+    U = _nsk_state(U)
+    s = _solver(gpu, m, **PHYS)
+    s.set_state(U)
+    d0 = s.diagnostics()
+    dt = s.dt_estimate(0.5)
+    s.rk_step(dt, 200)
+    d1 = s.diagnostics()
+    assert d1["status"] == 0
+    assert abs(d1["mass"][0] - d0["mass"][0]) <= 1e-13 * abs(d0["mass"][0])
+    scale = max(abs(x) for x in d0["mass"][1:]) + abs(d0["mass"][0])
+    for k in range(1, 4):
+        assert abs(d1["mass"][k] - d0["mass"][k]) <= 1e-12 * scale
+    s.close()
+
+
+@pytest.mark.parametrize("dim,N,nel", [(1, 3, (37,)), (2, 4, (13, 11)), (3, 3, (7, 5, 3)), (3, 4, (5, 5, 3))])
+def test_nsk_launch_shapes_bitwise_identical(gpu, dim, N, nel):
+    """Every launch shape gives the same bits, for ragged element counts;
+    the global speed reduction is a maximum, which does not depend on the
+    order of the partial results."""
+    m, U = I.smooth_random(dim, N, nel, seed=140 + N)
+    U = _nsk_state(U)
+    outs = []
+    for variant in (0, 1):
+        for order in range(6):
+            s = _solver(gpu, m, **PHYS)
+            gpu.nsk_set_tile(s.ctx, variant, order)
+            s.set_state(U)
+            s.rk_step(1e-5, 3)
+            outs.append(s.get_state().cpu().numpy())
+            s.close()
+    assert np.all(np.isfinite(outs[0]))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_nsk_full_size_3d_sampled(O, gpu):
+    """The 96x48x48, N=4 collision (27.6M nodes) as an NSK state on the GPU,
+    in the launch configuration the benchmark times.  Sampled elements are
+    recomputed by the oracle on a 7x7x7-element periodic patch centred on each
+    sample (the right-hand side of an element depends on elements at most
+    three away: Sigma of a face neighbour needs its lap rho, which needs grad
+    rho one element further, which needs rho one more), with the global
+    Lax-Friedrichs speed of the whole state."""
+    import torch
+
+    nel = (96, 48, 48)
+    m, U = I.collision_3d(nel=nel, N=4, We=100.0)
+    U = _nsk_state(U)
+    kw = dict(PHYS, kappa=1e-5)
+    s = _solver(gpu, m, **kw)
+    gpu.nsk_set_tile(s.ctx, 0, 4)
+    Ut = torch.from_numpy(U.reshape(-1)).to("cuda:0")
+    R = torch.empty_like(Ut)
+    gpu.nsk_rhs(s.ctx, Ut.data_ptr(), R.data_ptr(), 0.0)
+    torch.cuda.synchronize()
+    R = R.reshape(U.shape)
+    h = [(m.hi[d] - m.lo[d]) / nel[d] for d in range(3)]
+    Pfull = O.Problem(dim=3, N=4, nel=nel, lo=(0, 0, 0), hi=tuple(m.hi), model=1, **kw)
+    lam = O.lf_speed(Pfull, U)
+    g = np.random.Generator(np.random.PCG64(177))
+    rho = U[0]
+    inter = np.where((rho.max(axis=1) > 1.0) & (rho.min(axis=1) < 1.0))[0]
+    samples = list(g.choice(inter, 10, replace=False)) + list(g.integers(0, m.nelem, 3))
+    Pp = O.Problem(dim=3, N=4, nel=(7, 7, 7), lo=(0, 0, 0), hi=(7 * h[0], 7 * h[1], 7 * h[2]), model=1, **kw)
+    for e in samples:
+        ex, ey, ez = e % nel[0], (e // nel[0]) % nel[1], e // (nel[0] * nel[1])
+        idx = [[(c + k) % nel[d] for k in range(-3, 4)] for d, c in enumerate((ex, ey, ez))]
+        patch = np.empty((4, 343, 125))
+        pe = 0
+        for kz in idx[2]:
+            for ky in idx[1]:
+                for kx in idx[0]:
+                    patch[:, pe, :] = U[:, kx + nel[0] * (ky + nel[1] * kz), :]
+                    pe += 1
+        Rp = O.rhs(Pp, patch, lf_speed=lam)
+        centre = 3 + 7 * (3 + 7 * 3)
+        got = R[:, e, :].cpu().numpy()
+        ref = Rp[:, centre, :]
+        scales = term_scales_nsk(O, Pp, patch, kw["kappa"], kw["eps"])
+        ulps = rhs_err_ulps(got, ref, scales)
+        assert ulps <= RHS_ULPS, (e, ulps)
+    s.close()

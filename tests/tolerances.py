@@ -32,3 +32,31 @@ def rhs_err_ulps(R_test, R_ref, scales):
     R_test = np.asarray(R_test).reshape(R_ref.shape)
     d = np.abs(R_test - R_ref).reshape(R_ref.shape[0], -1).max(axis=1)
     return float(np.max(d / (2.0 ** -53 * scales)))
+
+
+def term_scales_nsk(O, P, U, kappa, eps, T=0.85):
+    """The same bound for the original NSK path (state rho, m; P a model-1
+    oracle problem).  The momentum flux adds the second-order stress
+    Sigma = eps tau + kappa ((rho lap + |g|^2/2) I - g g^T), g = grad rho,
+    sized from the oracle's liftings, and the round-off of the two liftings
+    grows through the third-order term: an error of one ulp in rho becomes
+    K ulps in g and K (|g| + K rho) in lap rho, K = (2/h_min) C_D."""
+    b = O.basis(P.N)
+    cD = max(np.abs(b.Dhat).sum(axis=1).max(), (np.abs(b.Lp) + np.abs(b.Lm)).max() / b.w.min())
+    h_min = min(float(np.diff(P.breaks(d)).min()) for d in range(P.dim))
+    K = 2.0 / h_min * cD
+    dim = P.dim
+    rho = U[0]
+    rmax = float(np.abs(rho).max())
+    vmax = max(float(np.abs(U[1 + d] / rho).max()) for d in range(dim))
+    mmax = max(float(np.abs(U[1 + d]).max()) for d in range(dim))
+    pmax = max(abs(O.pressure(T, r)) for r in (float(rho.min()), rmax, 1.0))
+    lam = O.lf_speed(P, U)
+    _, Q, lap = O.rhs(P, U, return_Q=True)
+    gmax = float(np.abs(Q[:, dim]).max())
+    dvmax = float(np.abs(Q[:, :dim]).max())
+    sig = 2.0 * eps * dvmax * dim + kappa * (rmax * float(np.abs(lap).max()) + 1.5 * dim * gmax ** 2)
+    lift_err = kappa * rmax * K * (gmax + K * rmax) + kappa * gmax * K * rmax
+    s_rho = K * (mmax + lam * rmax)
+    s_m = K * (mmax * vmax + pmax + lam * mmax + sig + lift_err)
+    return np.array([s_rho] + [s_m] * dim)
