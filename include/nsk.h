@@ -63,6 +63,7 @@ extern "C" {
 #define NSK_EHIP (-3)      /* HIP runtime error                              */
 #define NSK_EUNBOUND (-4)  /* device memory not bound yet                    */
 #define NSK_EUNSUPPORTED (-5) /* degree/dimension combination not built      */
+#define NSK_ENOCONV (-6)   /* implicit stage equations did not converge      */
 
 typedef struct nsk_ctx nsk_ctx;
 
@@ -202,6 +203,55 @@ int nsk_set_params(nsk_ctx* ctx, const nsk_params* params);
  * nsk_timing_enable(ctx, 0) stops recording and releases the events. */
 int nsk_timing_enable(nsk_ctx* ctx, int enable);
 int nsk_timing_read(nsk_ctx* ctx, double out[4]);
+
+/* ------------------------------------------------------------------------
+ * Implicit time stepping (Sec. 3.1: the implicit runs use a six-stage,
+ * fourth-order ESDIRK scheme): Kennedy and Carpenter's ARK4(3)6L[2]SA
+ * implicit tableau, gamma = 1/4, explicit first stage, stiffly accurate.
+ * For stage i = 2..6 the equation X - dt gamma R(X) = B_i,
+ * B_i = U_n + dt sum_{j<i} a_ij K_j, is solved by Newton's method (initial
+ * guess B_i + dt gamma K_{i-1}); each Newton correction comes from one cycle
+ * of right-preconditioned GMRES (at most gmres_m Krylov vectors, classical
+ * Gram-Schmidt applied twice) with the Jacobian-vector product
+ * (R(X + s z) - R(X))/s, s = sqrt(eps_machine)(1 + |X|_2).  K_i = (X - B_i)/
+ * (dt gamma); U_{n+1} is the last stage.  Works on FP64 contexts of either
+ * model without the closure.
+ * ------------------------------------------------------------------------ */
+#define NSK_GMRES_MAX 64
+typedef struct {
+  double newton_tol; /* stage converged when |B + dt gamma R(X) - X|_2 <= newton_tol |B|_2 */
+  int newton_max;    /* Newton corrections per stage, 1..1000                  */
+  double gmres_rtol; /* GMRES stops when the residual falls by this factor, (0,1) */
+  int gmres_m;       /* Krylov vectors per GMRES cycle, 1..NSK_GMRES_MAX         */
+  int precond;       /* 1: node-local inverse of the stiff relaxation source
+                        (model II only): c -> (c + a rho)/(1 + a),
+                        a = dt gamma alpha/beta; 0: none                        */
+} nsk_implicit_opts;
+
+typedef struct {
+  long long steps;        /* steps completed                                  */
+  long long rhs_evals;    /* right-hand-side evaluations                      */
+  long long newton_iters; /* Newton corrections                               */
+  long long gmres_iters;  /* Jacobian-vector products (GMRES iterations)      */
+  double max_residual;    /* largest final relative stage residual            */
+  int converged;          /* 1 if every stage met newton_tol                  */
+} nsk_implicit_stats;
+
+/* Bytes of the device workspace nsk_esdirk_step needs (in addition to the
+ * bound workspace): (gmres_m + 9) state vectors plus reduction scratch.
+ * 0 for invalid arguments. */
+size_t nsk_implicit_workspace_bytes(const nsk_ctx* ctx, int gmres_m);
+
+/* Advances the bound state by nsteps ESDIRK4(6) steps of size dt.  d_iwork:
+ * caller-owned device memory of nsk_implicit_workspace_bytes(ctx,
+ * opts->gmres_m) bytes, 256-byte aligned.  Synchronises the stream after
+ * every Arnoldi step (the host needs the dot products).  Returns
+ * NSK_ENOCONV, with the state left at the last completed step, when a stage
+ * misses newton_tol after newton_max corrections; NSK_EUNSUPPORTED for mixed
+ * precision or closure contexts; NSK_EINVAL for invalid options or precond 1
+ * on a model 1 context.  stats_out (may be NULL) receives the counts. */
+int nsk_esdirk_step(nsk_ctx* ctx, void* d_iwork, double dt, int nsteps, const nsk_implicit_opts* opts,
+                    nsk_implicit_stats* stats_out);
 
 /* ------------------------------------------------------------------------
  * Learned closure (no counterpart in the paper; the paper's model II is the

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 REPO = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libnsk.so")
-SOURCES = [os.path.join(HERE, "csrc", n) for n in ("nsk.hip", "batch.hip", "closure.hip")]
+SOURCES = [os.path.join(HERE, "csrc", n) for n in ("nsk.hip", "batch.hip", "closure.hip", "implicit.hip")]
 DEPENDS = SOURCES + [
     os.path.join(HERE, "csrc", "dg_kernels.hpp"),
     os.path.join(HERE, "csrc", "closure.hpp"),

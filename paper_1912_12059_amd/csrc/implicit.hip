@@ -1,0 +1,416 @@
+// libnsk: implicit time stepping with the six-stage fourth-order ESDIRK
+// scheme named in Sec. 3.1 for the implicit runs (Kennedy and Carpenter's
+// ARK4(3)6L[2]SA implicit tableau: gamma = 1/4, explicit first stage,
+// stiffly accurate), with a Jacobian-free Newton-Krylov solver for the stage
+// equations.
+//
+// One step from U_n:  K_1 = R(U_n); for stage i = 2..6 solve
+//   G(X) = X - dt gamma R(X) - B_i = 0,   B_i = U_n + dt sum_{j<i} a_ij K_j,
+// by Newton's method, each correction from one cycle of right-preconditioned
+// GMRES with classical Gram-Schmidt applied twice and the Jacobian-vector
+// product (R(X + s z) - R(X)) / s; then K_i = (X - B_i)/(dt gamma); U_{n+1}
+// is the last stage's X.  Every right-hand side is nsk_rhs on the bound
+// context; the vector work runs in the kernels below, with fixed-order
+// reductions, so a run is bitwise reproducible.  The host reads back only
+// the dot products of each Arnoldi step.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "../../include/nsk.h"
+#include "host_common.hpp"
+
+using namespace nsk;
+
+namespace {
+
+constexpr int kVecThreads = 256;
+constexpr int kDotBlocks = 1024;  // partial sums per dot product
+constexpr int kLinTerms = 8;      // vectors per linear-combination launch
+
+struct LinArgs {
+  const double* x[kLinTerms];
+  double a[kLinTerms];
+  int nk;
+};
+
+// y[i] = sum_k a_k x_k[i] (y may be one of the x_k: each entry is read before
+// it is written by the same thread)
+__global__ void __launch_bounds__(kVecThreads) lincomb_kernel(LinArgs L, double* __restrict__ y, long long n) {
+  const long long stride = (long long)gridDim.x * kVecThreads;
+  for (long long i = (long long)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride) {
+    double s = 0.0;
+    for (int k = 0; k < L.nk; ++k) s += L.a[k] * L.x[k][i];
+    y[i] = s;
+  }
+}
+
+// part[b * ld + j] = sum over block b's contiguous chunk of w[i] * v_j[i],
+// v_j = V + j * vstride, for j < nj <= kLinTerms
+__global__ void __launch_bounds__(kVecThreads) multidot_kernel(const double* __restrict__ w,
+                                                               const double* __restrict__ V, long long vstride,
+                                                               int nj, long long n, double* __restrict__ part,
+                                                               int ld) {
+  __shared__ double red[kLinTerms][kVecThreads / 64];
+  const long long chunk = (n + gridDim.x - 1) / gridDim.x;
+  const long long beg = (long long)blockIdx.x * chunk;
+  const long long end = beg + chunk < n ? beg + chunk : n;
+  double s[kLinTerms];
+#pragma unroll
+  for (int j = 0; j < kLinTerms; ++j) s[j] = 0.0;
+  for (long long i = beg + threadIdx.x; i < end; i += kVecThreads) {
+    const double wi = w[i];
+#pragma unroll
+    for (int j = 0; j < kLinTerms; ++j)
+      if (j < nj) s[j] += wi * V[j * vstride + i];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < kLinTerms; ++j) {
+    double v = s[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) red[j][wv] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < nj) {
+    double t = 0.0;
+    for (int k = 0; k < kVecThreads / 64; ++k) t += red[threadIdx.x][k];
+    part[(long long)blockIdx.x * ld + threadIdx.x] = t;
+  }
+}
+
+// out[j] = sum_b part[b * ld + j] in a fixed order; one workgroup per j
+__global__ void __launch_bounds__(kVecThreads) dot_final_kernel(const double* __restrict__ part, int nb, int ld,
+                                                                double* __restrict__ out) {
+  __shared__ double red[kVecThreads];
+  const int j = blockIdx.x;
+  double t = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kVecThreads) t += part[(long long)b * ld + j];
+  red[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = kVecThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = red[0];
+}
+
+// Node-local preconditioner of the relaxation source (model II): with
+// a = dt gamma alpha / beta the stiff part of I - dt gamma dR/dU at a node is
+// identity except the c row, (1 + a) c - a rho; its inverse maps v to v with
+// c replaced by (v_c + a v_rho) / (1 + a).
+struct Precond {
+  int on;
+  int ci;      // index of the c variable
+  double a;
+  long long S; // entries per variable
+};
+
+__device__ __forceinline__ double pinv(const double* __restrict__ v, long long i, const Precond& p) {
+  if (p.on && i / p.S == p.ci) {
+    const long long o = i - (long long)p.ci * p.S;
+    return (v[i] + p.a * v[o]) / (1.0 + p.a);
+  }
+  return v[i];
+}
+
+// Xp = X + s P^{-1} v
+__global__ void __launch_bounds__(kVecThreads) perturb_kernel(const double* __restrict__ X,
+                                                              const double* __restrict__ v, double s, Precond p,
+                                                              double* __restrict__ Xp, long long n) {
+  const long long stride = (long long)gridDim.x * kVecThreads;
+  for (long long i = (long long)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride)
+    Xp[i] = X[i] + s * pinv(v, i, p);
+}
+
+// w = P^{-1} v - c (Rp - RX): the Jacobian-vector product of G, c = dt gamma / s
+__global__ void __launch_bounds__(kVecThreads) jvp_kernel(const double* __restrict__ v,
+                                                          const double* __restrict__ Rp,
+                                                          const double* __restrict__ RX, double c, Precond p,
+                                                          double* __restrict__ w, long long n) {
+  const long long stride = (long long)gridDim.x * kVecThreads;
+  for (long long i = (long long)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride)
+    w[i] = pinv(v, i, p) - c * (Rp[i] - RX[i]);
+}
+
+// X += P^{-1} Y
+__global__ void __launch_bounds__(kVecThreads) correct_kernel(double* __restrict__ X, const double* __restrict__ Y,
+                                                              Precond p, long long n) {
+  const long long stride = (long long)gridDim.x * kVecThreads;
+  for (long long i = (long long)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride)
+    X[i] += pinv(Y, i, p);
+}
+
+// ESDIRK4(6) implicit tableau (lower triangle with the diagonal gamma), gamma = 1/4.
+constexpr double kGamma = 0.25;
+const double kA[6][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 4, 0.25, 0, 0, 0, 0},
+    {8611.0 / 62500, -1743.0 / 31250, 0.25, 0, 0, 0},
+    {5012029.0 / 34652500, -654441.0 / 2922500, 174375.0 / 388108, 0.25, 0, 0},
+    {15267082809.0 / 155376265600, -71443401.0 / 120774400, 730878875.0 / 902184768, 2285395.0 / 8070912, 0.25,
+     0},
+    {82889.0 / 524892, 0.0, 15625.0 / 83664, 69875.0 / 102672, -2260.0 / 8211, 0.25},
+};
+
+// Workspace vectors (each M doubles, padded to 256 bytes)
+enum { vK0 = 0, vB = 5, vX, vRX, vR, vXp, vRp, vY, vV0 };
+
+struct Solver {
+  nsk_ctx* c;
+  char* base;
+  long long M;       // doubles per state vector
+  long long stride;  // doubles between workspace vectors
+  int m;
+  double* part;
+  double* dots;
+  hipStream_t st;
+  Precond pre;
+  nsk_implicit_stats* stats;
+
+  double* vec(int k) const { return reinterpret_cast<double*>(base) + (long long)k * stride; }
+  double* V(int k) const { return vec(vV0 + k); }
+  unsigned grid() const {
+    const long long b = (M + kVecThreads - 1) / kVecThreads;
+    return (unsigned)(b < 8192 ? b : 8192);
+  }
+
+  int lin(double* y, int nk, const double* const* x, const double* a) {
+    // chains of kLinTerms terms: y = sum; later chunks add onto y
+    int k0 = 0;
+    bool first = true;
+    while (k0 < nk || first) {
+      LinArgs L;
+      std::memset(&L, 0, sizeof(L));
+      int t = 0;
+      if (!first) { L.x[t] = y; L.a[t] = 1.0; ++t; }
+      while (t < kLinTerms && k0 < nk) { L.x[t] = x[k0]; L.a[t] = a[k0]; ++t; ++k0; }
+      L.nk = t;
+      hipLaunchKernelGGL(lincomb_kernel, dim3(grid()), dim3(kVecThreads), 0, st, L, y, M);
+      first = false;
+    }
+    return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
+  }
+
+  // dots[j] = <w, V_j> for j < nj (synchronous: values returned in h)
+  int dot_many(const double* w, const double* Vb, int nj, double* h) {
+    for (int j0 = 0; j0 < nj; j0 += kLinTerms) {
+      const int nn = nj - j0 < kLinTerms ? nj - j0 : kLinTerms;
+      hipLaunchKernelGGL(multidot_kernel, dim3(kDotBlocks), dim3(kVecThreads), 0, st, w, Vb + (long long)j0 * stride,
+                         stride, nn, M, part + j0, m + 2);
+    }
+    hipLaunchKernelGGL(dot_final_kernel, dim3(nj), dim3(kVecThreads), 0, st, part, kDotBlocks, m + 2, dots);
+    if (hipGetLastError() != hipSuccess) return NSK_EHIP;
+    if (hipMemcpyAsync(h, dots, sizeof(double) * nj, hipMemcpyDeviceToHost, st) != hipSuccess) return NSK_EHIP;
+    return hipStreamSynchronize(st) == hipSuccess ? NSK_OK : NSK_EHIP;
+  }
+
+  int norm(const double* w, double* out) {
+    int rc = dot_many(w, w, 1, out);
+    *out = std::sqrt(*out);
+    return rc;
+  }
+
+  int rhs(const double* X, double* R) {
+    ++stats->rhs_evals;
+    return nsk_rhs(c, X, R, 0.0);
+  }
+
+  // One GMRES cycle for (I - dtg J) P^{-1} y = r, r in vR; X += P^{-1} V y.
+  int gmres(double dtg, double xnorm, double rtol, int* iters) {
+    double beta;
+    int rc = norm(vec(vR), &beta);
+    if (rc) return rc;
+    *iters = 0;
+    if (!(beta > 0.0)) return NSK_OK;
+    {
+      const double* x[1] = {vec(vR)};
+      const double a[1] = {1.0 / beta};
+      if ((rc = lin(V(0), 1, x, a))) return rc;
+    }
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), h(m + 1), h2(m + 1);
+    g[0] = beta;
+    const double s = std::sqrt(2.2204460492503131e-16) * (1.0 + xnorm);
+    int kd = 0;
+    for (int k = 0; k < m; ++k) {
+      hipLaunchKernelGGL(perturb_kernel, dim3(grid()), dim3(kVecThreads), 0, st, vec(vX), V(k), s, pre, vec(vXp), M);
+      if ((rc = rhs(vec(vXp), vec(vRp)))) return rc;
+      double* w = V(k + 1);
+      hipLaunchKernelGGL(jvp_kernel, dim3(grid()), dim3(kVecThreads), 0, st, V(k), vec(vRp), vec(vRX), dtg / s, pre,
+                         w, M);
+      // classical Gram-Schmidt, twice
+      for (int pass = 0; pass < 2; ++pass) {
+        double* hh = pass == 0 ? h.data() : h2.data();
+        if ((rc = dot_many(w, V(0), k + 1, hh))) return rc;
+        std::vector<const double*> xs;
+        std::vector<double> as;
+        for (int j = 0; j <= k; ++j) { xs.push_back(V(j)); as.push_back(-hh[j]); }
+        xs.insert(xs.begin(), w);
+        as.insert(as.begin(), 1.0);
+        if ((rc = lin(w, (int)xs.size(), xs.data(), as.data()))) return rc;
+      }
+      for (int j = 0; j <= k; ++j) H[(size_t)j * m + k] = h[j] + h2[j];
+      double hk1;
+      if ((rc = norm(w, &hk1))) return rc;
+      H[(size_t)(k + 1) * m + k] = hk1;
+      if (hk1 > 0.0) {
+        const double* x[1] = {w};
+        const double a[1] = {1.0 / hk1};
+        if ((rc = lin(w, 1, x, a))) return rc;
+      }
+      // Givens rotations on the new column
+      for (int j = 0; j < k; ++j) {
+        const double t0 = H[(size_t)j * m + k], t1 = H[(size_t)(j + 1) * m + k];
+        H[(size_t)j * m + k] = cs[j] * t0 + sn[j] * t1;
+        H[(size_t)(j + 1) * m + k] = -sn[j] * t0 + cs[j] * t1;
+      }
+      const double a0 = H[(size_t)k * m + k], a1 = H[(size_t)(k + 1) * m + k];
+      const double r = std::hypot(a0, a1);
+      cs[k] = r > 0.0 ? a0 / r : 1.0;
+      sn[k] = r > 0.0 ? a1 / r : 0.0;
+      H[(size_t)k * m + k] = r;
+      H[(size_t)(k + 1) * m + k] = 0.0;
+      g[k + 1] = -sn[k] * g[k];
+      g[k] = cs[k] * g[k];
+      kd = k + 1;
+      ++stats->gmres_iters;
+      if (std::fabs(g[k + 1]) <= rtol * beta || !(hk1 > 0.0)) break;
+    }
+    // back substitution and the correction X += P^{-1} sum_j y_j V_j
+    std::vector<double> y(kd);
+    for (int i = kd - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int j = i + 1; j < kd; ++j) t -= H[(size_t)i * m + j] * y[j];
+      y[i] = t / H[(size_t)i * m + i];
+    }
+    std::vector<const double*> xs;
+    for (int j = 0; j < kd; ++j) xs.push_back(V(j));
+    if ((rc = lin(vec(vY), kd, xs.data(), y.data()))) return rc;
+    hipLaunchKernelGGL(correct_kernel, dim3(grid()), dim3(kVecThreads), 0, st, vec(vX), vec(vY), pre, M);
+    *iters = kd;
+    return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
+  }
+};
+
+size_t vec_stride(const nsk_ctx* c) {
+  const size_t M = (size_t)c->nvar * c->S;
+  return (M + 31) / 32 * 32;
+}
+
+int check_opts(const nsk_implicit_opts* o) {
+  if (!o) return NSK_EINVAL;
+  if (!(o->newton_tol > 0.0) || !std::isfinite(o->newton_tol) || o->newton_max < 1 || o->newton_max > 1000)
+    return NSK_EINVAL;
+  if (!(o->gmres_rtol > 0.0) || !(o->gmres_rtol < 1.0) || o->gmres_m < 1 || o->gmres_m > NSK_GMRES_MAX)
+    return NSK_EINVAL;
+  if (o->precond != 0 && o->precond != 1) return NSK_EINVAL;
+  return NSK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t nsk_implicit_workspace_bytes(const nsk_ctx* c, int gmres_m) {
+  if (!c || gmres_m < 1 || gmres_m > NSK_GMRES_MAX) return 0;
+  const size_t vecs = (size_t)vV0 + gmres_m + 1;
+  return sizeof(double) * (vecs * vec_stride(c) + (size_t)kDotBlocks * (gmres_m + 2) + 256);
+}
+
+int nsk_esdirk_step(nsk_ctx* c, void* d_iwork, double dt, int nsteps, const nsk_implicit_opts* opts,
+                    nsk_implicit_stats* stats_out) {
+  if (!c || !d_iwork || nsteps < 0 || !(dt > 0.0) || !std::isfinite(dt)) return NSK_EINVAL;
+  int rc = check_opts(opts);
+  if (rc) return rc;
+  if ((reinterpret_cast<uintptr_t>(d_iwork) & 255) != 0) return NSK_EINVAL;
+  // finite-difference Jacobian products need FP64 right-hand sides
+  if (c->par.precision != 0 || c->par.closure != 0) return NSK_EUNSUPPORTED;
+  if (opts->precond == 1 && c->par.model != 0) return NSK_EINVAL;  // the relaxation source is model II's
+  if (!c->bound) return NSK_EUNBOUND;
+  if (c->cur != 0) return NSK_EINVAL;
+
+  nsk_implicit_stats stats;
+  std::memset(&stats, 0, sizeof(stats));
+  stats.converged = 1;
+  Solver S;
+  S.c = c;
+  S.base = static_cast<char*>(d_iwork);
+  S.M = (long long)c->nvar * c->S;
+  S.stride = (long long)vec_stride(c);
+  S.m = opts->gmres_m;
+  S.part = reinterpret_cast<double*>(S.base) + (long long)(vV0 + S.m + 1) * S.stride;
+  S.dots = S.part + (long long)kDotBlocks * (S.m + 2);
+  S.st = c->stream;
+  S.stats = &stats;
+  const double dtg = dt * kGamma;
+  S.pre.on = opts->precond;
+  S.pre.ci = c->dim + 1;
+  S.pre.a = dtg * c->par.alpha / c->par.beta;
+  S.pre.S = c->S;
+
+  double* U = c->U;
+  for (int step = 0; step < nsteps && rc == NSK_OK; ++step) {
+    if ((rc = S.rhs(U, S.vec(vK0)))) break;
+    for (int i = 1; i < 6 && rc == NSK_OK; ++i) {
+      // B = U + dt sum_{j<i} a_ij K_j
+      std::vector<const double*> xs{U};
+      std::vector<double> as{1.0};
+      for (int j = 0; j < i; ++j)
+        if (kA[i][j] != 0.0) { xs.push_back(S.vec(vK0 + j)); as.push_back(dt * kA[i][j]); }
+      if ((rc = S.lin(S.vec(vB), (int)xs.size(), xs.data(), as.data()))) break;
+      // predictor X = B + dt gamma K_{i-1}
+      {
+        const double* x[2] = {S.vec(vB), S.vec(vK0 + i - 1)};
+        const double a[2] = {1.0, dtg};
+        if ((rc = S.lin(S.vec(vX), 2, x, a))) break;
+      }
+      double bnorm;
+      if ((rc = S.norm(S.vec(vB), &bnorm))) break;
+      bool conv = false;
+      double res = 0.0;
+      for (int it = 0; it <= opts->newton_max; ++it) {
+        if ((rc = S.rhs(S.vec(vX), S.vec(vRX)))) break;
+        // r = B + dtg R(X) - X = -G(X)
+        const double* x[3] = {S.vec(vB), S.vec(vRX), S.vec(vX)};
+        const double a[3] = {1.0, dtg, -1.0};
+        if ((rc = S.lin(S.vec(vR), 3, x, a))) break;
+        double rn;
+        if ((rc = S.norm(S.vec(vR), &rn))) break;
+        res = rn / (bnorm > 0.0 ? bnorm : 1.0);
+        if (!std::isfinite(rn)) { rc = NSK_ENONPHYS; break; }
+        if (res <= opts->newton_tol) { conv = true; break; }
+        if (it == opts->newton_max) break;
+        double xnorm;
+        if ((rc = S.norm(S.vec(vX), &xnorm))) break;
+        int gi = 0;
+        if ((rc = S.gmres(dtg, xnorm, opts->gmres_rtol, &gi))) break;
+        ++stats.newton_iters;
+      }
+      if (rc) break;
+      if (res > stats.max_residual) stats.max_residual = res;
+      if (!conv) { stats.converged = 0; rc = NSK_ENOCONV; break; }
+      if (i < 5) {
+        // K_i = (X - B) / (dt gamma)
+        const double* x[2] = {S.vec(vX), S.vec(vB)};
+        const double a[2] = {1.0 / dtg, -1.0 / dtg};
+        if ((rc = S.lin(S.vec(vK0 + i), 2, x, a))) break;
+      }
+    }
+    if (rc) break;
+    // stiffly accurate: U_{n+1} is the last stage
+    if (hipMemcpyAsync(U, S.vec(vX), sizeof(double) * S.M, hipMemcpyDeviceToDevice, S.st) != hipSuccess) {
+      rc = NSK_EHIP;
+      break;
+    }
+    ++stats.steps;
+  }
+  if (hipStreamSynchronize(S.st) != hipSuccess && rc == NSK_OK) rc = NSK_EHIP;
+  if (stats_out) *stats_out = stats;
+  return rc;
+}
+
+}  // extern "C"

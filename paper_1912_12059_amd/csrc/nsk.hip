@@ -217,6 +217,7 @@ const char* nsk_strerror(int code) {
     case NSK_EHIP: return "HIP runtime error";
     case NSK_EUNBOUND: return "device memory not bound";
     case NSK_EUNSUPPORTED: return "unsupported dimension/degree";
+    case NSK_ENOCONV: return "implicit stage equations did not converge";
   }
   return "unknown error";
 }

@@ -20,6 +20,8 @@ NSK_ENONPHYS = -2
 NSK_EHIP = -3
 NSK_EUNBOUND = -4
 NSK_EUNSUPPORTED = -5
+NSK_ENOCONV = -6
+NSK_GMRES_MAX = 64
 
 
 class NskError(RuntimeError):
@@ -59,6 +61,27 @@ class nsk_closure_norm(C.Structure):
 
 
 NSK_MLP_NPARAM = 8770
+
+
+class nsk_implicit_opts(C.Structure):
+    _fields_ = [
+        ("newton_tol", C.c_double),
+        ("newton_max", C.c_int),
+        ("gmres_rtol", C.c_double),
+        ("gmres_m", C.c_int),
+        ("precond", C.c_int),
+    ]
+
+
+class nsk_implicit_stats(C.Structure):
+    _fields_ = [
+        ("steps", C.c_longlong),
+        ("rhs_evals", C.c_longlong),
+        ("newton_iters", C.c_longlong),
+        ("gmres_iters", C.c_longlong),
+        ("max_residual", C.c_double),
+        ("converged", C.c_int),
+    ]
 
 
 class nsk_diag(C.Structure):
@@ -122,6 +145,10 @@ def load() -> C.CDLL:
         L.nsk_batch_set_group.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
         L.nsk_timing_enable.argtypes = [vp, C.c_int]
         L.nsk_timing_read.argtypes = [vp, dp]
+        L.nsk_implicit_workspace_bytes.argtypes = [vp, C.c_int]
+        L.nsk_implicit_workspace_bytes.restype = C.c_size_t
+        L.nsk_esdirk_step.argtypes = [vp, vp, C.c_double, C.c_int, C.POINTER(nsk_implicit_opts),
+                                      C.POINTER(nsk_implicit_stats)]
         fp = C.POINTER(C.c_float)
         L.nsk_closure_set.argtypes = [vp, vp, C.POINTER(nsk_closure_norm), C.c_int]
         L.nsk_closure_nudge.argtypes = [vp, C.POINTER(nsk_closure_norm), vp, C.c_double, C.c_double, C.c_double, vp,
@@ -256,6 +283,30 @@ def nsk_timing_read(ctx: int) -> tuple[float, float, int, float]:
     out = (C.c_double * 4)()
     _check("nsk_timing_read", load().nsk_timing_read(ctx, out))
     return out[0], out[1], int(out[2]), out[3]
+
+
+def make_implicit_opts(newton_tol=1e-10, newton_max=20, gmres_rtol=1e-3, gmres_m=20, precond=0):
+    o = nsk_implicit_opts()
+    o.newton_tol, o.newton_max, o.gmres_rtol, o.gmres_m, o.precond = newton_tol, newton_max, gmres_rtol, gmres_m, \
+        precond
+    return o
+
+
+def nsk_implicit_workspace_bytes(ctx: int, gmres_m: int) -> int:
+    return load().nsk_implicit_workspace_bytes(ctx, gmres_m)
+
+
+def nsk_esdirk_step(ctx: int, iwork_ptr: int, dt: float, nsteps: int, opts: nsk_implicit_opts) -> dict:
+    """Runs the steps; returns the statistics (raises NskError on failure,
+    with the statistics in its .stats attribute)."""
+    st = nsk_implicit_stats()
+    rc = load().nsk_esdirk_step(ctx, iwork_ptr, dt, nsteps, C.byref(opts), C.byref(st))
+    stats = {k: getattr(st, k) for k, _ in nsk_implicit_stats._fields_}
+    if rc != NSK_OK:
+        err = NskError("nsk_esdirk_step", rc)
+        err.stats = stats
+        raise err
+    return stats
 
 
 def nsk_batch_create(meshes: list, params: nsk_params) -> int:
@@ -447,6 +498,19 @@ class Solver:
 
     def dt_estimate(self, cfl: float) -> float:
         return nsk_dt_estimate(self.ctx, cfl)
+
+    def esdirk_step(self, dt: float, nsteps: int = 1, **opts) -> dict:
+        """Implicit ESDIRK4(6) steps (nsk_esdirk_step); the Krylov workspace
+        is allocated with torch on first use and kept for the same size."""
+        import torch
+
+        o = make_implicit_opts(**opts)
+        need = nsk_implicit_workspace_bytes(self.ctx, o.gmres_m)
+        if getattr(self, "_iwork", None) is None or self._iwork.numel() < need + 256:
+            self._iwork = None
+            self._iwork = torch.empty(need + 256, dtype=torch.uint8, device=self.U.device)
+        ptr = (self._iwork.data_ptr() + 255) // 256 * 256
+        return nsk_esdirk_step(self.ctx, ptr, dt, nsteps, o)
 
     def diagnostics(self) -> dict:
         rc, d = nsk_diagnostics(self.ctx)

@@ -188,3 +188,43 @@ def test_nsk_model_host_side_checks():
     with pytest.raises(nsk.NskError) as e:
         nsk.nsk_batch_create([bm], nsk.make_params(model=1))
     assert e.value.code == nsk.NSK_EUNSUPPORTED
+
+
+def test_implicit_host_side_checks():
+    """nsk_esdirk_step validates its arguments on the host, before any device
+    work: options, alignment, context kind, binding."""
+    m, keep = _ok_mesh()
+    ctx = nsk.nsk_create(m, nsk.make_params())
+    mixed = nsk.nsk_create(m, nsk.make_params(precision=1))
+    orig = nsk.nsk_create(m, nsk.make_params(model=1))
+    try:
+        M = 5 * 24 * 125
+        assert nsk.nsk_implicit_workspace_bytes(ctx, 0) == 0
+        assert nsk.nsk_implicit_workspace_bytes(ctx, nsk.NSK_GMRES_MAX + 1) == 0
+        assert nsk.nsk_implicit_workspace_bytes(ctx, 20) >= 8 * (20 + 9) * M
+        fake = 256  # never dereferenced: every call below fails its host checks
+        ok = nsk.make_implicit_opts()
+        for bad in (dict(newton_tol=0.0), dict(newton_max=0), dict(gmres_rtol=1.0), dict(gmres_rtol=0.0),
+                    dict(gmres_m=0), dict(gmres_m=nsk.NSK_GMRES_MAX + 1), dict(precond=2)):
+            with pytest.raises(nsk.NskError) as e:
+                nsk.nsk_esdirk_step(ctx, fake, 1e-3, 1, nsk.make_implicit_opts(**bad))
+            assert e.value.code == nsk.NSK_EINVAL, bad
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_esdirk_step(ctx, fake, -1.0, 1, ok)
+        assert e.value.code == nsk.NSK_EINVAL
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_esdirk_step(ctx, fake + 8, 1e-3, 1, ok)  # not 256-byte aligned
+        assert e.value.code == nsk.NSK_EINVAL
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_esdirk_step(mixed, fake, 1e-3, 1, ok)
+        assert e.value.code == nsk.NSK_EUNSUPPORTED
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_esdirk_step(orig, fake, 1e-3, 1, nsk.make_implicit_opts(precond=1))
+        assert e.value.code == nsk.NSK_EINVAL
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_esdirk_step(ctx, fake, 1e-3, 1, ok)
+        assert e.value.code == nsk.NSK_EUNBOUND
+        assert "converge" in nsk.nsk_strerror(nsk.NSK_ENOCONV)
+    finally:
+        for c in (ctx, mixed, orig):
+            nsk.nsk_destroy(c)
