@@ -222,6 +222,47 @@ def run_nsk_form(nsk, m, U0, w, steps: int, warmup: int, tile: str, ref: dict):
     }
 
 
+def run_implicit_form(nsk, m, U0, w, factors=(100, 200)):
+    """Implicit ESDIRK4(6) steps (Jacobian-free Newton-GMRES with the
+    node-local source preconditioner) on the same workload, FP64, one step
+    each of `factor` times the explicit step, against the explicit LSRK4(5)
+    over the same simulated time: wall time, solver counts, and the relative
+    L2 difference of rho between the two integrators."""
+    import torch
+
+    s = nsk.Solver(dim=m.dim, N=m.N, nel=tuple(m.nel), lo=tuple(m.lo), hi=tuple(m.hi), alpha=w["alpha"],
+                   beta=1e-3, eps=1e-3, kappa=1e-5)
+    s.set_state(U0)
+    nsk.nsk_autotune(s.ctx, 3)
+    dte = s.dt_estimate(0.5)
+    opts = dict(precond=1, gmres_m=40, newton_tol=1e-8, gmres_rtol=1e-3, newton_max=20)
+    out = {"dt_explicit": dte, "opts": opts, "steps": []}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for fac in factors:
+        s.set_state(U0)
+        torch.cuda.synchronize()
+        e0.record(s.stream)
+        s.rk_step(dte, fac)
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        ms_exp = e0.elapsed_time(e1)
+        ref = s.get_state()[0].clone()
+        s.set_state(U0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = s.esdirk_step(fac * dte, 1, **opts)
+        torch.cuda.synchronize()
+        ms_imp = (time.perf_counter() - t0) * 1e3
+        got = s.get_state()[0]
+        l2 = float(torch.linalg.vector_norm(got - ref) / torch.linalg.vector_norm(ref))
+        print(f"[bench] implicit x{fac}: {ms_imp:.0f} ms vs explicit {ms_exp:.0f} ms", file=sys.stderr, flush=True)
+        out["steps"].append({"factor": fac, "dt": fac * dte, "implicit_ms": ms_imp, "explicit_ms": ms_exp,
+                             "speedup_vs_explicit": ms_exp / ms_imp, "l2_rel_rho_vs_explicit": l2, **st})
+        del ref, got
+    s.close()
+    return out
+
+
 def run_batched(nsk, steps: int, warmup: int):
     """The batched collision sweep: 24 3D head-on collisions (n_x x 32 x 32
     elements, n_x in 32..64, N in {3,4,5}, We ~ U[5,150], impact ~ U[0,0.5] R,
@@ -525,6 +566,7 @@ def main() -> int:
                     help="form reported as value; the other one is measured beside it unless --no-forms")
     ap.add_argument("--no-forms", action="store_true", help="skip the second precision form and the batch")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched collision sweep")
+    ap.add_argument("--no-implicit", action="store_true", help="skip the implicit ESDIRK form")
     ap.add_argument("--no-closure", action="store_true", help="skip the closure form")
     ap.add_argument("--only-closure", action="store_true", help="run only the closure form (prints its block)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -656,6 +698,8 @@ def main() -> int:
         }
         del hl
         out["forms"]["nsk_original_fp64"] = run_nsk_form(nsk, m, U0, w, args.steps, args.warmup, args.tile, f64)
+        if not args.no_implicit:
+            out["forms"]["implicit_esdirk"] = run_implicit_form(nsk, m, U0, w)
     del forms
     if not args.no_forms and not args.no_batched and args.workload == "3d-collision":
         out.setdefault("forms", {})["batched"] = run_batched(nsk, 10, 2)

@@ -212,7 +212,8 @@ int nsk_timing_read(nsk_ctx* ctx, double out[4]);
  * B_i = U_n + dt sum_{j<i} a_ij K_j, is solved by Newton's method (initial
  * guess B_i + dt gamma K_{i-1}); each Newton correction comes from one cycle
  * of right-preconditioned GMRES (at most gmres_m Krylov vectors, classical
- * Gram-Schmidt applied twice) with the Jacobian-vector product
+ * Gram-Schmidt, repeated when the projection removes more than 1/sqrt(2) of
+ * the vector's norm) with the Jacobian-vector product
  * (R(X + s z) - R(X))/s, s = sqrt(eps_machine)(1 + |X|_2).  K_i = (X - B_i)/
  * (dt gamma); U_{n+1} is the last stage.  Works on FP64 contexts of either
  * model without the closure.
@@ -233,6 +234,7 @@ typedef struct {
   long long rhs_evals;    /* right-hand-side evaluations                      */
   long long newton_iters; /* Newton corrections                               */
   long long gmres_iters;  /* Jacobian-vector products (GMRES iterations)      */
+  long long reorth;       /* Arnoldi steps that needed a second projection    */
   double max_residual;    /* largest final relative stage residual            */
   int converged;          /* 1 if every stage met newton_tol                  */
 } nsk_implicit_stats;

@@ -7,9 +7,9 @@
 // One step from U_n:  K_1 = R(U_n); for stage i = 2..6 solve
 //   G(X) = X - dt gamma R(X) - B_i = 0,   B_i = U_n + dt sum_{j<i} a_ij K_j,
 // by Newton's method, each correction from one cycle of right-preconditioned
-// GMRES with classical Gram-Schmidt applied twice and the Jacobian-vector
-// product (R(X + s z) - R(X)) / s; then K_i = (X - B_i)/(dt gamma); U_{n+1}
-// is the last stage's X.  Every right-hand side is nsk_rhs on the bound
+// GMRES with classical Gram-Schmidt (repeated when the projection cancels
+// most of the vector) and the Jacobian-vector product (R(X + s z) - R(X))/s;
+// then K_i = (X - B_i)/(dt gamma); U_{n+1} is the last stage's X.  Every right-hand side is nsk_rhs on the bound
 // context; the vector work runs in the kernels below, with fixed-order
 // reductions, so a run is bitwise reproducible.  The host reads back only
 // the dot products of each Arnoldi step.
@@ -127,14 +127,18 @@ __global__ void __launch_bounds__(kVecThreads) perturb_kernel(const double* __re
     Xp[i] = X[i] + s * pinv(v, i, p);
 }
 
-// w = P^{-1} v - c (Rp - RX): the Jacobian-vector product of G, c = dt gamma / s
+// w = (P^{-1} v - v) - c (Rp - RX), c = dt gamma / s: the product of v with
+// B = A - I, where A = (I - dt gamma dR/dU) P^{-1} is the GMRES operator.
+// A and B span the same Krylov spaces and A's Hessenberg matrix is B's plus
+// the identity; A is close to the identity, so projecting A v onto the basis
+// would cancel most of it, while B v keeps only the part that is not v.
 __global__ void __launch_bounds__(kVecThreads) jvp_kernel(const double* __restrict__ v,
                                                           const double* __restrict__ Rp,
                                                           const double* __restrict__ RX, double c, Precond p,
                                                           double* __restrict__ w, long long n) {
   const long long stride = (long long)gridDim.x * kVecThreads;
   for (long long i = (long long)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride)
-    w[i] = pinv(v, i, p) - c * (Rp[i] - RX[i]);
+    w[i] = (pinv(v, i, p) - v[i]) - c * (Rp[i] - RX[i]);
 }
 
 // X += P^{-1} Y
@@ -232,7 +236,7 @@ struct Solver {
       const double a[1] = {1.0 / beta};
       if ((rc = lin(V(0), 1, x, a))) return rc;
     }
-    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), h(m + 1), h2(m + 1);
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), h(m + 2), h2(m + 2);
     g[0] = beta;
     const double s = std::sqrt(2.2204460492503131e-16) * (1.0 + xnorm);
     int kd = 0;
@@ -242,26 +246,40 @@ struct Solver {
       double* w = V(k + 1);
       hipLaunchKernelGGL(jvp_kernel, dim3(grid()), dim3(kVecThreads), 0, st, V(k), vec(vRp), vec(vRX), dtg / s, pre,
                          w, M);
-      // classical Gram-Schmidt, twice
-      for (int pass = 0; pass < 2; ++pass) {
-        double* hh = pass == 0 ? h.data() : h2.data();
-        if ((rc = dot_many(w, V(0), k + 1, hh))) return rc;
-        std::vector<const double*> xs;
-        std::vector<double> as;
-        for (int j = 0; j <= k; ++j) { xs.push_back(V(j)); as.push_back(-hh[j]); }
-        xs.insert(xs.begin(), w);
-        as.insert(as.begin(), 1.0);
-        if ((rc = lin(w, (int)xs.size(), xs.data(), as.data()))) return rc;
+      // classical Gram-Schmidt: w is V_{k+1}, so one multi-dot gives
+      // <w, V_0..V_k> and |w|^2 together; |w - sum h_j V_j|^2 then follows
+      // from Pythagoras, and the subtraction and the normalisation are one
+      // linear combination.  When more than 1/sqrt(2) of |w| cancels
+      // (Kahan's criterion) the projection is repeated and the norm is
+      // recomputed exactly.
+      if ((rc = dot_many(w, V(0), k + 2, h.data()))) return rc;
+      const double ww = h[k + 1];
+      double proj = 0.0;
+      for (int j = 0; j <= k; ++j) proj += h[j] * h[j];
+      double hk1 = ww - proj > 0.0 ? std::sqrt(ww - proj) : 0.0;
+      const bool again = !(hk1 * hk1 > 0.5 * ww);
+      for (int j = 0; j <= k; ++j) h2[j] = 0.0;
+      auto subtract = [&](const double* hh, double scale) {
+        std::vector<const double*> xs{w};
+        std::vector<double> as{scale};
+        for (int j = 0; j <= k; ++j) { xs.push_back(V(j)); as.push_back(-hh[j] * scale); }
+        return lin(w, (int)xs.size(), xs.data(), as.data());
+      };
+      if (!again) {
+        if ((rc = subtract(h.data(), 1.0 / hk1))) return rc;
+      } else {
+        if ((rc = subtract(h.data(), 1.0))) return rc;
+        if ((rc = dot_many(w, V(0), k + 2, h2.data()))) return rc;
+        const double ww2 = h2[k + 1];
+        double proj2 = 0.0;
+        for (int j = 0; j <= k; ++j) proj2 += h2[j] * h2[j];
+        hk1 = ww2 - proj2 > 0.0 ? std::sqrt(ww2 - proj2) : 0.0;
+        if ((rc = subtract(h2.data(), hk1 > 0.0 ? 1.0 / hk1 : 1.0))) return rc;
+        ++stats->reorth;
       }
       for (int j = 0; j <= k; ++j) H[(size_t)j * m + k] = h[j] + h2[j];
-      double hk1;
-      if ((rc = norm(w, &hk1))) return rc;
+      H[(size_t)k * m + k] += 1.0;  // A = I + B
       H[(size_t)(k + 1) * m + k] = hk1;
-      if (hk1 > 0.0) {
-        const double* x[1] = {w};
-        const double a[1] = {1.0 / hk1};
-        if ((rc = lin(w, 1, x, a))) return rc;
-      }
       // Givens rotations on the new column
       for (int j = 0; j < k; ++j) {
         const double t0 = H[(size_t)j * m + k], t1 = H[(size_t)(j + 1) * m + k];

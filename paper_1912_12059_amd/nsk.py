@@ -79,6 +79,7 @@ class nsk_implicit_stats(C.Structure):
         ("rhs_evals", C.c_longlong),
         ("newton_iters", C.c_longlong),
         ("gmres_iters", C.c_longlong),
+        ("reorth", C.c_longlong),
         ("max_residual", C.c_double),
         ("converged", C.c_int),
     ]
