@@ -569,6 +569,8 @@ def main() -> int:
     ap.add_argument("--no-implicit", action="store_true", help="skip the implicit ESDIRK form")
     ap.add_argument("--no-closure", action="store_true", help="skip the closure form")
     ap.add_argument("--only-closure", action="store_true", help="run only the closure form (prints its block)")
+    ap.add_argument("--only-nsk", action="store_true",
+                    help="run only the original NSK form on the workload (prints its block)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="auto", help="auto (autotuner) or 'variant,order', e.g. 0,4")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -600,6 +602,16 @@ def main() -> int:
     print(f"[bench] building {args.workload} state", file=sys.stderr, flush=True)
     m, U = build_state(args.workload)
     U0 = torch.from_numpy(U.reshape(-1)).to("cuda:0")
+    if args.only_nsk:
+        del U
+        s2 = nsk.Solver(dim=m.dim, N=m.N, nel=tuple(m.nel), lo=tuple(m.lo), hi=tuple(m.hi), alpha=w["alpha"],
+                        beta=1e-3, eps=1e-3, kappa=1e-5)
+        s2.set_state(U0)
+        ref = {"dt": s2.dt_estimate(0.5), "ms": float("nan")}
+        s2.close()
+        print(json.dumps({"nsk_original_fp64": run_nsk_form(nsk, m, U0, w, args.steps, args.warmup, args.tile,
+                                                            ref)}))
+        return 0
     if m.dim == 3:
         sub = (16, 16, 16)
         block = ((24, 16), (16, 16), (16, 16))  # around the first droplet's interface
