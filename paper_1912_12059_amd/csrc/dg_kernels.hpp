@@ -825,16 +825,19 @@ lap_kernel(const double* __restrict__ U, double* __restrict__ G, BasisArgs bas, 
   lap_block<DIM, NP, EPB>(remap_block(blockIdx.x, gridDim.x, msh.nxcd), threadIdx.x, U, G, bas, msh, ph);
 }
 
-// ... and the maximum of the n partial speeds into out[0] (one workgroup).
-constexpr int kMaxReduceThreads = 1024;
+// ... and the maximum of the partial speeds, in two launches: kMaxReduceBlocks
+// workgroups each reduce a strided share into out[blockIdx.x], then one
+// workgroup reduces those.
+constexpr int kMaxReduceThreads = 256;
+constexpr int kMaxReduceBlocks = 128;
 template <int THREADS>
 __global__ void __launch_bounds__(THREADS)
 max_reduce_kernel(const double* __restrict__ part, int n, double* __restrict__ out) {
   __shared__ double red[THREADS / 64];
   const int tid = threadIdx.x;
   double m = 0.0;
-  for (int i = tid; i < n; i += THREADS) m = fmax(m, part[i]);
-  block_max_store<THREADS>(m, red, out, tid);
+  for (int i = blockIdx.x * THREADS + tid; i < n; i += gridDim.x * THREADS) m = fmax(m, part[i]);
+  block_max_store<THREADS>(m, red, out + blockIdx.x, tid);
 }
 
 // -------------------------------------------------------------------------

@@ -54,14 +54,21 @@ int launch_stage_nsk(nsk_ctx* c, const double* Uin, double* Uout, double* dU, co
   const MeshArgs m = mesh_args(c);
   const PhysArgs p = phys_args(c);
   double* G = reinterpret_cast<double*>(c->work + c->off_G);
-  double* lf = reinterpret_cast<double*>(c->work + c->off_lf);  // [0]: speed, [1..blocks]: partial maxima
+  // lf[0]: the speed; lf[1..kMaxReduceBlocks]: second-level maxima; then one
+  // partial maximum per lifting workgroup
+  double* lf = reinterpret_cast<double*>(c->work + c->off_lf);
+  double* lf2 = lf + 1;
+  double* lfpart = lf + 1 + kMaxReduceBlocks;
   const unsigned blocks = (unsigned)((c->E + EPB - 1) / EPB);
   hipEvent_t* ev = stage_events(c, st);
   if (ev) (void)hipEventRecord(ev[0], c->stream);
   hipLaunchKernelGGL((nsk_lift_kernel<DIM, NP, EPB>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream, Uin, G, b, m, p,
-                     lf + 1);
+                     lfpart);
   if (ev) (void)hipEventRecord(ev[1], c->stream);
-  hipLaunchKernelGGL(max_reduce_kernel<kMaxReduceThreads>, dim3(1), dim3(kMaxReduceThreads), 0, c->stream, lf + 1, (int)blocks, lf);
+  hipLaunchKernelGGL(max_reduce_kernel<kMaxReduceThreads>, dim3(kMaxReduceBlocks), dim3(kMaxReduceThreads), 0,
+                     c->stream, lfpart, (int)blocks, lf2);
+  hipLaunchKernelGGL(max_reduce_kernel<kMaxReduceThreads>, dim3(1), dim3(kMaxReduceThreads), 0, c->stream, lf2,
+                     kMaxReduceBlocks, lf);
   hipLaunchKernelGGL((lap_kernel<DIM, NP, EPB>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream, Uin, G, b, m, p);
   if (ev) (void)hipEventRecord(ev[2], c->stream);
   StageArgs sta = st;
@@ -299,10 +306,10 @@ int nsk_create(const nsk_mesh* mesh, const nsk_params* params, nsk_ctx** out) {
     off = align256(off + sizeof(float) * (size_t)(c->dim + 1) * c->S);
   }
   if (c->par.model == 1) {
-    // global LF speed and one partial maximum per lifting workgroup (at
-    // most one workgroup per element)
+    // global LF speed, the second-level maxima and one partial maximum per
+    // lifting workgroup (at most one workgroup per element)
     c->off_lf = off;
-    off = align256(off + sizeof(double) * (size_t)(c->E + 1));
+    off = align256(off + sizeof(double) * (size_t)(c->E + 1 + kMaxReduceBlocks));
   }
   c->ws_bytes = off;
   // default launch shape: tiled work order in 3D, natural order otherwise
