@@ -227,6 +227,9 @@ typedef struct {
   int precond;       /* 1: node-local inverse of the stiff relaxation source
                         (model II only): c -> (c + a rho)/(1 + a),
                         a = dt gamma alpha/beta; 0: none                        */
+  int basis_fp32;    /* 1: Krylov basis stored in FP32 (half the Gram-Schmidt
+                        traffic; products, sums, the new vector and all
+                        Newton quantities stay FP64); 0: FP64 basis          */
 } nsk_implicit_opts;
 
 typedef struct {
@@ -240,7 +243,8 @@ typedef struct {
 } nsk_implicit_stats;
 
 /* Bytes of the device workspace nsk_esdirk_step needs (in addition to the
- * bound workspace): (gmres_m + 9) state vectors plus reduction scratch.
+ * bound workspace): 13 + gmres_m + 1 state vectors plus reduction scratch
+ * (sized for an FP64 basis).
  * 0 for invalid arguments. */
 size_t nsk_implicit_workspace_bytes(const nsk_ctx* ctx, int gmres_m);
 

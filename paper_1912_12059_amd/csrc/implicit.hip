@@ -49,37 +49,60 @@ __global__ void __launch_bounds__(kVecThreads) lincomb_kernel(LinArgs L, double*
 }
 
 // part[b * ld + j] = sum over block b's contiguous chunk of w[i] * v_j[i],
-// v_j = V + j * vstride, for j < nj <= kLinTerms
+// v_j = V + j * vstride, for j < nj <= kLinTerms; with self, also
+// part[b * ld + nj] = the chunk's sum of w[i]^2.  V is the Krylov basis
+// (FP64 or FP32); products and sums are FP64.
+template <typename VT>
 __global__ void __launch_bounds__(kVecThreads) multidot_kernel(const double* __restrict__ w,
-                                                               const double* __restrict__ V, long long vstride,
-                                                               int nj, long long n, double* __restrict__ part,
+                                                               const VT* __restrict__ V, long long vstride, int nj,
+                                                               int self, long long n, double* __restrict__ part,
                                                                int ld) {
-  __shared__ double red[kLinTerms][kVecThreads / 64];
+  __shared__ double red[kLinTerms + 1][kVecThreads / 64];
   const long long chunk = (n + gridDim.x - 1) / gridDim.x;
   const long long beg = (long long)blockIdx.x * chunk;
   const long long end = beg + chunk < n ? beg + chunk : n;
-  double s[kLinTerms];
+  double s[kLinTerms + 1];
 #pragma unroll
-  for (int j = 0; j < kLinTerms; ++j) s[j] = 0.0;
+  for (int j = 0; j <= kLinTerms; ++j) s[j] = 0.0;
   for (long long i = beg + threadIdx.x; i < end; i += kVecThreads) {
     const double wi = w[i];
 #pragma unroll
     for (int j = 0; j < kLinTerms; ++j)
-      if (j < nj) s[j] += wi * V[j * vstride + i];
+      if (j < nj) s[j] += wi * double(V[j * vstride + i]);
+    s[kLinTerms] += wi * wi;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int j = 0; j < kLinTerms; ++j) {
+  for (int j = 0; j <= kLinTerms; ++j) {
     double v = s[j];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     if (lane == 0) red[j][wv] = v;
   }
   __syncthreads();
-  if (threadIdx.x < nj) {
+  const int outs = nj + (self ? 1 : 0);
+  if (threadIdx.x < outs) {
+    const int j = threadIdx.x < nj ? threadIdx.x : kLinTerms;
     double t = 0.0;
-    for (int k = 0; k < kVecThreads / 64; ++k) t += red[threadIdx.x][k];
+    for (int k = 0; k < kVecThreads / 64; ++k) t += red[j][k];
     part[(long long)blockIdx.x * ld + threadIdx.x] = t;
+  }
+}
+
+// y[i] = aw w[i] + sum_{j < nk} a_j v_j[i], v_j = V + j * vstride (nk <=
+// kLinTerms; w may be null; y may be w)
+struct BasisCoefs {
+  double a[kLinTerms];
+};
+template <typename VT, typename OT>
+__global__ void __launch_bounds__(kVecThreads) basis_comb_kernel(const double* w, double aw,
+                                                                 const VT* __restrict__ V, long long vstride,
+                                                                 BasisCoefs c, int nk, OT* y, long long n) {
+  const long long stride = (long long)gridDim.x * kVecThreads;
+  for (long long i = (long long)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride) {
+    double t = w ? aw * w[i] : 0.0;
+    for (int j = 0; j < nk; ++j) t += c.a[j] * double(V[j * vstride + i]);
+    y[i] = OT(t);
   }
 }
 
@@ -110,17 +133,19 @@ struct Precond {
   long long S; // entries per variable
 };
 
-__device__ __forceinline__ double pinv(const double* __restrict__ v, long long i, const Precond& p) {
+template <typename VT>
+__device__ __forceinline__ double pinv(const VT* __restrict__ v, long long i, const Precond& p) {
   if (p.on && i / p.S == p.ci) {
     const long long o = i - (long long)p.ci * p.S;
-    return (v[i] + p.a * v[o]) / (1.0 + p.a);
+    return (double(v[i]) + p.a * double(v[o])) / (1.0 + p.a);
   }
-  return v[i];
+  return double(v[i]);
 }
 
 // Xp = X + s P^{-1} v
+template <typename VT>
 __global__ void __launch_bounds__(kVecThreads) perturb_kernel(const double* __restrict__ X,
-                                                              const double* __restrict__ v, double s, Precond p,
+                                                              const VT* __restrict__ v, double s, Precond p,
                                                               double* __restrict__ Xp, long long n) {
   const long long stride = (long long)gridDim.x * kVecThreads;
   for (long long i = (long long)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride)
@@ -132,13 +157,14 @@ __global__ void __launch_bounds__(kVecThreads) perturb_kernel(const double* __re
 // A and B span the same Krylov spaces and A's Hessenberg matrix is B's plus
 // the identity; A is close to the identity, so projecting A v onto the basis
 // would cancel most of it, while B v keeps only the part that is not v.
-__global__ void __launch_bounds__(kVecThreads) jvp_kernel(const double* __restrict__ v,
+template <typename VT>
+__global__ void __launch_bounds__(kVecThreads) jvp_kernel(const VT* __restrict__ v,
                                                           const double* __restrict__ Rp,
                                                           const double* __restrict__ RX, double c, Precond p,
                                                           double* __restrict__ w, long long n) {
   const long long stride = (long long)gridDim.x * kVecThreads;
   for (long long i = (long long)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride)
-    w[i] = (pinv(v, i, p) - v[i]) - c * (Rp[i] - RX[i]);
+    w[i] = (pinv(v, i, p) - double(v[i])) - c * (Rp[i] - RX[i]);
 }
 
 // X += P^{-1} Y
@@ -161,8 +187,9 @@ const double kA[6][6] = {
     {82889.0 / 524892, 0.0, 15625.0 / 83664, 69875.0 / 102672, -2260.0 / 8211, 0.25},
 };
 
-// Workspace vectors (each M doubles, padded to 256 bytes)
-enum { vK0 = 0, vB = 5, vX, vRX, vR, vXp, vRp, vY, vV0 };
+// Workspace: FP64 vectors (each M doubles, padded to 256 bytes), then the
+// Krylov basis V_0..V_m (FP64 or FP32), then the reduction scratch
+enum { vK0 = 0, vB = 5, vX, vRX, vR, vXp, vRp, vY, vW, kNumVec };
 
 struct Solver {
   nsk_ctx* c;
@@ -176,8 +203,13 @@ struct Solver {
   Precond pre;
   nsk_implicit_stats* stats;
 
+  int f32;            // Krylov basis in FP32
+  long long vstride;  // elements between basis vectors
   double* vec(int k) const { return reinterpret_cast<double*>(base) + (long long)k * stride; }
-  double* V(int k) const { return vec(vV0 + k); }
+  template <typename VT>
+  VT* V(int k) const {
+    return reinterpret_cast<VT*>(reinterpret_cast<double*>(base) + (long long)kNumVec * stride) + (long long)k * vstride;
+  }
   unsigned grid() const {
     const long long b = (M + kVecThreads - 1) / kVecThreads;
     return (unsigned)(b < 8192 ? b : 8192);
@@ -200,23 +232,58 @@ struct Solver {
     return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
   }
 
-  // dots[j] = <w, V_j> for j < nj (synchronous: values returned in h)
-  int dot_many(const double* w, const double* Vb, int nj, double* h) {
-    for (int j0 = 0; j0 < nj; j0 += kLinTerms) {
+  // h[j] = <w, V_j> for j < nj and h[nj] = <w, w> (synchronous)
+  template <typename VT>
+  int dot_basis(const double* w, int nj, double* h) {
+    int j0 = 0;
+    do {
       const int nn = nj - j0 < kLinTerms ? nj - j0 : kLinTerms;
-      hipLaunchKernelGGL(multidot_kernel, dim3(kDotBlocks), dim3(kVecThreads), 0, st, w, Vb + (long long)j0 * stride,
-                         stride, nn, M, part + j0, m + 2);
-    }
-    hipLaunchKernelGGL(dot_final_kernel, dim3(nj), dim3(kVecThreads), 0, st, part, kDotBlocks, m + 2, dots);
+      const bool last = j0 + nn >= nj;
+      hipLaunchKernelGGL(multidot_kernel<VT>, dim3(kDotBlocks), dim3(kVecThreads), 0, st, w, V<VT>(j0), vstride, nn,
+                         last ? 1 : 0, M, part + j0, m + 3);
+      j0 += nn;
+    } while (j0 < nj);
+    return fetch_dots(nj + 1, h);
+  }
+
+  int fetch_dots(int nout, double* h) {
+    hipLaunchKernelGGL(dot_final_kernel, dim3(nout), dim3(kVecThreads), 0, st, part, kDotBlocks, m + 3, dots);
     if (hipGetLastError() != hipSuccess) return NSK_EHIP;
-    if (hipMemcpyAsync(h, dots, sizeof(double) * nj, hipMemcpyDeviceToHost, st) != hipSuccess) return NSK_EHIP;
+    if (hipMemcpyAsync(h, dots, sizeof(double) * nout, hipMemcpyDeviceToHost, st) != hipSuccess) return NSK_EHIP;
     return hipStreamSynchronize(st) == hipSuccess ? NSK_OK : NSK_EHIP;
   }
 
   int norm(const double* w, double* out) {
-    int rc = dot_many(w, w, 1, out);
+    hipLaunchKernelGGL(multidot_kernel<double>, dim3(kDotBlocks), dim3(kVecThreads), 0, st, w, w, 0LL, 0, 1, M,
+                       part, m + 3);
+    int rc = fetch_dots(1, out);
     *out = std::sqrt(*out);
     return rc;
+  }
+
+  // y = aw w + sum_{j<nk} a_j V_j for any nk: launches of kLinTerms basis
+  // vectors, the partial sums accumulated in the FP64 vector acc (which may
+  // be w) when more than one launch is needed
+  template <typename VT, typename OT>
+  int comb(const double* w, double aw, int nk, const double* a, OT* y, double* acc) {
+    int j0 = 0;
+    const double* src = w;
+    double asrc = aw;
+    while (nk - j0 > kLinTerms) {
+      BasisCoefs cf;
+      for (int j = 0; j < kLinTerms; ++j) cf.a[j] = a[j0 + j];
+      hipLaunchKernelGGL((basis_comb_kernel<VT, double>), dim3(grid()), dim3(kVecThreads), 0, st, src, asrc,
+                         V<VT>(j0), vstride, cf, kLinTerms, acc, M);
+      src = acc;
+      asrc = 1.0;
+      j0 += kLinTerms;
+    }
+    BasisCoefs cf;
+    std::memset(&cf, 0, sizeof(cf));
+    for (int j = j0; j < nk; ++j) cf.a[j - j0] = a[j];
+    hipLaunchKernelGGL((basis_comb_kernel<VT, OT>), dim3(grid()), dim3(kVecThreads), 0, st, src, asrc, V<VT>(j0),
+                       vstride, cf, nk - j0, y, M);
+    return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
   }
 
   int rhs(const double* X, double* R) {
@@ -224,57 +291,57 @@ struct Solver {
     return nsk_rhs(c, X, R, 0.0);
   }
 
-  // One GMRES cycle for (I - dtg J) P^{-1} y = r, r in vR; X += P^{-1} V y.
   int gmres(double dtg, double xnorm, double rtol, int* iters) {
+    return f32 ? gmres_t<float>(dtg, xnorm, rtol, iters) : gmres_t<double>(dtg, xnorm, rtol, iters);
+  }
+
+  // One GMRES cycle for (I - dtg J) P^{-1} y = r, r in vR; X += P^{-1} V y.
+  template <typename VT>
+  int gmres_t(double dtg, double xnorm, double rtol, int* iters) {
     double beta;
     int rc = norm(vec(vR), &beta);
     if (rc) return rc;
     *iters = 0;
     if (!(beta > 0.0)) return NSK_OK;
-    {
-      const double* x[1] = {vec(vR)};
-      const double a[1] = {1.0 / beta};
-      if ((rc = lin(V(0), 1, x, a))) return rc;
-    }
+    if ((rc = comb<VT, VT>(vec(vR), 1.0 / beta, 0, nullptr, V<VT>(0), vec(vW)))) return rc;
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), h(m + 2), h2(m + 2);
     g[0] = beta;
     const double s = std::sqrt(2.2204460492503131e-16) * (1.0 + xnorm);
     int kd = 0;
+    std::vector<double> cf(m + 1);
     for (int k = 0; k < m; ++k) {
-      hipLaunchKernelGGL(perturb_kernel, dim3(grid()), dim3(kVecThreads), 0, st, vec(vX), V(k), s, pre, vec(vXp), M);
+      hipLaunchKernelGGL(perturb_kernel<VT>, dim3(grid()), dim3(kVecThreads), 0, st, vec(vX), V<VT>(k), s, pre,
+                         vec(vXp), M);
       if ((rc = rhs(vec(vXp), vec(vRp)))) return rc;
-      double* w = V(k + 1);
-      hipLaunchKernelGGL(jvp_kernel, dim3(grid()), dim3(kVecThreads), 0, st, V(k), vec(vRp), vec(vRX), dtg / s, pre,
-                         w, M);
-      // classical Gram-Schmidt: w is V_{k+1}, so one multi-dot gives
-      // <w, V_0..V_k> and |w|^2 together; |w - sum h_j V_j|^2 then follows
-      // from Pythagoras, and the subtraction and the normalisation are one
-      // linear combination.  When more than 1/sqrt(2) of |w| cancels
-      // (Kahan's criterion) the projection is repeated and the norm is
-      // recomputed exactly.
-      if ((rc = dot_many(w, V(0), k + 2, h.data()))) return rc;
+      double* w = vec(vW);
+      hipLaunchKernelGGL(jvp_kernel<VT>, dim3(grid()), dim3(kVecThreads), 0, st, V<VT>(k), vec(vRp), vec(vRX),
+                         dtg / s, pre, w, M);
+      // classical Gram-Schmidt: one multi-dot gives <w, V_0..V_k> and |w|^2
+      // together; |w - sum h_j V_j|^2 then follows from Pythagoras, and the
+      // subtraction and the normalisation into V_{k+1} are one combination.
+      // When more than 1/sqrt(2) of |w| cancels (Kahan's criterion) the
+      // projection is repeated on the FP64 w and the norm taken again.
+      if ((rc = dot_basis<VT>(w, k + 1, h.data()))) return rc;
       const double ww = h[k + 1];
       double proj = 0.0;
       for (int j = 0; j <= k; ++j) proj += h[j] * h[j];
       double hk1 = ww - proj > 0.0 ? std::sqrt(ww - proj) : 0.0;
       const bool again = !(hk1 * hk1 > 0.5 * ww);
       for (int j = 0; j <= k; ++j) h2[j] = 0.0;
-      auto subtract = [&](const double* hh, double scale) {
-        std::vector<const double*> xs{w};
-        std::vector<double> as{scale};
-        for (int j = 0; j <= k; ++j) { xs.push_back(V(j)); as.push_back(-hh[j] * scale); }
-        return lin(w, (int)xs.size(), xs.data(), as.data());
-      };
       if (!again) {
-        if ((rc = subtract(h.data(), 1.0 / hk1))) return rc;
+        for (int j = 0; j <= k; ++j) cf[j] = -h[j] / hk1;
+        if ((rc = comb<VT, VT>(w, 1.0 / hk1, k + 1, cf.data(), V<VT>(k + 1), w))) return rc;
       } else {
-        if ((rc = subtract(h.data(), 1.0))) return rc;
-        if ((rc = dot_many(w, V(0), k + 2, h2.data()))) return rc;
+        for (int j = 0; j <= k; ++j) cf[j] = -h[j];
+        if ((rc = comb<VT, double>(w, 1.0, k + 1, cf.data(), w, w))) return rc;
+        if ((rc = dot_basis<VT>(w, k + 1, h2.data()))) return rc;
         const double ww2 = h2[k + 1];
         double proj2 = 0.0;
         for (int j = 0; j <= k; ++j) proj2 += h2[j] * h2[j];
         hk1 = ww2 - proj2 > 0.0 ? std::sqrt(ww2 - proj2) : 0.0;
-        if ((rc = subtract(h2.data(), hk1 > 0.0 ? 1.0 / hk1 : 1.0))) return rc;
+        const double sc = hk1 > 0.0 ? 1.0 / hk1 : 1.0;
+        for (int j = 0; j <= k; ++j) cf[j] = -h2[j] * sc;
+        if ((rc = comb<VT, VT>(w, sc, k + 1, cf.data(), V<VT>(k + 1), w))) return rc;
         ++stats->reorth;
       }
       for (int j = 0; j <= k; ++j) H[(size_t)j * m + k] = h[j] + h2[j];
@@ -305,9 +372,7 @@ struct Solver {
       for (int j = i + 1; j < kd; ++j) t -= H[(size_t)i * m + j] * y[j];
       y[i] = t / H[(size_t)i * m + i];
     }
-    std::vector<const double*> xs;
-    for (int j = 0; j < kd; ++j) xs.push_back(V(j));
-    if ((rc = lin(vec(vY), kd, xs.data(), y.data()))) return rc;
+    if ((rc = comb<VT, double>(nullptr, 0.0, kd, y.data(), vec(vY), vec(vY)))) return rc;
     hipLaunchKernelGGL(correct_kernel, dim3(grid()), dim3(kVecThreads), 0, st, vec(vX), vec(vY), pre, M);
     *iters = kd;
     return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
@@ -319,6 +384,9 @@ size_t vec_stride(const nsk_ctx* c) {
   return (M + 31) / 32 * 32;
 }
 
+// doubles taken by the Krylov basis of gmres_m + 1 vectors (either precision)
+size_t basis_doubles(const nsk_ctx* c, int gmres_m) { return (size_t)(gmres_m + 1) * vec_stride(c); }
+
 int check_opts(const nsk_implicit_opts* o) {
   if (!o) return NSK_EINVAL;
   if (!(o->newton_tol > 0.0) || !std::isfinite(o->newton_tol) || o->newton_max < 1 || o->newton_max > 1000)
@@ -326,6 +394,7 @@ int check_opts(const nsk_implicit_opts* o) {
   if (!(o->gmres_rtol > 0.0) || !(o->gmres_rtol < 1.0) || o->gmres_m < 1 || o->gmres_m > NSK_GMRES_MAX)
     return NSK_EINVAL;
   if (o->precond != 0 && o->precond != 1) return NSK_EINVAL;
+  if (o->basis_fp32 != 0 && o->basis_fp32 != 1) return NSK_EINVAL;
   return NSK_OK;
 }
 
@@ -335,8 +404,8 @@ extern "C" {
 
 size_t nsk_implicit_workspace_bytes(const nsk_ctx* c, int gmres_m) {
   if (!c || gmres_m < 1 || gmres_m > NSK_GMRES_MAX) return 0;
-  const size_t vecs = (size_t)vV0 + gmres_m + 1;
-  return sizeof(double) * (vecs * vec_stride(c) + (size_t)kDotBlocks * (gmres_m + 2) + 256);
+  return sizeof(double) * ((size_t)kNumVec * vec_stride(c) + basis_doubles(c, gmres_m) +
+                           (size_t)kDotBlocks * (gmres_m + 3) + 256);
 }
 
 int nsk_esdirk_step(nsk_ctx* c, void* d_iwork, double dt, int nsteps, const nsk_implicit_opts* opts,
@@ -360,8 +429,10 @@ int nsk_esdirk_step(nsk_ctx* c, void* d_iwork, double dt, int nsteps, const nsk_
   S.M = (long long)c->nvar * c->S;
   S.stride = (long long)vec_stride(c);
   S.m = opts->gmres_m;
-  S.part = reinterpret_cast<double*>(S.base) + (long long)(vV0 + S.m + 1) * S.stride;
-  S.dots = S.part + (long long)kDotBlocks * (S.m + 2);
+  S.f32 = opts->basis_fp32;
+  S.vstride = S.stride;  // elements of either precision (an FP32 basis fills half its region)
+  S.part = reinterpret_cast<double*>(S.base) + (long long)kNumVec * S.stride + (long long)basis_doubles(c, S.m);
+  S.dots = S.part + (long long)kDotBlocks * (S.m + 3);
   S.st = c->stream;
   S.stats = &stats;
   const double dtg = dt * kGamma;

@@ -70,6 +70,7 @@ class nsk_implicit_opts(C.Structure):
         ("gmres_rtol", C.c_double),
         ("gmres_m", C.c_int),
         ("precond", C.c_int),
+        ("basis_fp32", C.c_int),
     ]
 
 
@@ -286,10 +287,10 @@ def nsk_timing_read(ctx: int) -> tuple[float, float, int, float]:
     return out[0], out[1], int(out[2]), out[3]
 
 
-def make_implicit_opts(newton_tol=1e-10, newton_max=20, gmres_rtol=1e-3, gmres_m=20, precond=0):
+def make_implicit_opts(newton_tol=1e-10, newton_max=20, gmres_rtol=1e-3, gmres_m=20, precond=0, basis_fp32=0):
     o = nsk_implicit_opts()
-    o.newton_tol, o.newton_max, o.gmres_rtol, o.gmres_m, o.precond = newton_tol, newton_max, gmres_rtol, gmres_m, \
-        precond
+    o.newton_tol, o.newton_max, o.gmres_rtol, o.gmres_m = newton_tol, newton_max, gmres_rtol, gmres_m
+    o.precond, o.basis_fp32 = precond, basis_fp32
     return o
 
 

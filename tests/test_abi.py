@@ -201,11 +201,11 @@ def test_implicit_host_side_checks():
         M = 5 * 24 * 125
         assert nsk.nsk_implicit_workspace_bytes(ctx, 0) == 0
         assert nsk.nsk_implicit_workspace_bytes(ctx, nsk.NSK_GMRES_MAX + 1) == 0
-        assert nsk.nsk_implicit_workspace_bytes(ctx, 20) >= 8 * (20 + 9) * M
+        assert nsk.nsk_implicit_workspace_bytes(ctx, 20) >= 8 * (13 + 20 + 1) * M
         fake = 256  # never dereferenced: every call below fails its host checks
         ok = nsk.make_implicit_opts()
         for bad in (dict(newton_tol=0.0), dict(newton_max=0), dict(gmres_rtol=1.0), dict(gmres_rtol=0.0),
-                    dict(gmres_m=0), dict(gmres_m=nsk.NSK_GMRES_MAX + 1), dict(precond=2)):
+                    dict(gmres_m=0), dict(gmres_m=nsk.NSK_GMRES_MAX + 1), dict(precond=2), dict(basis_fp32=2)):
             with pytest.raises(nsk.NskError) as e:
                 nsk.nsk_esdirk_step(ctx, fake, 1e-3, 1, nsk.make_implicit_opts(**bad))
             assert e.value.code == nsk.NSK_EINVAL, bad

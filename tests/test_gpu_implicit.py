@@ -51,11 +51,12 @@ def test_esdirk_parity_nsk_1d(O, gpu):
     s.close()
 
 
-@pytest.mark.parametrize("precond", [0, 1])
-def test_esdirk_parity_model2_stiff_1d(O, gpu, precond):
+@pytest.mark.parametrize("precond,basis_fp32", [(0, 0), (1, 0), (1, 1)])
+def test_esdirk_parity_model2_stiff_1d(O, gpu, precond, basis_fp32):
     """Model II with the stiff relaxation source (alpha/beta = 5e5), 1D,
     10 elements, N = 2: 3 steps of 50 times the explicit step, with and
-    without the source preconditioner."""
+    without the source preconditioner, with an FP64 and an FP32 Krylov basis
+    (the Newton residuals stay FP64, so both converge to the same stages)."""
     m, U = I.smooth_random(1, 2, (10,), seed=6, rho_range=(1.6, 1.9), dc=0.0)
     kw = dict(eps=1e-2, kappa=1e-4, alpha=500.0, beta=1e-3)
     P = _problem(O, m, **kw)
@@ -63,7 +64,7 @@ def test_esdirk_parity_model2_stiff_1d(O, gpu, precond):
     ref = E.run(P, U, dt, 3)
     s = _solver(gpu, m, **kw)
     s.set_state(U)
-    st = s.esdirk_step(dt, 3, precond=precond, **TIGHT)
+    st = s.esdirk_step(dt, 3, precond=precond, basis_fp32=basis_fp32, **TIGHT)
     assert st["converged"] == 1
     assert _relerr(s.get_state().cpu().numpy(), ref) <= TOL
     s.close()
@@ -105,7 +106,8 @@ def test_esdirk_preconditioner_cuts_krylov_iterations(gpu):
     assert _relerr(out[1], out[0]) <= 1e-7
 
 
-def test_esdirk_matches_explicit_on_3d_collision(gpu):
+@pytest.mark.parametrize("basis_fp32", [0, 1])
+def test_esdirk_matches_explicit_on_3d_collision(gpu, basis_fp32):
     """The 3D collision geometry (24x12x12, N = 4): 2 implicit steps of 25
     times the explicit step against 50 explicit LSRK4(5) steps; both
     integrators are fourth order, so the two states differ by the time
@@ -118,7 +120,7 @@ def test_esdirk_matches_explicit_on_3d_collision(gpu):
     s.rk_step(dte, 50)
     ref = s.get_state().cpu().numpy()
     s.set_state(U)
-    st = s.esdirk_step(25 * dte, 2, precond=1, newton_tol=1e-10, gmres_rtol=1e-4, gmres_m=40)
+    st = s.esdirk_step(25 * dte, 2, precond=1, newton_tol=1e-10, gmres_rtol=1e-4, gmres_m=40, basis_fp32=basis_fp32)
     assert st["converged"] == 1
     got = s.get_state().cpu().numpy()
     rel = np.linalg.norm(got[0] - ref[0]) / np.linalg.norm(ref[0])
