@@ -212,8 +212,7 @@ int nsk_timing_read(nsk_ctx* ctx, double out[4]);
  * B_i = U_n + dt sum_{j<i} a_ij K_j, is solved by Newton's method (initial
  * guess B_i + dt gamma K_{i-1}); each Newton correction comes from one cycle
  * of right-preconditioned GMRES (at most gmres_m Krylov vectors, classical
- * Gram-Schmidt, repeated when the projection removes more than 1/sqrt(2) of
- * the vector's norm) with the Jacobian-vector product
+ * Gram-Schmidt, repeated as reorth_tol says) with the Jacobian-vector product
  * (R(X + s z) - R(X))/s, s = sqrt(eps_machine)(1 + |X|_2).  K_i = (X - B_i)/
  * (dt gamma); U_{n+1} is the last stage.  Works on FP64 contexts of either
  * model without the closure.
@@ -230,6 +229,9 @@ typedef struct {
   int basis_fp32;    /* 1: Krylov basis stored in FP32 (half the Gram-Schmidt
                         traffic; products, sums, the new vector and all
                         Newton quantities stay FP64); 0: FP64 basis          */
+  double reorth_tol; /* the Gram-Schmidt projection is repeated when
+                        |w - sum h_j V_j|^2 <= reorth_tol |w|^2, [0, 1):
+                        1/2 is Kahan's criterion, 0 never repeats it        */
 } nsk_implicit_opts;
 
 typedef struct {

@@ -204,6 +204,7 @@ struct Solver {
   nsk_implicit_stats* stats;
 
   int f32;            // Krylov basis in FP32
+  double reorth_tol;  // second projection when |w'|^2 <= reorth_tol |w|^2
   long long vstride;  // elements between basis vectors
   double* vec(int k) const { return reinterpret_cast<double*>(base) + (long long)k * stride; }
   template <typename VT>
@@ -319,14 +320,15 @@ struct Solver {
       // classical Gram-Schmidt: one multi-dot gives <w, V_0..V_k> and |w|^2
       // together; |w - sum h_j V_j|^2 then follows from Pythagoras, and the
       // subtraction and the normalisation into V_{k+1} are one combination.
-      // When more than 1/sqrt(2) of |w| cancels (Kahan's criterion) the
-      // projection is repeated on the FP64 w and the norm taken again.
+      // When |w - sum h_j V_j|^2 <= reorth_tol |w|^2 (1/2: Kahan's criterion,
+      // more than 1/sqrt(2) of |w| cancelled) the projection is repeated on
+      // the FP64 w and the norm taken again.
       if ((rc = dot_basis<VT>(w, k + 1, h.data()))) return rc;
       const double ww = h[k + 1];
       double proj = 0.0;
       for (int j = 0; j <= k; ++j) proj += h[j] * h[j];
       double hk1 = ww - proj > 0.0 ? std::sqrt(ww - proj) : 0.0;
-      const bool again = !(hk1 * hk1 > 0.5 * ww);
+      const bool again = !(hk1 * hk1 > reorth_tol * ww) || !(hk1 > 0.0);
       for (int j = 0; j <= k; ++j) h2[j] = 0.0;
       if (!again) {
         for (int j = 0; j <= k; ++j) cf[j] = -h[j] / hk1;
@@ -395,6 +397,7 @@ int check_opts(const nsk_implicit_opts* o) {
     return NSK_EINVAL;
   if (o->precond != 0 && o->precond != 1) return NSK_EINVAL;
   if (o->basis_fp32 != 0 && o->basis_fp32 != 1) return NSK_EINVAL;
+  if (!(o->reorth_tol >= 0.0 && o->reorth_tol < 1.0)) return NSK_EINVAL;
   return NSK_OK;
 }
 
@@ -430,6 +433,7 @@ int nsk_esdirk_step(nsk_ctx* c, void* d_iwork, double dt, int nsteps, const nsk_
   S.stride = (long long)vec_stride(c);
   S.m = opts->gmres_m;
   S.f32 = opts->basis_fp32;
+  S.reorth_tol = opts->reorth_tol;
   S.vstride = S.stride;  // elements of either precision (an FP32 basis fills half its region)
   S.part = reinterpret_cast<double*>(S.base) + (long long)kNumVec * S.stride + (long long)basis_doubles(c, S.m);
   S.dots = S.part + (long long)kDotBlocks * (S.m + 3);

@@ -71,6 +71,7 @@ class nsk_implicit_opts(C.Structure):
         ("gmres_m", C.c_int),
         ("precond", C.c_int),
         ("basis_fp32", C.c_int),
+        ("reorth_tol", C.c_double),
     ]
 
 
@@ -287,10 +288,11 @@ def nsk_timing_read(ctx: int) -> tuple[float, float, int, float]:
     return out[0], out[1], int(out[2]), out[3]
 
 
-def make_implicit_opts(newton_tol=1e-10, newton_max=20, gmres_rtol=1e-3, gmres_m=20, precond=0, basis_fp32=0):
+def make_implicit_opts(newton_tol=1e-10, newton_max=20, gmres_rtol=1e-3, gmres_m=20, precond=0, basis_fp32=0,
+                       reorth_tol=0.5):
     o = nsk_implicit_opts()
     o.newton_tol, o.newton_max, o.gmres_rtol, o.gmres_m = newton_tol, newton_max, gmres_rtol, gmres_m
-    o.precond, o.basis_fp32 = precond, basis_fp32
+    o.precond, o.basis_fp32, o.reorth_tol = precond, basis_fp32, reorth_tol
     return o
 
 

@@ -205,7 +205,8 @@ def test_implicit_host_side_checks():
         fake = 256  # never dereferenced: every call below fails its host checks
         ok = nsk.make_implicit_opts()
         for bad in (dict(newton_tol=0.0), dict(newton_max=0), dict(gmres_rtol=1.0), dict(gmres_rtol=0.0),
-                    dict(gmres_m=0), dict(gmres_m=nsk.NSK_GMRES_MAX + 1), dict(precond=2), dict(basis_fp32=2)):
+                    dict(gmres_m=0), dict(gmres_m=nsk.NSK_GMRES_MAX + 1), dict(precond=2), dict(basis_fp32=2),
+                    dict(reorth_tol=-0.1), dict(reorth_tol=1.0)):
             with pytest.raises(nsk.NskError) as e:
                 nsk.nsk_esdirk_step(ctx, fake, 1e-3, 1, nsk.make_implicit_opts(**bad))
             assert e.value.code == nsk.NSK_EINVAL, bad
