@@ -125,6 +125,17 @@ double or_nsk_lf_speed(const or_prob* P, const double* U);
 double or_nsk_dt(const or_prob* P, const double* U, double cfl);
 int or_nsk_diagnostics(const or_prob* P, const double* U, double* out);
 
+/* ---------------- FV sub-cell shock capturing (Sec. 3.2), model II --------- */
+/* Sub-cell averaging matrix M (row k: mean of each Lagrange polynomial over
+ * sub-cell k of N+1 equal sub-cells) and its inverse, (N+1)^2 row-major. */
+int or_subcell_matrices(int N, double* M, double* Minv);
+/* Persson-Peraire indicator of rho per element (log10 of the share of the
+ * modal energy in the highest modes). */
+int or_persson(const or_prob* P, const double* U, double* ind);
+/* Right-hand side with troubled elements (indicator > threshold) on FV
+ * sub-cells; flags (optional) receives the troubled-element flags. */
+int or_rhs_subcell(const or_prob* P, const double* U, double threshold, double* R, int* flags);
+
 /* ---------------- learned closure (no counterpart in the paper) ------------ */
 #define OR_MLP_IN 4
 #define OR_MLP_HIDDEN 64

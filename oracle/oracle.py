@@ -18,7 +18,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
-SOURCES = ["basis.c", "thermo.c", "lsrk.c", "dg_weak.c", "dg_strong.c", "nsk_orig.c", "mlp.c", "closure.c"]
+SOURCES = ["basis.c", "thermo.c", "lsrk.c", "dg_weak.c", "dg_strong.c", "nsk_orig.c", "subcell.c", "mlp.c",
+           "closure.c"]
 
 
 def build(force: bool = True) -> str:
@@ -107,6 +108,9 @@ def _declare(L):
     L.or_nsk_dt.argtypes = [C.POINTER(_Prob), _dp, C.c_double]
     L.or_nsk_dt.restype = C.c_double
     L.or_nsk_diagnostics.argtypes = [C.POINTER(_Prob), _dp, _dp]
+    L.or_subcell_matrices.argtypes = [C.c_int, _dp, _dp]
+    L.or_persson.argtypes = [C.POINTER(_Prob), _dp, _dp]
+    L.or_rhs_subcell.argtypes = [C.POINTER(_Prob), _dp, C.c_double, _dp, C.POINTER(C.c_int)]
     L.or_gelu.argtypes = [C.c_double]
     L.or_gelu.restype = C.c_double
     L.or_gelu_d.argtypes = [C.c_double]
@@ -352,6 +356,38 @@ def dt(P: Problem, U, cfl: float) -> float:
     if P.model == 1:
         return lib().or_nsk_dt(C.byref(pc), _ptr(U), cfl)
     return lib().or_dt(C.byref(pc), _ptr(U), cfl)
+
+
+def subcell_matrices(N: int):
+    """(M, M^{-1}): sub-cell averaging of the Lagrange basis (or_subcell_matrices)."""
+    n = N + 1
+    M, Mi = np.zeros(n * n), np.zeros(n * n)
+    if lib().or_subcell_matrices(N, _ptr(M), _ptr(Mi)) != 0:
+        raise RuntimeError("or_subcell_matrices failed")
+    return M.reshape(n, n), Mi.reshape(n, n)
+
+
+def persson(P: Problem, U) -> np.ndarray:
+    """Persson-Peraire indicator of rho per element (or_persson)."""
+    U = _state(P, U)
+    ind = np.zeros(P.nelem)
+    pc = P.c()
+    if lib().or_persson(C.byref(pc), _ptr(U), _ptr(ind)) != 0:
+        raise RuntimeError("or_persson failed")
+    return ind
+
+
+def rhs_subcell(P: Problem, U, threshold: float):
+    """Right-hand side with FV sub-cells in troubled elements
+    (or_rhs_subcell); returns (R, flags)."""
+    U = _state(P, U)
+    R = np.zeros_like(U)
+    flags = np.zeros(P.nelem, dtype=np.int32)
+    pc = P.c()
+    if lib().or_rhs_subcell(C.byref(pc), _ptr(U), float(threshold), _ptr(R),
+                            flags.ctypes.data_as(C.POINTER(C.c_int))) != 0:
+        raise RuntimeError("or_rhs_subcell failed")
+    return R.reshape(P.shape()), flags.astype(bool)
 
 
 def lf_speed(P: Problem, U) -> float:
