@@ -29,6 +29,18 @@
  * recomputed at every evaluation; the second-order face flux is the mean of
  * the traces of the nodal Sigma.
  *
+ * FV sub-cell shock capturing (Sec. 3.2, subcell = 1, model II): at every
+ * right-hand side, elements whose Persson-Peraire indicator of rho (log10 of
+ * the share of the orthonormal-Legendre modal energy in the modes whose
+ * largest one-direction degree is N) exceeds subcell_threshold are treated
+ * on (N+1)^dim equidistant sub-cells: sub-cell means by exact integration,
+ * MinMod-limited reconstruction of (rho, v, c), Rusanov flux, viscous flux
+ * from the means of the adjacent central-difference sub-cell gradients, the
+ * source at the sub-cell means; on faces shared with DG elements the
+ * sub-face means of the DG face-flux polynomial (mass is conserved exactly);
+ * the element's nodal rate is the inverse sub-cell averaging of its
+ * sub-cell rates, so a Runge-Kutta stage advances the sub-cell means.
+ *
  * Mesh: periodic tensor-product grid of axis-aligned box elements.
  *
  * Data layout of every state array (device memory, double):
@@ -90,6 +102,12 @@ typedef struct {
   int model;      /* 0 = relaxation model II (Sec. 2.3); 1 = the original
                      NSK equations (Sec. 2.2): flux must be 2, precision 0,
                      closure 0; alpha, beta and diss_c are not used          */
+  int subcell;    /* 1: FV sub-cell shock capturing (Sec. 3.2) in elements
+                     whose Persson-Peraire indicator exceeds
+                     subcell_threshold (model 0, flux 0, precision 0,
+                     closure 0 only)                                          */
+  double subcell_threshold; /* log10 of the share of the modal energy of rho
+                     in the highest modes above which an element is troubled */
 } nsk_params;
 
 typedef struct {
@@ -109,7 +127,9 @@ typedef struct {
  * of LDS),
  * non-increasing breakpoints, T outside (0,1), eps < 0, kappa < 0, model
  * outside 0..1, and for model 0 alpha <= 6 (1 - T), beta <= 0 or flux
- * outside 0..1; for model 1 flux != 2, precision != 0 or closure != 0.
+ * outside 0..1; for model 1 flux != 2, precision != 0, closure != 0 or
+ * subcell != 0; subcell = 1 with flux, precision or closure not 0, or a
+ * non-finite threshold.
  * *out is set on success. */
 int nsk_create(const nsk_mesh* mesh, const nsk_params* params, nsk_ctx** out);
 
@@ -190,6 +210,12 @@ int nsk_autotune(nsk_ctx* ctx, int reps, int* variant_out, int* order_out, doubl
 
 /* Changes alpha, beta, eps, kappa of an existing context (same mesh). */
 int nsk_set_params(nsk_ctx* ctx, const nsk_params* params);
+
+/* Troubled-element flags (0/1 per element, element order) of the last
+ * right-hand side evaluated with subcell = 1, copied to the device array
+ * d_flags (nelem ints).  Asynchronous.  NSK_EINVAL for contexts without
+ * subcell. */
+int nsk_subcell_flags(nsk_ctx* ctx, int* d_flags);
 
 /* Kernel timing with HIP events on the bound stream (measurement only).
  * nsk_timing_enable(ctx, 1) makes every stage enqueued by nsk_rk_step record
@@ -359,8 +385,8 @@ int nsk_mlp_moments(const float* d_Y, long long n, int ncol, void* d_ws, double*
  * ------------------------------------------------------------------------ */
 typedef struct nsk_batch nsk_batch;
 
-/* meshes[0..ninst-1] must all be 3D, params->model 0, params->closure 0 and
- * params->flux 0 (Rusanov) (NSK_EUNSUPPORTED otherwise); the validation rules of
+/* meshes[0..ninst-1] must all be 3D, params->model 0, params->closure 0,
+ * params->subcell 0 and params->flux 0 (Rusanov) (NSK_EUNSUPPORTED otherwise); the validation rules of
  * nsk_create apply per instance.  Host only. */
 int nsk_batch_create(const nsk_mesh* meshes, int ninst, const nsk_params* params, nsk_batch** out);
 

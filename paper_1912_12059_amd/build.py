@@ -12,6 +12,7 @@ DEPENDS = SOURCES + [
     os.path.join(HERE, "csrc", "dg_kernels.hpp"),
     os.path.join(HERE, "csrc", "closure.hpp"),
     os.path.join(HERE, "csrc", "host_common.hpp"),
+    os.path.join(HERE, "csrc", "subcell.hpp"),
     os.path.join(REPO, "include", "nsk.h"),
 ]
 

@@ -280,7 +280,7 @@ int nsk_batch_create(const nsk_mesh* meshes, int ninst, const nsk_params* params
   *out = nullptr;
   for (int i = 0; i < ninst; ++i)
     if (meshes[i].dim != 3) return NSK_EUNSUPPORTED;
-  if (params->model != 0 || params->closure != 0 || params->flux != 0) return NSK_EUNSUPPORTED;
+  if (params->model != 0 || params->closure != 0 || params->flux != 0 || params->subcell != 0) return NSK_EUNSUPPORTED;
   nsk_batch* b = new (std::nothrow) nsk_batch();
   if (!b) return NSK_EINVAL;
   b->ninst = ninst;

@@ -112,6 +112,7 @@ struct StageArgs {
   int mode;          // 0: write R; 1: Runge-Kutta stage update
   const float* closure = nullptr;  // learned closure source [dim+1][elem][node], or none
   const double* lf = nullptr;      // global Lax-Friedrichs speed (original NSK path)
+  const int* skip = nullptr;       // elements left to the FV sub-cell kernel (flag per element)
 };
 
 // -------------------------------------------------------------------------
@@ -538,6 +539,8 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
   if (tid < NP * NP) sD[tid / NP][tid % NP] = R(bas.Dhat[tid / NP][tid % NP]);
   if (tid < NP) { sLm[tid] = R(bas.Lm[tid]); sLp[tid] = R(bas.Lp[tid]); sIw[tid] = R(bas.invw[tid]); }
   elem_info<DIM, EPB>(info, msh, L, tid);
+  // elements on FV sub-cells are updated by their own kernel: treat them as absent
+  if (st.skip && tid < EPB && info.e[tid] >= 0 && st.skip[info.e[tid]]) info.e[tid] = -1;
   __syncthreads();
 
   const int el = tid / NN, n = tid - (tid / NN) * NN;

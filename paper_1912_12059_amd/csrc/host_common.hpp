@@ -144,6 +144,9 @@ struct nsk_ctx {
   size_t off_U2 = 0, off_G = 0, off_h2[3] = {0, 0, 0}, off_wq = 0, off_order = 0, off_part = 0, off_out = 0;
   size_t off_cl = 0;  // closure source [dim+1][elem][node], FP32 (closure contexts only)
   size_t off_lf = 0;  // original NSK path: global LF speed, then per-workgroup partial maxima
+  // FV sub-cells: flags, the elements needing sub-cell means, the means
+  size_t off_sc_flags = 0, off_sc_need = 0, off_sc_Ub = 0;
+  double sc_M[kMaxNP][kMaxNP] = {}, sc_Minv[kMaxNP][kMaxNP] = {}, sc_V[kMaxNP][kMaxNP] = {};
   size_t ws_bytes = 0;
   int diag_blocks = 0;
   int tile = 0;      // elements-per-workgroup variant
@@ -173,11 +176,15 @@ int check_params(const nsk_params* p) {
   if (!(p->T > 0.0 && p->T < 1.0)) return NSK_EINVAL;
   if (!(p->eps >= 0.0) || !(p->kappa >= 0.0) || !std::isfinite(p->eps) || !std::isfinite(p->kappa))
     return NSK_EINVAL;
+  if (p->subcell != 0 && p->subcell != 1) return NSK_EINVAL;
   if (p->model == 1) {
     // original NSK equations: global Lax-Friedrichs flux, FP64, no closure
-    if (p->flux != 2 || p->precision != 0 || p->closure != 0) return NSK_EINVAL;
+    if (p->flux != 2 || p->precision != 0 || p->closure != 0 || p->subcell != 0) return NSK_EINVAL;
     return NSK_OK;
   }
+  if (p->subcell == 1 &&
+      (p->flux != 0 || p->precision != 0 || p->closure != 0 || !std::isfinite(p->subcell_threshold)))
+    return NSK_EINVAL;
   if (p->model != 0) return NSK_EINVAL;
   if (!(p->alpha > 0.0) || !(p->beta > 0.0)) return NSK_EINVAL;
   if (!std::isfinite(p->alpha) || !std::isfinite(p->beta)) return NSK_EINVAL;
@@ -299,4 +306,52 @@ struct Epb {
   static constexpr int V1 = V0 / 2 < 1 ? 1 : V0 / 2;
 };
 
+}  // namespace
+
+namespace {
+// FV sub-cell matrices for degree N: M[k][j] the mean of the Lagrange
+// polynomial l_j over sub-cell k of N+1 equal sub-cells of [-1, 1] (Gauss
+// quadrature with N+1 points on the sub-cell, exact), Minv its inverse, and
+// V[k][i] = w_i P_k(x_i) with P_k the orthonormal Legendre polynomial, which
+// maps nodal values to modal coefficients.
+void subcell_matrices(const Basis1D& b, double M[kMaxNP][kMaxNP], double Minv[kMaxNP][kMaxNP],
+                      double V[kMaxNP][kMaxNP]) {
+  const int n = b.np;
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j) {
+      double acc = 0.0;
+      for (int q = 0; q < n; ++q) {
+        const double x = -1.0 + (2.0 / n) * (k + 0.5 * (b.x[q] + 1.0));
+        double l = 1.0;
+        for (int m = 0; m < n; ++m)
+          if (m != j) l *= (x - b.x[m]) / (b.x[j] - b.x[m]);
+        acc += 0.5 * b.w[q] * l;
+      }
+      M[k][j] = acc;
+    }
+  double A[kMaxNP][2 * kMaxNP];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < 2 * n; ++j) A[i][j] = j < n ? M[i][j] : (j - n == i ? 1.0 : 0.0);
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+    for (int j = 0; j < 2 * n; ++j) std::swap(A[c][j], A[piv][j]);
+    const double d = A[c][c];
+    for (int j = 0; j < 2 * n; ++j) A[c][j] /= d;
+    for (int r = 0; r < n; ++r)
+      if (r != c) {
+        const double f = A[r][c];
+        for (int j = 0; j < 2 * n; ++j) A[r][j] -= f * A[c][j];
+      }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Minv[i][j] = A[i][n + j];
+  for (int k = 0; k < n; ++k)
+    for (int i = 0; i < n; ++i) {
+      long double P, dP;
+      legendre_eval(k, (long double)b.x[i], P, dP);
+      V[k][i] = b.w[i] * std::sqrt(k + 0.5) * (double)P;
+    }
+}
 }  // namespace

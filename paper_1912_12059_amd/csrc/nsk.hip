@@ -18,6 +18,7 @@
 #include "closure.hpp"
 #include "dg_kernels.hpp"
 #include "host_common.hpp"
+#include "subcell.hpp"
 
 using namespace nsk;
 
@@ -79,10 +80,57 @@ int launch_stage_nsk(nsk_ctx* c, const double* Uin, double* Uout, double* dU, co
   return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
 }
 
+SubcellArgs subcell_args(const nsk_ctx* c) {
+  SubcellArgs a;
+  std::memset(&a, 0, sizeof(a));
+  std::memcpy(a.M, c->sc_M, sizeof(a.M));
+  std::memcpy(a.Minv, c->sc_Minv, sizeof(a.Minv));
+  std::memcpy(a.V, c->sc_V, sizeof(a.V));
+  a.threshold = c->par.subcell_threshold;
+  a.flags = reinterpret_cast<int*>(c->work + c->off_sc_flags);
+  a.need = reinterpret_cast<int*>(c->work + c->off_sc_need);
+  a.Ub = reinterpret_cast<double*>(c->work + c->off_sc_Ub);
+  return a;
+}
+
+// Model II with FV sub-cells: indicator, the elements needing sub-cell means,
+// the means, the lifting, the DG right-hand side of the untroubled
+// elements, then the FV sub-cell update of the troubled ones.
+template <int DIM, int NP, int EPB>
+int launch_stage_subcell(nsk_ctx* c, const double* Uin, double* Uout, double* dU, const StageArgs& st) {
+  using Tl = Tile<DIM, NP, EPB>;
+  const BasisArgs b = basis_args(c);
+  const MeshArgs m = mesh_args(c);
+  const PhysArgs p = phys_args(c);
+  const SubcellArgs sa = subcell_args(c);
+  double* G = reinterpret_cast<double*>(c->work + c->off_G);
+  const unsigned blocks = (unsigned)((c->E + EPB - 1) / EPB);
+  const unsigned E = (unsigned)c->E;
+  hipEvent_t* ev = stage_events(c, st);
+  if (ev) (void)hipEventRecord(ev[0], c->stream);
+  hipLaunchKernelGGL((lift_kernel<DIM, NP, EPB, double, double>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream, Uin,
+                     G, b, m, p);
+  if (ev) (void)hipEventRecord(ev[1], c->stream);
+  hipLaunchKernelGGL((persson_kernel<DIM, NP>), dim3(E), dim3(kSubThreads), 0, c->stream, Uin, sa, m);
+  hipLaunchKernelGGL((dilate_kernel<DIM>), dim3((E + kSubThreads - 1) / kSubThreads), dim3(kSubThreads), 0,
+                     c->stream, sa, m);
+  hipLaunchKernelGGL((means_kernel<DIM, NP>), dim3(E), dim3(kSubThreads), 0, c->stream, Uin, sa, m);
+  if (ev) (void)hipEventRecord(ev[2], c->stream);
+  StageArgs sta = st;
+  sta.skip = sa.flags;
+  hipLaunchKernelGGL((rhs_kernel<DIM, NP, EPB, double, double, 0>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream,
+                     Uin, G, Uout, dU, b, m, p, sta);
+  hipLaunchKernelGGL((fv_kernel<DIM, NP>), dim3(E), dim3(kSubThreads), 0, c->stream, Uin, G, Uout, dU, b, m, p, sta,
+                     sa);
+  if (ev) (void)hipEventRecord(ev[3], c->stream);
+  return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
+}
+
 template <int DIM, int NP, int EPB, typename R, typename GT>
 int launch_stage_e(nsk_ctx* c, const double* Uin, double* Uout, double* dU, const StageArgs& st) {
   if constexpr (std::is_same<R, double>::value) {
     if (c->par.model == 1) return launch_stage_nsk<DIM, NP, EPB>(c, Uin, Uout, dU, st);
+    if (c->par.subcell == 1) return launch_stage_subcell<DIM, NP, EPB>(c, Uin, Uout, dU, st);
   }
   using Tl = Tile<DIM, NP, EPB>;
   const BasisArgs b = basis_args(c);
@@ -305,6 +353,15 @@ int nsk_create(const nsk_mesh* mesh, const nsk_params* params, nsk_ctx** out) {
     c->off_cl = off;
     off = align256(off + sizeof(float) * (size_t)(c->dim + 1) * c->S);
   }
+  if (c->par.subcell == 1) {
+    subcell_matrices(c->basis, c->sc_M, c->sc_Minv, c->sc_V);
+    c->off_sc_flags = off;
+    off = align256(off + sizeof(int) * (size_t)c->E);
+    c->off_sc_need = off;
+    off = align256(off + sizeof(int) * (size_t)c->E);
+    c->off_sc_Ub = off;
+    off = align256(off + sizeof(double) * (size_t)c->nvar * c->S);
+  }
   if (c->par.model == 1) {
     // global LF speed, the second-level maxima and one partial maximum per
     // lifting workgroup (at most one workgroup per element)
@@ -323,6 +380,15 @@ void nsk_destroy(nsk_ctx* c) {
   if (c->bound) (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   delete c;
+}
+
+int nsk_subcell_flags(nsk_ctx* c, int* d_flags) {
+  if (!c || !d_flags || c->par.subcell != 1) return NSK_EINVAL;
+  if (!c->bound) return NSK_EUNBOUND;
+  return hipMemcpyAsync(d_flags, c->work + c->off_sc_flags, sizeof(int) * (size_t)c->E, hipMemcpyDeviceToDevice,
+                        c->stream) == hipSuccess
+             ? NSK_OK
+             : NSK_EHIP;
 }
 
 int nsk_timing_enable(nsk_ctx* c, int enable) {
@@ -569,7 +635,8 @@ int nsk_set_params(nsk_ctx* c, const nsk_params* p) {
   int rc = check_params(p);
   if (rc) return rc;
   // the workspace layout depends on the model, the precision and the closure flag
-  if (p->model != c->par.model || p->precision != c->par.precision || p->closure != c->par.closure)
+  if (p->model != c->par.model || p->precision != c->par.precision || p->closure != c->par.closure ||
+      p->subcell != c->par.subcell)
     return NSK_EINVAL;
   c->par = *p;
   spinodal_band(c->par.T, c->rho_lo64, c->rho_hi64);

@@ -53,6 +53,8 @@ class nsk_params(C.Structure):
         ("precision", C.c_int),
         ("closure", C.c_int),
         ("model", C.c_int),
+        ("subcell", C.c_int),
+        ("subcell_threshold", C.c_double),
     ]
 
 
@@ -148,6 +150,7 @@ def load() -> C.CDLL:
         L.nsk_batch_set_group.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
         L.nsk_timing_enable.argtypes = [vp, C.c_int]
         L.nsk_timing_read.argtypes = [vp, dp]
+        L.nsk_subcell_flags.argtypes = [vp, vp]
         L.nsk_implicit_workspace_bytes.argtypes = [vp, C.c_int]
         L.nsk_implicit_workspace_bytes.restype = C.c_size_t
         L.nsk_esdirk_step.argtypes = [vp, vp, C.c_double, C.c_int, C.POINTER(nsk_implicit_opts),
@@ -197,7 +200,7 @@ def make_mesh(dim, N, nel, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), xbreaks=None)
 
 
 def make_params(T=0.85, eps=1e-3, kappa=1e-5, alpha=500.0, beta=1e-3, diss_c=1, precision=0, flux=0, closure=0,
-                model=0):
+                model=0, subcell=0, subcell_threshold=0.0):
     """model 0: relaxation model II; model 1: the original NSK equations
     (flux 2, the global Lax-Friedrichs flux, is then the default)."""
     p = nsk_params()
@@ -205,6 +208,7 @@ def make_params(T=0.85, eps=1e-3, kappa=1e-5, alpha=500.0, beta=1e-3, diss_c=1, 
     if model == 1 and flux == 0:
         flux = 2
     p.flux, p.diss_c, p.precision, p.closure, p.model = flux, diss_c, precision, closure, model
+    p.subcell, p.subcell_threshold = subcell, subcell_threshold
     return p
 
 
@@ -286,6 +290,10 @@ def nsk_timing_read(ctx: int) -> tuple[float, float, int, float]:
     out = (C.c_double * 4)()
     _check("nsk_timing_read", load().nsk_timing_read(ctx, out))
     return out[0], out[1], int(out[2]), out[3]
+
+
+def nsk_subcell_flags(ctx: int, d_flags_ptr: int) -> None:
+    _check("nsk_subcell_flags", load().nsk_subcell_flags(ctx, d_flags_ptr))
 
 
 def make_implicit_opts(newton_tol=1e-10, newton_max=20, gmres_rtol=1e-3, gmres_m=20, precond=0, basis_fp32=0,
@@ -439,6 +447,8 @@ class Solver:
     flux: int = 0
     closure: int = 0
     model: int = 0  # 0: relaxation model II, 1: original NSK (state rho, rho v)
+    subcell: int = 0  # 1: FV sub-cells in elements whose indicator exceeds subcell_threshold
+    subcell_threshold: float = 0.0
     xbreaks: list | None = None
     device: str = "cuda:0"
     stream: object = None
@@ -449,7 +459,8 @@ class Solver:
 
         mesh, keep = make_mesh(self.dim, self.N, self.nel, self.lo, self.hi, self.xbreaks)
         params = make_params(self.T, self.eps, self.kappa, self.alpha, self.beta, self.diss_c, self.precision,
-                             flux=self.flux, closure=self.closure, model=self.model)
+                             flux=self.flux, closure=self.closure, model=self.model, subcell=self.subcell,
+                             subcell_threshold=self.subcell_threshold)
         self.ctx = nsk_create(mesh, params)
         del keep
         n = nsk_state_size(self.ctx)
@@ -502,6 +513,15 @@ class Solver:
 
     def dt_estimate(self, cfl: float) -> float:
         return nsk_dt_estimate(self.ctx, cfl)
+
+    def subcell_flags(self):
+        """Troubled-element flags of the last right-hand side (numpy bool)."""
+        import torch
+
+        f = torch.zeros(self.nelem, dtype=torch.int32, device=self.U.device)
+        nsk_subcell_flags(self.ctx, f.data_ptr())
+        self.stream.synchronize()
+        return f.cpu().numpy().astype(bool)
 
     def esdirk_step(self, dt: float, nsteps: int = 1, **opts) -> dict:
         """Implicit ESDIRK4(6) steps (nsk_esdirk_step); the Krylov workspace

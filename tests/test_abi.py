@@ -229,3 +229,37 @@ def test_implicit_host_side_checks():
     finally:
         for c in (ctx, mixed, orig):
             nsk.nsk_destroy(c)
+
+
+def test_subcell_host_side_checks():
+    """FV sub-cells: model II with the Rusanov flux in FP64 without the
+    closure only; the flags call needs a sub-cell context; the workspace
+    holds the flags and the sub-cell means."""
+    m, keep = _ok_mesh()
+    plain = nsk.nsk_create(m, nsk.make_params())
+    sc = nsk.nsk_create(m, nsk.make_params(subcell=1, subcell_threshold=-3.0))
+    try:
+        # flags, the needed-element marks and the sub-cell means (a state's worth)
+        assert nsk.nsk_workspace_bytes(sc) >= nsk.nsk_workspace_bytes(plain) + 8 * 5 * 24 * 125
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_subcell_flags(plain, 256)
+        assert e.value.code == nsk.NSK_EINVAL
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_subcell_flags(sc, 256)  # not bound yet
+        assert e.value.code == nsk.NSK_EUNBOUND
+        with pytest.raises(nsk.NskError):
+            nsk.nsk_set_params(sc, nsk.make_params())  # the sub-cell workspace is part of the layout
+    finally:
+        nsk.nsk_destroy(plain)
+        nsk.nsk_destroy(sc)
+    for bad in (dict(flux=1), dict(precision=1), dict(closure=1), dict(subcell=2),
+                dict(subcell_threshold=float("nan")), dict(model=1, flux=2)):
+        kw = dict(subcell=1, subcell_threshold=-3.0)
+        kw.update(bad)
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_create(m, nsk.make_params(**kw))
+        assert e.value.code == nsk.NSK_EINVAL, bad
+    bm, bkeep = nsk.make_mesh(3, 3, (2, 2, 2))
+    with pytest.raises(nsk.NskError) as e:
+        nsk.nsk_batch_create([bm], nsk.make_params(subcell=1, subcell_threshold=-3.0))
+    assert e.value.code == nsk.NSK_EUNSUPPORTED
