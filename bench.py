@@ -137,15 +137,17 @@ def cpu_baseline(name: str, sample, sub, budget_s: float = 20.0):
     }
 
 
-def run_form(nsk, m, U0, w, precision: int, steps: int, warmup: int, tile: str, flux: int = 0, model: int = 0):
+def run_form(nsk, m, U0, w, precision: int, steps: int, warmup: int, tile: str, flux: int = 0, model: int = 0,
+             subcell_threshold=None):
     """Time `steps` LSRK4(5) steps of one form (precision, numerical flux,
     model) from the resident state U0 (torch, device).  Returns timings, the
     stage-kernel means from HIP events on the bound stream, and the final
     state (device)."""
     import torch
 
+    sc = {} if subcell_threshold is None else dict(subcell=1, subcell_threshold=subcell_threshold)
     s = nsk.Solver(dim=m.dim, N=m.N, nel=tuple(m.nel), lo=tuple(m.lo), hi=tuple(m.hi), alpha=w["alpha"],
-                   beta=1e-3, eps=1e-3, kappa=1e-5, precision=precision, flux=flux, model=model)
+                   beta=1e-3, eps=1e-3, kappa=1e-5, precision=precision, flux=flux, model=model, **sc)
     s.set_state(U0)
     dt = s.dt_estimate(0.5)
     if tile == "auto":
@@ -172,12 +174,13 @@ def run_form(nsk, m, U0, w, precision: int, steps: int, warmup: int, tile: str, 
     ms = e0.elapsed_time(e1)
     ms_lift, ms_rhs, nst, ms_mid = nsk.nsk_timing_read(s.ctx)
     nsk.nsk_timing_enable(s.ctx, 0)
+    troubled = float(s.subcell_flags().mean()) if subcell_threshold is not None else None
     diag = s.diagnostics()
     final = s.get_state()
     s.close()
     return {"ms": ms, "wall": wall, "ms_lift": ms_lift / max(nst, 1), "ms_rhs": ms_rhs / max(nst, 1),
             "ms_mid": ms_mid / max(nst, 1), "dt": dt, "variant": variant, "order": order, "tune_ms": tune_ms,
-            "diag": diag, "final": final}
+            "diag": diag, "final": final, "troubled": troubled}
 
 
 def nsk_bytes_per_node(dim: int, stage_first: bool) -> dict:
@@ -220,6 +223,27 @@ def run_nsk_form(nsk, m, U0, w, steps: int, warmup: int, tile: str, ref: dict):
         "tile": {"variant": r["variant"], "order": r["order"]},
         "physics": "kappa=1e-5, eps=1e-3, no alpha/beta; state (rho, rho v) of the same collision",
     }
+
+
+def run_subcell_form(nsk, m, U0, w, ref: dict, thresholds=(-7.5, -9.0, -12.0, -1e9), steps: int = 10,
+                     warmup: int = 2):
+    """FV sub-cell shock capturing (model II, FP64) on the same workload at
+    several indicator thresholds (the last one troubles every element): rate
+    against the FP64 DG run, the troubled fraction at the last stage, and the
+    stage time split into the lifting, the indicator/means kernels and the DG
+    right-hand side plus the FV sub-cell kernel."""
+    dofs = m.nelem * m.nnode
+    out = []
+    for thr in thresholds:
+        r = run_form(nsk, m, U0, w, 0, steps, warmup, "0,4", subcell_threshold=thr)
+        out.append({"threshold": thr, "troubled_fraction": r["troubled"],
+                    "value": dofs * 5 * steps / (r["ms"] * 1e-3), "unit": "DOF-stage/s",
+                    "ms_per_step": r["ms"] / steps, "rel_to_dg_fp64": (ref["ms"] / ref["steps"]) / (r["ms"] / steps),
+                    "lift_ms": r["ms_lift"], "indicator_and_means_ms": r["ms_mid"],
+                    "dg_rhs_plus_fv_ms": r["ms_rhs"], "status_after": r["diag"]["status"]})
+        print(f"[bench] subcell threshold {thr:g}: troubled {r['troubled']:.4f}, {r['ms'] / steps:.2f} ms/step",
+              file=sys.stderr, flush=True)
+    return out
 
 
 def run_implicit_form(nsk, m, U0, w, factors=(100, 200), reference: bool = True):
@@ -576,6 +600,8 @@ def main() -> int:
     ap.add_argument("--only-closure", action="store_true", help="run only the closure form (prints its block)")
     ap.add_argument("--only-implicit", action="store_true",
                     help="run only one implicit step of 100x the explicit step, no explicit reference (profiling)")
+    ap.add_argument("--only-subcell", type=float, default=None, metavar="THRESHOLD",
+                    help="run only the FV sub-cell form at this indicator threshold (profiling)")
     ap.add_argument("--only-nsk", action="store_true",
                     help="run only the original NSK form on the workload (prints its block)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -609,6 +635,15 @@ def main() -> int:
     print(f"[bench] building {args.workload} state", file=sys.stderr, flush=True)
     m, U = build_state(args.workload)
     U0 = torch.from_numpy(U.reshape(-1)).to("cuda:0")
+    if args.only_subcell is not None:
+        del U
+        r = run_form(nsk, m, U0, w, 0, args.steps, args.warmup, args.tile, subcell_threshold=args.only_subcell)
+        dofs = m.nelem * m.nnode
+        print(json.dumps({"subcell": {"threshold": args.only_subcell, "troubled_fraction": r["troubled"],
+                                      "value": dofs * 5 * args.steps / (r["ms"] * 1e-3),
+                                      "ms_per_step": r["ms"] / args.steps, "lift_ms": r["ms_lift"],
+                                      "indicator_and_means_ms": r["ms_mid"], "dg_rhs_plus_fv_ms": r["ms_rhs"]}}))
+        return 0
     if args.only_implicit:
         del U
         print(json.dumps({"implicit_esdirk": run_implicit_form(nsk, m, U0, w, (100,), reference=False)}))
@@ -723,6 +758,7 @@ def main() -> int:
         out["forms"]["nsk_original_fp64"] = run_nsk_form(nsk, m, U0, w, args.steps, args.warmup, args.tile, f64)
         if not args.no_implicit:
             out["forms"]["implicit_esdirk"] = run_implicit_form(nsk, m, U0, w)
+        out["forms"]["subcell_fp64"] = run_subcell_form(nsk, m, U0, w, dict(f64, steps=args.steps))
     del forms
     if not args.no_forms and not args.no_batched and args.workload == "3d-collision":
         out.setdefault("forms", {})["batched"] = run_batched(nsk, 10, 2)

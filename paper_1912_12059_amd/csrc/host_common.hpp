@@ -145,7 +145,7 @@ struct nsk_ctx {
   size_t off_cl = 0;  // closure source [dim+1][elem][node], FP32 (closure contexts only)
   size_t off_lf = 0;  // original NSK path: global LF speed, then per-workgroup partial maxima
   // FV sub-cells: flags, the elements needing sub-cell means, the means
-  size_t off_sc_flags = 0, off_sc_need = 0, off_sc_Ub = 0;
+  size_t off_sc_flags = 0, off_sc_need = 0, off_sc_Ub = 0, off_sc_Gb = 0;
   double sc_M[kMaxNP][kMaxNP] = {}, sc_Minv[kMaxNP][kMaxNP] = {}, sc_V[kMaxNP][kMaxNP] = {};
   size_t ws_bytes = 0;
   int diag_blocks = 0;

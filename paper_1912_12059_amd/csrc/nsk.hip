@@ -90,6 +90,7 @@ SubcellArgs subcell_args(const nsk_ctx* c) {
   a.flags = reinterpret_cast<int*>(c->work + c->off_sc_flags);
   a.need = reinterpret_cast<int*>(c->work + c->off_sc_need);
   a.Ub = reinterpret_cast<double*>(c->work + c->off_sc_Ub);
+  a.Gb = reinterpret_cast<double*>(c->work + c->off_sc_Gb);
   return a;
 }
 
@@ -111,10 +112,13 @@ int launch_stage_subcell(nsk_ctx* c, const double* Uin, double* Uout, double* dU
   hipLaunchKernelGGL((lift_kernel<DIM, NP, EPB, double, double>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream, Uin,
                      G, b, m, p);
   if (ev) (void)hipEventRecord(ev[1], c->stream);
-  hipLaunchKernelGGL((persson_kernel<DIM, NP>), dim3(E), dim3(kSubThreads), 0, c->stream, Uin, sa, m);
+  constexpr int EPG = PerssonTile<DIM, NP>::EPG;
+  hipLaunchKernelGGL((persson_kernel<DIM, NP>), dim3((E + EPG - 1) / EPG), dim3(kSubThreads), 0, c->stream, Uin, sa,
+                     m);
   hipLaunchKernelGGL((dilate_kernel<DIM>), dim3((E + kSubThreads - 1) / kSubThreads), dim3(kSubThreads), 0,
                      c->stream, sa, m);
   hipLaunchKernelGGL((means_kernel<DIM, NP>), dim3(E), dim3(kSubThreads), 0, c->stream, Uin, sa, m);
+  hipLaunchKernelGGL((grad_kernel<DIM, NP>), dim3(E), dim3(kSubThreads), 0, c->stream, sa, m);
   if (ev) (void)hipEventRecord(ev[2], c->stream);
   StageArgs sta = st;
   sta.skip = sa.flags;
@@ -361,6 +365,8 @@ int nsk_create(const nsk_mesh* mesh, const nsk_params* params, nsk_ctx** out) {
     off = align256(off + sizeof(int) * (size_t)c->E);
     c->off_sc_Ub = off;
     off = align256(off + sizeof(double) * (size_t)c->nvar * c->S);
+    c->off_sc_Gb = off;
+    off = align256(off + sizeof(double) * (size_t)c->dim * (c->dim + 1) * c->S);
   }
   if (c->par.model == 1) {
     // global LF speed, the second-level maxima and one partial maximum per

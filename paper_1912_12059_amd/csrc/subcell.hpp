@@ -10,6 +10,8 @@
 //                   stencils read);
 //   means_kernel    sub-cell means Ub = (M x M x M) U of the needed elements,
 //                   M[k][j] the mean of l_j over sub-cell k of N+1 equal ones;
+//   grad_kernel     the central-difference sub-cell gradients of (v, c) of the
+//                   troubled elements (all the FV fluxes and sources use);
 //   (the DG right-hand-side kernel skips flagged elements)
 //   fv_kernel       troubled elements on (N+1)^dim sub-cells:
 //                   MinMod-limited reconstruction of (rho, v, c), Rusanov flux,
@@ -34,10 +36,8 @@ struct SubcellArgs {
   int* flags;
   int* need;
   double* Ub;                   // sub-cell means, layout of U
+  double* Gb;                   // sub-cell gradients of (v, c) of troubled elements, [dd*(dim+1)+j][elem][sub-cell]
 };
-
-template <int NP>
-__host__ __device__ constexpr int ipow_dim(int dim) { return dim == 1 ? NP : (dim == 2 ? NP * NP : NP * NP * NP); }
 
 // element index of e shifted by (sx, sy, sz) with periodic wrap
 __device__ __forceinline__ int shifted_elem(const MeshArgs& m, int e, int sx, int sy, int sz) {
@@ -72,50 +72,53 @@ __device__ __forceinline__ void sweep(const double (*A)[kMaxNP], const double* a
 
 constexpr int kSubThreads = 256;
 
+// elements of the indicator kernel per workgroup (one thread per node)
+template <int DIM, int NP>
+struct PerssonTile {
+  static constexpr int NN = ipow<NP, DIM>::v;
+  static constexpr int EPG = kSubThreads / NN > 0 ? kSubThreads / NN : 1;
+};
+
 template <int DIM, int NP>
 __global__ void __launch_bounds__(kSubThreads) persson_kernel(const double* __restrict__ U, SubcellArgs sa,
                                                               MeshArgs msh) {
-  constexpr int NN = ipow<NP, DIM>::v;
-  __shared__ double a[NN], b[NN];
-  __shared__ double red[2][kSubThreads / 64];
-  const int e = blockIdx.x, t = threadIdx.x;
-  if (t < NN) a[t] = U[(long long)e * NN + t];
+  constexpr int NN = ipow<NP, DIM>::v, EPG = PerssonTile<DIM, NP>::EPG;
+  __shared__ double a[EPG][NN], b[EPG][NN];
+  __shared__ double tot_s[EPG][NN], top_s[EPG][NN];
+  const int t = threadIdx.x, le = t / NN, n = t - (t / NN) * NN;
+  const int e = blockIdx.x * EPG + le;
+  const bool active = le < EPG && e < msh.E;
+  if (active) a[le][n] = U[(long long)e * NN + n];
   __syncthreads();
-  double* src = a;
-  double* dst = b;
+  double* src = active ? a[le] : a[0];
+  double* dst = active ? b[le] : b[0];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    sweep<DIM, NP>(sa.V, src, dst, d, t);
+    if (active) sweep<DIM, NP>(sa.V, src, dst, d, n);
     __syncthreads();
     double* x = src;
     src = dst;
     dst = x;
   }
-  double tot = 0.0, top = 0.0;
-  if (t < NN) {
-    const double c = src[t];
-    int r = t, kmax = 0;
+  if (active) {
+    const double c = src[n];
+    int r = n, kmax = 0;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       const int k = r % NP;
       r /= NP;
       kmax = k > kmax ? k : kmax;
     }
-    tot = c * c;
-    top = kmax == NP - 1 ? c * c : 0.0;
+    tot_s[le][n] = c * c;
+    top_s[le][n] = kmax == NP - 1 ? c * c : 0.0;
   }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    tot += __shfl_xor(tot, off);
-    top += __shfl_xor(top, off);
-  }
-  if ((t & 63) == 0) { red[0][t >> 6] = tot; red[1][t >> 6] = top; }
   __syncthreads();
-  if (t == 0) {
+  // one thread per element sums its modes in a fixed order
+  if (t < EPG && blockIdx.x * EPG + t < msh.E) {
     double T0 = 0.0, T1 = 0.0;
-    for (int w = 0; w < kSubThreads / 64; ++w) { T0 += red[0][w]; T1 += red[1][w]; }
+    for (int k = 0; k < NN; ++k) { T0 += tot_s[t][k]; T1 += top_s[t][k]; }
     const double ind = (T1 > 0.0 && T0 > 0.0) ? log10(T1 / T0) : -99.0;
-    sa.flags[e] = ind > sa.threshold ? 1 : 0;
+    sa.flags[blockIdx.x * EPG + t] = ind > sa.threshold ? 1 : 0;
   }
 }
 
@@ -206,6 +209,30 @@ __device__ __forceinline__ void sub_grad(const double* Ub, const MeshArgs& m, in
   }
 }
 
+template <int DIM, int NP>
+__global__ void __launch_bounds__(kSubThreads) grad_kernel(SubcellArgs sa, MeshArgs msh) {
+  constexpr int NN = Sub<DIM, NP>::NN;
+  const int e = blockIdx.x, t = threadIdx.x;
+  if (!sa.flags[e] || t >= NN) return;
+  double q[DIM][DIM + 1];
+  sub_grad<DIM, NP>(sa.Ub, msh, e, t, q);
+  const long long o = (long long)e * NN + t;
+#pragma unroll
+  for (int dd = 0; dd < DIM; ++dd)
+#pragma unroll
+    for (int j = 0; j <= DIM; ++j) sa.Gb[(long long)(dd * (DIM + 1) + j) * msh.S + o] = q[dd][j];
+}
+
+// the stored sub-cell gradient of a troubled element's sub-cell
+template <int DIM, int NP>
+__device__ __forceinline__ void load_grad(const double* Gb, long long S, int e, int k, double q[DIM][DIM + 1]) {
+  const long long o = (long long)e * Sub<DIM, NP>::NN + k;
+#pragma unroll
+  for (int dd = 0; dd < DIM; ++dd)
+#pragma unroll
+    for (int j = 0; j <= DIM; ++j) q[dd][j] = Gb[(long long)(dd * (DIM + 1) + j) * S + o];
+}
+
 __device__ __forceinline__ double minmod_d(double a, double b) {
   if (a * b <= 0.0) return 0.0;
   return fabs(a) < fabs(b) ? a : b;
@@ -235,8 +262,8 @@ __device__ __forceinline__ void rusanov(int d, const double* uL, const double* u
 // FV flux across the face between sub-cell a = (ea, ka) (left) and
 // b = (eb, kb) (right) in direction d
 template <int DIM, int NP>
-__device__ __forceinline__ void fv_face(const double* Ub, const MeshArgs& m, const PhysArgs& ph, int ea, int ka,
-                                        int eb, int kb, int d, double* F) {
+__device__ __forceinline__ void fv_face(const double* Ub, const double* Gb, const MeshArgs& m, const PhysArgs& ph,
+                                        int ea, int ka, int eb, int kb, int d, double* F) {
   constexpr int NV = DIM + 2;
   int eam, kam, ebp, kbp;
   sub_nb<DIM, NP>(m, ea, ka, d, -1, eam, kam);
@@ -263,8 +290,8 @@ __device__ __forceinline__ void fv_face(const double* Ub, const MeshArgs& m, con
   }
   rusanov<DIM>(d, uL, uR, ph, F);
   double ga[DIM][DIM + 1], gb[DIM][DIM + 1], q[DIM][DIM + 1];
-  sub_grad<DIM, NP>(Ub, m, ea, ka, ga);
-  sub_grad<DIM, NP>(Ub, m, eb, kb, gb);
+  load_grad<DIM, NP>(Gb, m.S, ea, ka, ga);
+  load_grad<DIM, NP>(Gb, m.S, eb, kb, gb);
   double div = 0.0;
 #pragma unroll
   for (int i = 0; i < DIM; ++i)
@@ -382,7 +409,7 @@ __global__ void __launch_bounds__(kSubThreads) fv_kernel(const double* __restric
           ka = k0 + (pos - 1) * sd;
           sub_nb<DIM, NP>(msh, e, ka, d, +1, eb, kb);
         }
-        fv_face<DIM, NP>(Ub, msh, ph, ea, ka, eb, kb, d, F);
+        fv_face<DIM, NP>(Ub, sa.Gb, msh, ph, ea, ka, eb, kb, d, F);
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) Ff[pos][line][v] = F[v];
@@ -402,7 +429,7 @@ __global__ void __launch_bounds__(kSubThreads) fv_kernel(const double* __restric
   if (t < NN) {
     const long long o = (long long)e * NN + t;
     double q[DIM][DIM + 1];
-    sub_grad<DIM, NP>(Ub, msh, e, t, q);
+    load_grad<DIM, NP>(sa.Gb, msh.S, e, t, q);
     const double rho = Ub[o], c = Ub[(DIM + 1) * msh.S + o];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) rs[1 + d][t] += ph.alpha * rho * q[d][DIM];
