@@ -34,7 +34,8 @@
  * the share of the orthonormal-Legendre modal energy in the modes whose
  * largest one-direction degree is N) exceeds subcell_threshold are treated
  * on (N+1)^dim equidistant sub-cells: sub-cell means by exact integration,
- * MinMod-limited reconstruction of (rho, v, c), Rusanov flux, viscous flux
+ * MinMod-limited reconstruction of (rho, v, c), the Rusanov or HLLC flux
+ * (flux 0 or 1), viscous flux
  * from the means of the adjacent central-difference sub-cell gradients, the
  * source at the sub-cell means; on faces shared with DG elements the
  * sub-face means of the DG face-flux polynomial (mass is conserved exactly);
@@ -104,8 +105,9 @@ typedef struct {
                      closure 0; alpha, beta and diss_c are not used          */
   int subcell;    /* 1: FV sub-cell shock capturing (Sec. 3.2) in elements
                      whose Persson-Peraire indicator exceeds
-                     subcell_threshold (model 0, flux 0, precision 0,
-                     closure 0 only)                                          */
+                     subcell_threshold (model 0, precision 0, closure 0
+                     only; the FV faces use the Rusanov or HLLC flux of
+                     the flux field)                                          */
   double subcell_threshold; /* log10 of the share of the modal energy of rho
                      in the highest modes above which an element is troubled */
 } nsk_params;
@@ -128,7 +130,7 @@ typedef struct {
  * non-increasing breakpoints, T outside (0,1), eps < 0, kappa < 0, model
  * outside 0..1, and for model 0 alpha <= 6 (1 - T), beta <= 0 or flux
  * outside 0..1; for model 1 flux != 2, precision != 0, closure != 0 or
- * subcell != 0; subcell = 1 with flux, precision or closure not 0, or a
+ * subcell != 0; subcell = 1 with precision or closure not 0, or a
  * non-finite threshold.
  * *out is set on success. */
 int nsk_create(const nsk_mesh* mesh, const nsk_params* params, nsk_ctx** out);
@@ -282,7 +284,7 @@ size_t nsk_implicit_workspace_bytes(const nsk_ctx* ctx, int gmres_m);
  * every Arnoldi step (the host needs the dot products).  Returns
  * NSK_ENOCONV, with the state left at the last completed step, when a stage
  * misses newton_tol after newton_max corrections; NSK_EUNSUPPORTED for mixed
- * precision or closure contexts; NSK_EINVAL for invalid options or precond 1
+ * precision, closure or sub-cell contexts; NSK_EINVAL for invalid options or precond 1
  * on a model 1 context.  stats_out (may be NULL) receives the counts. */
 int nsk_esdirk_step(nsk_ctx* ctx, void* d_iwork, double dt, int nsteps, const nsk_implicit_opts* opts,
                     nsk_implicit_stats* stats_out);

@@ -182,8 +182,7 @@ int check_params(const nsk_params* p) {
     if (p->flux != 2 || p->precision != 0 || p->closure != 0 || p->subcell != 0) return NSK_EINVAL;
     return NSK_OK;
   }
-  if (p->subcell == 1 &&
-      (p->flux != 0 || p->precision != 0 || p->closure != 0 || !std::isfinite(p->subcell_threshold)))
+  if (p->subcell == 1 && (p->precision != 0 || p->closure != 0 || !std::isfinite(p->subcell_threshold)))
     return NSK_EINVAL;
   if (p->model != 0) return NSK_EINVAL;
   if (!(p->alpha > 0.0) || !(p->beta > 0.0)) return NSK_EINVAL;

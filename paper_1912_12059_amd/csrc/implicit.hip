@@ -418,7 +418,8 @@ int nsk_esdirk_step(nsk_ctx* c, void* d_iwork, double dt, int nsteps, const nsk_
   if (rc) return rc;
   if ((reinterpret_cast<uintptr_t>(d_iwork) & 255) != 0) return NSK_EINVAL;
   // finite-difference Jacobian products need FP64 right-hand sides
-  if (c->par.precision != 0 || c->par.closure != 0) return NSK_EUNSUPPORTED;
+  // FV sub-cell right-hand sides switch elements and limit slopes: not differentiable
+  if (c->par.precision != 0 || c->par.closure != 0 || c->par.subcell != 0) return NSK_EUNSUPPORTED;
   if (opts->precond == 1 && c->par.model != 0) return NSK_EINVAL;  // the relaxation source is model II's
   if (!c->bound) return NSK_EUNBOUND;
   if (c->cur != 0) return NSK_EINVAL;

@@ -14,7 +14,8 @@
 //                   troubled elements (all the FV fluxes and sources use);
 //   (the DG right-hand-side kernel skips flagged elements)
 //   fv_kernel       troubled elements on (N+1)^dim sub-cells:
-//                   MinMod-limited reconstruction of (rho, v, c), Rusanov flux,
+//                   MinMod-limited reconstruction of (rho, v, c), Rusanov or
+//                   HLLC flux (as the DG faces),
 //                   viscous flux from face gradients (means of the two
 //                   adjacent central-difference sub-cell gradients); on a face
 //                   shared with a DG element, the sub-face means of the DG face
@@ -239,7 +240,7 @@ __device__ __forceinline__ double minmod_d(double a, double b) {
 }
 
 // Rusanov flux of model II between the point states uL, uR in direction d
-// (dissipation on c as diss_c says), as the DG face flux computes it
+// (dissipation on c as diss_c says), as the DG face flux computes it (flux = 0)
 template <int DIM>
 __device__ __forceinline__ void rusanov(int d, const double* uL, const double* uR, const PhysArgs& ph, double* Fc) {
   constexpr int NV = DIM + 2;
@@ -257,6 +258,55 @@ __device__ __forceinline__ void rusanov(int d, const double* uL, const double* u
     const double diss = (v == NV - 1 && !ph.diss_c) ? 0.0 : lam * (uR[v] - uL[v]);
     Fc[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * diss;
   }
+}
+
+// HLLC flux of the barotropic model II convective part between uL and uR
+// (flux = 1), the formula of the DG right-hand-side kernel: Davis speeds;
+// HLL flux for mass and normal momentum; tangential momenta carried by the
+// mass flux with the upwind tangential velocity of the contact
+// S* = F_hll[rho] / rho_hll; HLL dissipation alone on c (if diss_c)
+template <int DIM>
+__device__ __forceinline__ void hllc(int d, const double* uL, const double* uR, const PhysArgs& ph, double* Fc) {
+  constexpr int NV = DIM + 2;
+  double paL, paR, aL, aR;
+  p_alpha_sound<double>(uL[0], ph.T, ph.alpha, paL, aL);
+  p_alpha_sound<double>(uR[0], ph.T, ph.alpha, paR, aR);
+  const double irL = 1.0 / uL[0], irR = 1.0 / uR[0];
+  double FL[NV], FR[NV];
+  conv_flux<DIM, double>(d, uL, irL, paL, FL);
+  conv_flux<DIM, double>(d, uR, irR, paR, FR);
+  const double vnL = uL[1 + d] * irL, vnR = uR[1 + d] * irR;
+  const double SL = fmin(vnL - aL, vnR - aR), SR = fmax(vnL + aL, vnR + aR);
+  if (SL >= 0.0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fc[v] = FL[v];
+  } else if (SR <= 0.0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fc[v] = FR[v];
+  } else {
+    const double w = 1.0 / (SR - SL);
+    const double Fm = (SR * FL[0] - SL * FR[0] + SL * SR * (uR[0] - uL[0])) * w;
+    const double rh = (SR * uR[0] - SL * uL[0] - (FR[0] - FL[0])) * w;
+    const bool left = Fm / rh >= 0.0;
+    Fc[0] = Fm;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      if (j == d)
+        Fc[1 + j] = (SR * FL[1 + j] - SL * FR[1 + j] + SL * SR * (uR[1 + j] - uL[1 + j])) * w;
+      else
+        Fc[1 + j] = Fm * (left ? uL[1 + j] * irL : uR[1 + j] * irR);
+    }
+    Fc[NV - 1] = ph.diss_c ? SL * SR * (uR[NV - 1] - uL[NV - 1]) * w : 0.0;
+  }
+}
+
+template <int DIM>
+__device__ __forceinline__ void conv_numflux(int d, const double* uL, const double* uR, const PhysArgs& ph,
+                                             double* F) {
+  if (ph.flux == 1)
+    hllc<DIM>(d, uL, uR, ph, F);
+  else
+    rusanov<DIM>(d, uL, uR, ph, F);
 }
 
 // FV flux across the face between sub-cell a = (ea, ka) (left) and
@@ -288,7 +338,7 @@ __device__ __forceinline__ void fv_face(const double* Ub, const double* Gb, cons
     uL[NV - 1] = wL[NV - 1];
     uR[NV - 1] = wR[NV - 1];
   }
-  rusanov<DIM>(d, uL, uR, ph, F);
+  conv_numflux<DIM>(d, uL, uR, ph, F);
   double ga[DIM][DIM + 1], gb[DIM][DIM + 1], q[DIM][DIM + 1];
   load_grad<DIM, NP>(Gb, m.S, ea, ka, ga);
   load_grad<DIM, NP>(Gb, m.S, eb, kb, gb);
@@ -334,7 +384,7 @@ __device__ __forceinline__ void dg_face(const double* U, const double* G, const 
     vL[DIM] += bas.Lp[l] * G[(long long)(NT + d) * m.S + oL + node];
     vR[DIM] += bas.Lm[l] * G[(long long)(NT + d) * m.S + oR + node];
   }
-  rusanov<DIM>(d, uL, uR, ph, F);
+  conv_numflux<DIM>(d, uL, uR, ph, F);
 #pragma unroll
   for (int j = 0; j < DIM; ++j) F[1 + j] -= 0.5 * (vL[j] + vR[j]);
   F[NV - 1] -= 0.5 * ph.kb * (vL[DIM] + vR[DIM]);

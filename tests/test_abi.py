@@ -219,6 +219,11 @@ def test_implicit_host_side_checks():
         with pytest.raises(nsk.NskError) as e:
             nsk.nsk_esdirk_step(mixed, fake, 1e-3, 1, ok)
         assert e.value.code == nsk.NSK_EUNSUPPORTED
+        scx = nsk.nsk_create(m, nsk.make_params(subcell=1, subcell_threshold=-3.0))
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_esdirk_step(scx, fake, 1e-3, 1, ok)
+        assert e.value.code == nsk.NSK_EUNSUPPORTED
+        nsk.nsk_destroy(scx)
         with pytest.raises(nsk.NskError) as e:
             nsk.nsk_esdirk_step(orig, fake, 1e-3, 1, nsk.make_implicit_opts(precond=1))
         assert e.value.code == nsk.NSK_EINVAL
@@ -252,7 +257,7 @@ def test_subcell_host_side_checks():
     finally:
         nsk.nsk_destroy(plain)
         nsk.nsk_destroy(sc)
-    for bad in (dict(flux=1), dict(precision=1), dict(closure=1), dict(subcell=2),
+    for bad in (dict(flux=2), dict(precision=1), dict(closure=1), dict(subcell=2),
                 dict(subcell_threshold=float("nan")), dict(model=1, flux=2)):
         kw = dict(subcell=1, subcell_threshold=-3.0)
         kw.update(bad)

@@ -40,14 +40,6 @@ def _threshold(ind):
     return 0.5 * (v[i] + v[i + 1])
 
 
-def _pair(O, gpu, m, U, thr):
-    dim = m.dim
-    nel = tuple(m.nel) + (1,) * (3 - dim)
-    P = O.Problem(dim=dim, N=m.N, nel=nel, **KW)
-    s = gpu.Solver(dim=dim, N=m.N, nel=tuple(m.nel), subcell=1, subcell_threshold=thr, **KW)
-    return P, s
-
-
 def _scales(O, P, U):
     _, Mi = O.subcell_matrices(P.N)
     amp = np.abs(Mi).sum(axis=1).max() ** P.dim
@@ -55,15 +47,17 @@ def _scales(O, P, U):
     return term_scales(O, P.N, h, U, KW["alpha"]) * amp
 
 
+@pytest.mark.parametrize("flux", [0, 1])
 @pytest.mark.parametrize("dim,N,nel", [(1, 3, (24,)), (1, 5, (16,)), (2, 2, (12, 5)), (2, 4, (9, 4)),
                                        (3, 2, (8, 3, 2)), (3, 4, (6, 3, 3))])
-def test_subcell_flags_and_rhs_parity(O, gpu, dim, N, nel):
+def test_subcell_flags_and_rhs_parity(O, gpu, dim, N, nel, flux):
+    """Rusanov (flux 0) and HLLC (flux 1) on the DG and FV faces."""
     m, U = _interface_state(dim, N, nel, seed=3 + dim + N)
-    P = O.Problem(dim=dim, N=N, nel=tuple(nel) + (1,) * (3 - dim), **KW)
+    P = O.Problem(dim=dim, N=N, nel=tuple(nel) + (1,) * (3 - dim), flux=flux, **KW)
     thr = _threshold(O.persson(P, U))
     Rc, fc = O.rhs_subcell(P, U, thr)
     assert 0 < fc.sum() < P.nelem
-    P, s = _pair(O, gpu, m, U, thr)
+    s = gpu.Solver(dim=dim, N=N, nel=tuple(nel), subcell=1, subcell_threshold=thr, flux=flux, **KW)
     R = s.rhs(U).cpu().numpy()
     assert np.array_equal(s.subcell_flags(), fc)
     ulps = rhs_err_ulps(R, Rc, _scales(O, P, U))
