@@ -529,7 +529,7 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
   __shared__ R sOwn[EPB][NX][NN];           // own U and (tau_{.d}, dc/dx_d)
   __shared__ R sNb[EPB][2][NX][NN];         // the same for the two neighbours in direction d
   __shared__ double sRho64[R64E][3][R64N];  // FP64 densities (mixed precision only)
-  __shared__ R sF[EPB][NV][NN];             // total flux Fc_d - Fv_d
+  __shared__ R sF[2][EPB][NV][NN];          // total flux Fc_d - Fv_d (double-buffered by direction)
   __shared__ R sFs[EPB][2][NV][NF];         // numerical flux on the two d-faces
   __shared__ R sD[NP][NP];
   __shared__ R sLm[NP], sLp[NP], sIw[NP];
@@ -605,7 +605,12 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
   };
   if (PREFETCH && active) fetch_nb(std::integral_constant<int, 0>{});
 
-  static_for<DIM>([&](auto dc) {  // d-dependent index math is compile-time
+  // Per direction: stage (own viscous components, nodal flux, neighbours),
+  // faces (numerical fluxes), accumulate (volume and surface terms).  The
+  // accumulation of direction d and the staging of d+1 share a phase: the
+  // nodal flux alternates between two buffers, and everything else staging
+  // writes is read only by the face phase before it.
+  auto stage = [&](auto dc) {  // d-dependent index math is compile-time
     constexpr int d = decltype(dc)::value;
     if (active) {
       // own viscous components of direction d and the nodal total flux
@@ -618,7 +623,7 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
       for (int j = 0; j < DIM; ++j) F[1 + j] -= g[tau_index<DIM>(j, d)];
       if constexpr (MODEL == 0) F[DIM + 1] -= kb * g[NT + d];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) sF[el][v][n] = F[v];
+      for (int v = 0; v < NV; ++v) sF[d & 1][el][v][n] = F[v];
       // the two neighbours, coalesced
       if (!PREFETCH) fetch_nb(dc);
 #pragma unroll
@@ -629,7 +634,9 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
       }
       if constexpr (PREFETCH && d + 1 < DIM) fetch_nb(std::integral_constant<int, d + 1>{});
     }
-    __syncthreads();
+  };
+  auto faces = [&](auto dc) {
+    constexpr int d = decltype(dc)::value;
     if (tid < EPB * 2 * NF) {
       const int f = tid % NF;
       const int s = (tid / NF) & 1;
@@ -637,41 +644,37 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
       if (info.e[le] >= 0) {
         const int base = face_base<NP>(d, f);
         const int sd = dstride<NP>(d);
-        double ro64 = 0.0, rn64 = 0.0;   // density traces in FP64 (EoS guard)
-        R uo[NV], un[NV], vo[NVX], vn[NVX];
+        // left/right in direction d: on side + this element is the left
+        // state.  The left trace takes the weights of xi = +1, the right one
+        // those of xi = -1, so only the two source elements depend on s.
+        const R (*eL)[NN] = s ? sOwn[le] : sNb[le][s];
+        const R (*eR)[NN] = s ? sNb[le][s] : sOwn[le];
+        const int qL = s ? 0 : 1, qR = s ? 2 : 0;  // FP64 density slots (mixed precision)
+        double rL = 0.0, rR = 0.0;  // density traces in FP64 (EoS guard)
+        R uL[NV], uR[NV], vL[NVX], vR[NVX];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) { uo[v] = R(0); un[v] = R(0); }
+        for (int v = 0; v < NV; ++v) { uL[v] = R(0); uR[v] = R(0); }
 #pragma unroll
-        for (int k = 0; k < NVX; ++k) { vo[k] = R(0); vn[k] = R(0); }
+        for (int k = 0; k < NVX; ++k) { vL[k] = R(0); vR[k] = R(0); }
 #pragma unroll
         for (int l = 0; l < NP; ++l) {
           const int node = base + l * sd;
-          const R Lo = s ? sLp[l] : sLm[l];   // own trace on side s
-          const R Ln = s ? sLm[l] : sLp[l];   // neighbour trace on the opposite side
-          const double Lo64 = s ? bas.Lp[l] : bas.Lm[l];
-          const double Ln64 = s ? bas.Lm[l] : bas.Lp[l];
-          const double ro = MIXED ? sRho64[MIXED ? le : 0][0][MIXED ? node : 0] : double(sOwn[le][0][node]);
-          const double rn = MIXED ? sRho64[MIXED ? le : 0][1 + s][MIXED ? node : 0] : double(sNb[le][s][0][node]);
-          ro64 += Lo64 * ro;
-          rn64 += Ln64 * rn;
+          const R Lp = sLp[l], Lm = sLm[l];
+          const double xl = MIXED ? sRho64[MIXED ? le : 0][MIXED ? qL : 0][MIXED ? node : 0] : double(eL[0][node]);
+          const double xr = MIXED ? sRho64[MIXED ? le : 0][MIXED ? qR : 0][MIXED ? node : 0] : double(eR[0][node]);
+          rL += bas.Lp[l] * xl;
+          rR += bas.Lm[l] * xr;
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
-            uo[v] += Lo * sOwn[le][v][node];
-            un[v] += Ln * sNb[le][s][v][node];
+            uL[v] += Lp * eL[v][node];
+            uR[v] += Lm * eR[v][node];
           }
 #pragma unroll
           for (int k = 0; k < NVX; ++k) {
-            vo[k] += Lo * sOwn[le][NV + k][node];
-            vn[k] += Ln * sNb[le][s][NV + k][node];
+            vL[k] += Lp * eL[NV + k][node];
+            vR[k] += Lm * eR[NV + k][node];
           }
         }
-        // left/right in direction d: on side + this element is the left state
-        R uL[NV], uR[NV], vL[NVX], vR[NVX];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) { uL[v] = s ? uo[v] : un[v]; uR[v] = s ? un[v] : uo[v]; }
-#pragma unroll
-        for (int k = 0; k < NVX; ++k) { vL[k] = s ? vo[k] : vn[k]; vR[k] = s ? vn[k] : vo[k]; }
-        const double rL = s ? ro64 : rn64, rR = s ? rn64 : ro64;
         R paL, paR, aL = R(0), aR = R(0);
         if constexpr (FLUX == 2) {
           // the global Lax-Friedrichs flux needs no local sound speed
@@ -739,7 +742,9 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
         }
       }
     }
-    __syncthreads();
+  };
+  auto accum = [&](auto dc) {
+    constexpr int d = decltype(dc)::value;
     if (active) {
       const int sd = dstride<NP>(d);
       const int i = (n / sd) % NP;
@@ -753,11 +758,22 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
       for (int v = 0; v < NV; ++v) {
         R vol = R(0);
 #pragma unroll
-        for (int l = 0; l < NP; ++l) vol += Drow[l] * sF[el][v][n + (l - i) * sd];
+        for (int l = 0; l < NP; ++l) vol += Drow[l] * sF[d & 1][el][v][n + (l - i) * sd];
         acc[v] += h2 * (vol - (lp * sFs[el][1][v][f] - lm * sFs[el][0][v][f]));
       }
     }
-    __syncthreads();  // LDS reused by the next direction
+  };
+  stage(std::integral_constant<int, 0>{});
+  __syncthreads();
+  static_for<DIM>([&](auto dc) {
+    constexpr int d = decltype(dc)::value;
+    faces(dc);
+    __syncthreads();
+    accum(dc);
+    if constexpr (d + 1 < DIM) {
+      stage(std::integral_constant<int, d + 1>{});
+      __syncthreads();
+    }
   });
 
   // source (FP64) and update
