@@ -122,14 +122,17 @@ int launch_stage_subcell(nsk_ctx* c, const double* Uin, double* Uout, double* dU
   if (ev) (void)hipEventRecord(ev[2], c->stream);
   StageArgs sta = st;
   sta.skip = sa.flags;
-  if (c->par.flux == 1)
+  if (c->par.flux == 1) {
     hipLaunchKernelGGL((rhs_kernel<DIM, NP, EPB, double, double, 1>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream,
                        Uin, G, Uout, dU, b, m, p, sta);
-  else
+    hipLaunchKernelGGL((fv_kernel<DIM, NP, 1>), dim3(E), dim3(kSubThreads), 0, c->stream, Uin, G, Uout, dU, b, m, p,
+                       sta, sa);
+  } else {
     hipLaunchKernelGGL((rhs_kernel<DIM, NP, EPB, double, double, 0>), dim3(blocks), dim3(Tl::THREADS), 0, c->stream,
                        Uin, G, Uout, dU, b, m, p, sta);
-  hipLaunchKernelGGL((fv_kernel<DIM, NP>), dim3(E), dim3(kSubThreads), 0, c->stream, Uin, G, Uout, dU, b, m, p, sta,
-                     sa);
+    hipLaunchKernelGGL((fv_kernel<DIM, NP, 0>), dim3(E), dim3(kSubThreads), 0, c->stream, Uin, G, Uout, dU, b, m, p,
+                       sta, sa);
+  }
   if (ev) (void)hipEventRecord(ev[3], c->stream);
   return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
 }

@@ -300,10 +300,12 @@ __device__ __forceinline__ void hllc(int d, const double* uL, const double* uR, 
   }
 }
 
-template <int DIM>
+// the numerical flux is a compile-time choice, so that a kernel holds only
+// the registers of the one it uses
+template <int DIM, int FLUX>
 __device__ __forceinline__ void conv_numflux(int d, const double* uL, const double* uR, const PhysArgs& ph,
                                              double* F) {
-  if (ph.flux == 1)
+  if constexpr (FLUX == 1)
     hllc<DIM>(d, uL, uR, ph, F);
   else
     rusanov<DIM>(d, uL, uR, ph, F);
@@ -311,7 +313,7 @@ __device__ __forceinline__ void conv_numflux(int d, const double* uL, const doub
 
 // FV flux across the face between sub-cell a = (ea, ka) (left) and
 // b = (eb, kb) (right) in direction d
-template <int DIM, int NP>
+template <int DIM, int NP, int FLUX>
 __device__ __forceinline__ void fv_face(const double* Ub, const double* Gb, const MeshArgs& m, const PhysArgs& ph,
                                         int ea, int ka, int eb, int kb, int d, double* F) {
   constexpr int NV = DIM + 2;
@@ -338,7 +340,7 @@ __device__ __forceinline__ void fv_face(const double* Ub, const double* Gb, cons
     uL[NV - 1] = wL[NV - 1];
     uR[NV - 1] = wR[NV - 1];
   }
-  conv_numflux<DIM>(d, uL, uR, ph, F);
+  conv_numflux<DIM, FLUX>(d, uL, uR, ph, F);
   double ga[DIM][DIM + 1], gb[DIM][DIM + 1], q[DIM][DIM + 1];
   load_grad<DIM, NP>(Gb, m.S, ea, ka, ga);
   load_grad<DIM, NP>(Gb, m.S, eb, kb, gb);
@@ -357,7 +359,7 @@ __device__ __forceinline__ void fv_face(const double* Ub, const double* Gb, cons
 // DG face flux at Gauss point f of the face between eL (left) and eR
 // (right) in direction d: Rusanov of the traces minus the mean of the traced
 // viscous fluxes, from the same operands as the DG right-hand-side kernel
-template <int DIM, int NP>
+template <int DIM, int NP, int FLUX>
 __device__ __forceinline__ void dg_face(const double* U, const double* G, const BasisArgs& bas, const MeshArgs& m,
                                         const PhysArgs& ph, int eL, int eR, int d, int f, double* F) {
   constexpr int NN = Sub<DIM, NP>::NN, NV = DIM + 2, NT = Shape<DIM, NP>::NTAU;
@@ -384,13 +386,13 @@ __device__ __forceinline__ void dg_face(const double* U, const double* G, const 
     vL[DIM] += bas.Lp[l] * G[(long long)(NT + d) * m.S + oL + node];
     vR[DIM] += bas.Lm[l] * G[(long long)(NT + d) * m.S + oR + node];
   }
-  conv_numflux<DIM>(d, uL, uR, ph, F);
+  conv_numflux<DIM, FLUX>(d, uL, uR, ph, F);
 #pragma unroll
   for (int j = 0; j < DIM; ++j) F[1 + j] -= 0.5 * (vL[j] + vR[j]);
   F[NV - 1] -= 0.5 * ph.kb * (vL[DIM] + vR[DIM]);
 }
 
-template <int DIM, int NP>
+template <int DIM, int NP, int FLUX>
 __global__ void __launch_bounds__(kSubThreads) fv_kernel(const double* __restrict__ U, const double* __restrict__ G,
                                                          double* __restrict__ Uout, double* __restrict__ dU,
                                                          BasisArgs bas, MeshArgs msh, PhysArgs ph, StageArgs st,
@@ -417,8 +419,8 @@ __global__ void __launch_bounds__(kSubThreads) fv_kernel(const double* __restric
       const int s = i / NF, f = i % NF;
       if (!trn[s]) {
         double F[NV];
-        if (s == 0) dg_face<DIM, NP>(U, G, bas, msh, ph, en[0], e, d, f, F);
-        else dg_face<DIM, NP>(U, G, bas, msh, ph, e, en[1], d, f, F);
+        if (s == 0) dg_face<DIM, NP, FLUX>(U, G, bas, msh, ph, en[0], e, d, f, F);
+        else dg_face<DIM, NP, FLUX>(U, G, bas, msh, ph, e, en[1], d, f, F);
 #pragma unroll
         for (int v = 0; v < NV; ++v) Fg[s][f][v] = F[v];
       }
@@ -459,7 +461,7 @@ __global__ void __launch_bounds__(kSubThreads) fv_kernel(const double* __restric
           ka = k0 + (pos - 1) * sd;
           sub_nb<DIM, NP>(msh, e, ka, d, +1, eb, kb);
         }
-        fv_face<DIM, NP>(Ub, sa.Gb, msh, ph, ea, ka, eb, kb, d, F);
+        fv_face<DIM, NP, FLUX>(Ub, sa.Gb, msh, ph, ea, ka, eb, kb, d, F);
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) Ff[pos][line][v] = F[v];
