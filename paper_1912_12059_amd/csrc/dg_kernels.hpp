@@ -328,7 +328,10 @@ __device__ __forceinline__ void lift_block(int L, int tid, const double* __restr
   };
   if (active) fetch_nb(std::integral_constant<int, 0>{});
 
-  static_for<DIM>([&](auto dc) {  // d-dependent index math is compile-time
+  // Per direction: stage the neighbours' primitives, then the central face
+  // values.  (Double-buffering the neighbours so that the face values of d
+  // share a phase with the staging of d+1 costs occupancy and was slower.)
+  auto stage = [&](auto dc) {
     constexpr int d = decltype(dc)::value;
     if (active) {
 #pragma unroll
@@ -340,7 +343,9 @@ __device__ __forceinline__ void lift_block(int L, int tid, const double* __restr
       }
       if constexpr (d + 1 < DIM) fetch_nb(std::integral_constant<int, d + 1>{});
     }
-    __syncthreads();
+  };
+  auto faces = [&](auto dc) {
+    constexpr int d = decltype(dc)::value;
     if (tid < EPB * 2 * NF) {
       const int f = tid % NF;
       const int s = (tid / NF) & 1;
@@ -348,30 +353,38 @@ __device__ __forceinline__ void lift_block(int L, int tid, const double* __restr
       if (info.e[le] >= 0) {
         const int base = face_base<NP>(d, f);
         const int sd = dstride<NP>(d);
-        R own[NL], oth[NL];
+        // on side + the element is the left state: the left trace takes the
+        // weights of xi = +1, the right one those of xi = -1
+        const R (*eL)[NN] = s ? sW[le] : sNbW[le][s];
+        const R (*eR)[NN] = s ? sNbW[le][s] : sW[le];
+        R wl[NL], wr[NL];
 #pragma unroll
-        for (int k = 0; k < NL; ++k) { own[k] = R(0); oth[k] = R(0); }
+        for (int k = 0; k < NL; ++k) { wl[k] = R(0); wr[k] = R(0); }
 #pragma unroll
         for (int l = 0; l < NP; ++l) {
-          const R Lo = s ? sLp[l] : sLm[l];   // own trace on side s
-          const R Ln = s ? sLm[l] : sLp[l];   // neighbour trace on the opposite side
+          const R Lp = sLp[l], Lm = sLm[l];
           const int node = base + l * sd;
 #pragma unroll
           for (int k = 0; k < NL; ++k) {
-            own[k] += Lo * sW[le][k][node];
-            oth[k] += Ln * sNbW[le][s][k][node];
+            wl[k] += Lp * eL[k][node];
+            wr[k] += Lm * eR[k][node];
           }
         }
 #pragma unroll
-        for (int k = 0; k < NL; ++k) {
-          // left state first: on side + the element is left, on side - it is right
-          const R wl = s ? own[k] : oth[k];
-          const R wr = s ? oth[k] : own[k];
-          sWs[le][d][s][k][f] = R(0.5) * (wl + wr);
-        }
+        for (int k = 0; k < NL; ++k) sWs[le][d][s][k][f] = R(0.5) * (wl[k] + wr[k]);
       }
     }
+  };
+  stage(std::integral_constant<int, 0>{});
+  __syncthreads();
+  static_for<DIM>([&](auto dc) {  // d-dependent index math is compile-time
+    constexpr int d = decltype(dc)::value;
+    faces(dc);
     __syncthreads();
+    if constexpr (d + 1 < DIM) {
+      stage(std::integral_constant<int, d + 1>{});
+      __syncthreads();
+    }
   });
 
   if (active) {
