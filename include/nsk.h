@@ -205,7 +205,8 @@ int nsk_set_tile(nsk_ctx* ctx, int variant, int order);
  * pair with HIP events, keeps the fastest in the context and returns it;
  * ms_out (12 doubles, may be NULL) receives the mean ms per evaluation at
  * index variant * 6 + order (-1 for pairs skipped because they coincide with
- * another, e.g. tiled orders in 1D).  Uses the workspace's second state
+ * another: tiled orders in 1D, and variant 1 where both variants put the same
+ * number of elements in a workgroup; variant 0 is then returned).  Uses the workspace's second state
  * buffer as scratch, so it must be called between steps, and waits for the
  * stream. */
 int nsk_autotune(nsk_ctx* ctx, int reps, int* variant_out, int* order_out, double* ms_out);

@@ -271,6 +271,24 @@ int run_diag(nsk_ctx* c, double* h) {
   return NSK_OK;
 }
 
+// whether the two tile variants launch the same elements per workgroup
+template <int DIM, int NP>
+constexpr bool same_variants() { return Epb<DIM, NP>::V0 == Epb<DIM, NP>::V1; }
+template <int DIM>
+bool variants_coincide_dim(int N) {
+  switch (N) {
+    case 1: return same_variants<DIM, 2>();
+    case 2: return same_variants<DIM, 3>();
+    case 3: return same_variants<DIM, 4>();
+    case 4: return same_variants<DIM, 5>();
+    case 5: return same_variants<DIM, 6>();
+    default: return same_variants<DIM, 7>();
+  }
+}
+bool variants_coincide(int dim, int N) {
+  return dim == 1 ? variants_coincide_dim<1>(N) : dim == 2 ? variants_coincide_dim<2>(N) : variants_coincide_dim<3>(N);
+}
+
 }  // namespace
 
 extern "C" {
@@ -616,6 +634,7 @@ int nsk_autotune(nsk_ctx* c, int reps, int* variant_out, int* order_out, double*
     if (ms_out) ms_out[k] = -1.0;
     // orders that coincide for this mesh (1D, or the same tiles) are skipped
     if (o >= 2 && c->dim == 1) continue;
+    if (v == 1 && variants_coincide(c->dim, c->N)) continue;
     rc = nsk_set_tile(c, v, o);
     if (rc) break;
     // right-hand side of the bound state written into the scratch state buffer
