@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/nsk.h"
@@ -37,71 +38,93 @@ struct LinArgs {
   int nk;
 };
 
-// y[i] = sum_k a_k x_k[i] (y may be one of the x_k: each entry is read before
-// it is written by the same thread)
-__global__ void __launch_bounds__(kVecThreads) lincomb_kernel(LinArgs L, double* __restrict__ y, long long n) {
+// Calls f(std::integral_constant<int, K>{}) for the runtime count k in
+// [0, kLinTerms]: the vector kernels take their vector count as a template
+// parameter, so that all of an entry's loads issue together instead of one
+// branch and wait per vector.
+template <typename F>
+void with_count(int k, F&& f) {
+  switch (k) {
+    case 0: f(std::integral_constant<int, 0>{}); break;
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    case 7: f(std::integral_constant<int, 7>{}); break;
+    default: f(std::integral_constant<int, 8>{}); break;
+  }
+}
+static_assert(kLinTerms == 8, "with_count covers counts up to 8");
+
+// y[i] = sum_{k < NK} a_k x_k[i] (y may be one of the x_k: each entry is read
+// before it is written by the same thread)
+template <int NK>
+__global__ void __launch_bounds__(kVecThreads) lincomb_kernel(LinArgs L, double* y, long long n) {
   const long long stride = (long long)gridDim.x * kVecThreads;
   for (long long i = (long long)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride) {
     double s = 0.0;
-    for (int k = 0; k < L.nk; ++k) s += L.a[k] * L.x[k][i];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) s += L.a[k] * L.x[k][i];
     y[i] = s;
   }
 }
 
 // part[b * ld + j] = sum over block b's contiguous chunk of w[i] * v_j[i],
-// v_j = V + j * vstride, for j < nj <= kLinTerms; with self, also
-// part[b * ld + nj] = the chunk's sum of w[i]^2.  V is the Krylov basis
+// v_j = V + j * vstride, for j < NJ <= kLinTerms; with self, also
+// part[b * ld + NJ] = the chunk's sum of w[i]^2.  V is the Krylov basis
 // (FP64 or FP32); products and sums are FP64.
-template <typename VT>
+template <typename VT, int NJ>
 __global__ void __launch_bounds__(kVecThreads) multidot_kernel(const double* __restrict__ w,
-                                                               const VT* __restrict__ V, long long vstride, int nj,
+                                                               const VT* __restrict__ V, long long vstride,
                                                                int self, long long n, double* __restrict__ part,
                                                                int ld) {
-  __shared__ double red[kLinTerms + 1][kVecThreads / 64];
+  __shared__ double red[NJ + 1][kVecThreads / 64];
   const long long chunk = (n + gridDim.x - 1) / gridDim.x;
   const long long beg = (long long)blockIdx.x * chunk;
   const long long end = beg + chunk < n ? beg + chunk : n;
-  double s[kLinTerms + 1];
+  double s[NJ + 1];
 #pragma unroll
-  for (int j = 0; j <= kLinTerms; ++j) s[j] = 0.0;
+  for (int j = 0; j <= NJ; ++j) s[j] = 0.0;
   for (long long i = beg + threadIdx.x; i < end; i += kVecThreads) {
     const double wi = w[i];
 #pragma unroll
-    for (int j = 0; j < kLinTerms; ++j)
-      if (j < nj) s[j] += wi * double(V[j * vstride + i]);
-    s[kLinTerms] += wi * wi;
+    for (int j = 0; j < NJ; ++j) s[j] += wi * double(V[j * vstride + i]);
+    s[NJ] += wi * wi;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int j = 0; j <= kLinTerms; ++j) {
+  for (int j = 0; j <= NJ; ++j) {
     double v = s[j];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     if (lane == 0) red[j][wv] = v;
   }
   __syncthreads();
-  const int outs = nj + (self ? 1 : 0);
+  const int outs = NJ + (self ? 1 : 0);
   if (threadIdx.x < outs) {
-    const int j = threadIdx.x < nj ? threadIdx.x : kLinTerms;
+    const int j = threadIdx.x;
     double t = 0.0;
     for (int k = 0; k < kVecThreads / 64; ++k) t += red[j][k];
     part[(long long)blockIdx.x * ld + threadIdx.x] = t;
   }
 }
 
-// y[i] = aw w[i] + sum_{j < nk} a_j v_j[i], v_j = V + j * vstride (nk <=
+// y[i] = aw w[i] + sum_{j < NK} a_j v_j[i], v_j = V + j * vstride (NK <=
 // kLinTerms; w may be null; y may be w)
 struct BasisCoefs {
   double a[kLinTerms];
 };
-template <typename VT, typename OT>
+template <typename VT, typename OT, int NK>
 __global__ void __launch_bounds__(kVecThreads) basis_comb_kernel(const double* w, double aw,
                                                                  const VT* __restrict__ V, long long vstride,
-                                                                 BasisCoefs c, int nk, OT* y, long long n) {
+                                                                 BasisCoefs c, OT* y, long long n) {
   const long long stride = (long long)gridDim.x * kVecThreads;
   for (long long i = (long long)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride) {
     double t = w ? aw * w[i] : 0.0;
-    for (int j = 0; j < nk; ++j) t += c.a[j] * double(V[j * vstride + i]);
+#pragma unroll
+    for (int j = 0; j < NK; ++j) t += c.a[j] * double(V[j * vstride + i]);
     y[i] = OT(t);
   }
 }
@@ -135,8 +158,9 @@ struct Precond {
 
 template <typename VT>
 __device__ __forceinline__ double pinv(const VT* __restrict__ v, long long i, const Precond& p) {
-  if (p.on && i / p.S == p.ci) {
-    const long long o = i - (long long)p.ci * p.S;
+  const long long c0 = (long long)p.ci * p.S;  // first entry of the c variable
+  if (p.on && i >= c0 && i - c0 < p.S) {
+    const long long o = i - c0;
     return (double(v[i]) + p.a * double(v[o])) / (1.0 + p.a);
   }
   return double(v[i]);
@@ -227,7 +251,9 @@ struct Solver {
       if (!first) { L.x[t] = y; L.a[t] = 1.0; ++t; }
       while (t < kLinTerms && k0 < nk) { L.x[t] = x[k0]; L.a[t] = a[k0]; ++t; ++k0; }
       L.nk = t;
-      hipLaunchKernelGGL(lincomb_kernel, dim3(grid()), dim3(kVecThreads), 0, st, L, y, M);
+      with_count(t, [&](auto K) {
+        hipLaunchKernelGGL(lincomb_kernel<decltype(K)::value>, dim3(grid()), dim3(kVecThreads), 0, st, L, y, M);
+      });
       first = false;
     }
     return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
@@ -240,8 +266,10 @@ struct Solver {
     do {
       const int nn = nj - j0 < kLinTerms ? nj - j0 : kLinTerms;
       const bool last = j0 + nn >= nj;
-      hipLaunchKernelGGL(multidot_kernel<VT>, dim3(kDotBlocks), dim3(kVecThreads), 0, st, w, V<VT>(j0), vstride, nn,
-                         last ? 1 : 0, M, part + j0, m + 3);
+      with_count(nn, [&](auto K) {
+        hipLaunchKernelGGL((multidot_kernel<VT, decltype(K)::value>), dim3(kDotBlocks), dim3(kVecThreads), 0, st, w,
+                           V<VT>(j0), vstride, last ? 1 : 0, M, part + j0, m + 3);
+      });
       j0 += nn;
     } while (j0 < nj);
     return fetch_dots(nj + 1, h);
@@ -255,7 +283,7 @@ struct Solver {
   }
 
   int norm(const double* w, double* out) {
-    hipLaunchKernelGGL(multidot_kernel<double>, dim3(kDotBlocks), dim3(kVecThreads), 0, st, w, w, 0LL, 0, 1, M,
+    hipLaunchKernelGGL((multidot_kernel<double, 0>), dim3(kDotBlocks), dim3(kVecThreads), 0, st, w, w, 0LL, 1, M,
                        part, m + 3);
     int rc = fetch_dots(1, out);
     *out = std::sqrt(*out);
@@ -273,8 +301,8 @@ struct Solver {
     while (nk - j0 > kLinTerms) {
       BasisCoefs cf;
       for (int j = 0; j < kLinTerms; ++j) cf.a[j] = a[j0 + j];
-      hipLaunchKernelGGL((basis_comb_kernel<VT, double>), dim3(grid()), dim3(kVecThreads), 0, st, src, asrc,
-                         V<VT>(j0), vstride, cf, kLinTerms, acc, M);
+      hipLaunchKernelGGL((basis_comb_kernel<VT, double, kLinTerms>), dim3(grid()), dim3(kVecThreads), 0, st, src,
+                         asrc, V<VT>(j0), vstride, cf, acc, M);
       src = acc;
       asrc = 1.0;
       j0 += kLinTerms;
@@ -282,8 +310,10 @@ struct Solver {
     BasisCoefs cf;
     std::memset(&cf, 0, sizeof(cf));
     for (int j = j0; j < nk; ++j) cf.a[j - j0] = a[j];
-    hipLaunchKernelGGL((basis_comb_kernel<VT, OT>), dim3(grid()), dim3(kVecThreads), 0, st, src, asrc, V<VT>(j0),
-                       vstride, cf, nk - j0, y, M);
+    with_count(nk - j0, [&](auto K) {
+      hipLaunchKernelGGL((basis_comb_kernel<VT, OT, decltype(K)::value>), dim3(grid()), dim3(kVecThreads), 0, st, src,
+                         asrc, V<VT>(j0), vstride, cf, y, M);
+    });
     return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
   }
 
