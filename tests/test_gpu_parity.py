@@ -226,6 +226,26 @@ def test_autotune_keeps_results(gpu):
     s.close()
 
 
+def test_autotune_skips_coinciding_variant(gpu):
+    """At N = 4 in 3D both tile variants hold one element per workgroup (a
+    125-node element's LDS does not fit twice in the 40 KB budget), so the
+    tuner times variant 0 only, reports -1 for variant 1 and returns 0; with
+    N = 2 (27 nodes) the variants differ and all six tiled orders of both
+    are timed."""
+    m, U = I.smooth_random(3, 4, (6, 5, 4), seed=9)
+    s = _solver(gpu, m, **PHYS)
+    s.set_state(U)
+    variant, order, ms = gpu.nsk_autotune(s.ctx, 1)
+    assert variant == 0 and all(x == -1 for x in ms[6:]) and all(x > 0 for x in ms[:6])
+    s.close()
+    m, U = I.smooth_random(3, 2, (6, 5, 4), seed=9)
+    s = _solver(gpu, m, **PHYS)
+    s.set_state(U)
+    variant, order, ms = gpu.nsk_autotune(s.ctx, 1)
+    assert all(x > 0 for x in ms)
+    s.close()
+
+
 def test_full_size_3d_sampled(O, gpu):
     """The 96x48x48, N=4 collision (27.6M nodes) on the GPU in the launch
     configuration the benchmark times; sampled elements are recomputed by the
