@@ -6,7 +6,8 @@ threshold, so the tests set the threshold in the widest gap between the
 oracle's indicator values: both sides then flag the same elements.  Right-
 hand sides are compared at the bar of tests/tolerances.py, widened by the
 largest row sum of the inverse sub-cell averaging (the troubled elements'
-rates pass through it once per direction)."""
+rates pass through it once per direction), with the relaxation source in the
+scale of c (it acts on rounded sub-cell means)."""
 import numpy as np
 import pytest
 
@@ -41,10 +42,17 @@ def _threshold(ind):
 
 
 def _scales(O, P, U):
+    """The DG round-off scales, plus for c the relaxation source: on sub-cells
+    (alpha/beta)(rho - c) is evaluated on sub-cell means, whose own rounding
+    (an ulp of |rho| and |c|) it multiplies by alpha/beta, so that where rho
+    and c nearly cancel an ulp of a mean is many ulps of the rate; all of it
+    then passes through the inverse averaging."""
     _, Mi = O.subcell_matrices(P.N)
     amp = np.abs(Mi).sum(axis=1).max() ** P.dim
     h = min(float(np.diff(P.breaks(d)).min()) for d in range(P.dim))
-    return term_scales(O, P.N, h, U, KW["alpha"]) * amp
+    sc = term_scales(O, P.N, h, U, KW["alpha"])
+    sc[-1] += KW["alpha"] / KW["beta"] * float(np.abs(U[[0, -1]]).max())
+    return sc * amp
 
 
 @pytest.mark.parametrize("flux", [0, 1])
@@ -63,6 +71,29 @@ def test_subcell_flags_and_rhs_parity(O, gpu, dim, N, nel, flux):
     ulps = rhs_err_ulps(R, Rc, _scales(O, P, U))
     assert ulps <= RHS_ULPS, f"{ulps:.1f} ulps"
     s.close()
+
+
+@pytest.mark.parametrize("flux", [0, 1])
+@pytest.mark.parametrize("dim,N,nel", [(1, 3, (1,)), (2, 3, (1, 4)), (3, 2, (2, 1, 3)), (3, 3, (1, 1, 1))])
+def test_subcell_degenerate_grids_parity(O, gpu, dim, N, nel, flux):
+    """Periodic grids with one element in a direction (the element is its own
+    neighbour there, and sub-cell stencils wrap onto it): every element on
+    sub-cells, and where the indicator separates the elements also a mixed
+    DG/FV grid."""
+    m, U = _interface_state(dim, N, nel, seed=30 + dim)
+    P = O.Problem(dim=dim, N=N, nel=tuple(nel) + (1,) * (3 - dim), flux=flux, **KW)
+    ind = O.persson(P, U)
+    thrs = [-1e9]
+    if np.ptp(ind) > 0.5:
+        thrs.append(_threshold(ind))
+    for thr in thrs:
+        Rc, fc = O.rhs_subcell(P, U, thr)
+        s = gpu.Solver(dim=dim, N=N, nel=tuple(nel), subcell=1, subcell_threshold=thr, flux=flux, **KW)
+        R = s.rhs(U).cpu().numpy()
+        assert np.array_equal(s.subcell_flags(), fc)
+        ulps = rhs_err_ulps(R, Rc, _scales(O, P, U))
+        assert ulps <= RHS_ULPS, f"threshold {thr}: {ulps:.1f} ulps"
+        s.close()
 
 
 def test_subcell_trajectory_shock_tube(O, gpu):
