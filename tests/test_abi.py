@@ -268,3 +268,7 @@ def test_subcell_host_side_checks():
     with pytest.raises(nsk.NskError) as e:
         nsk.nsk_batch_create([bm], nsk.make_params(subcell=1, subcell_threshold=-3.0))
     assert e.value.code == nsk.NSK_EUNSUPPORTED
+    # the batch kernels are instantiated for the Rusanov flux only
+    with pytest.raises(nsk.NskError) as e:
+        nsk.nsk_batch_create([bm], nsk.make_params(flux=1))
+    assert e.value.code == nsk.NSK_EUNSUPPORTED
