@@ -71,6 +71,24 @@ def test_esdirk_parity_model2_stiff_1d(O, gpu, precond, basis_fp32, reorth_tol):
     s.close()
 
 
+def test_esdirk_parity_model2_hllc_1d(O, gpu):
+    """Model II with the HLLC flux, 1D, 10 elements, N = 2, both phases:
+    3 steps of 20 times the explicit step (the flux's branches are the same
+    on both sides; the finite-difference Jacobian-vector products see the
+    branch of the state they perturb)."""
+    m, U = I.smooth_random(1, 2, (10,), seed=9)
+    kw = dict(eps=1e-2, kappa=1e-4, alpha=500.0, beta=1e-2)
+    P = _problem(O, m, flux=1, **kw)
+    dt = 20 * O.dt(P, U, 0.5)
+    ref = E.run(P, U, dt, 3)
+    s = _solver(gpu, m, flux=1, **kw)
+    s.set_state(U)
+    st = s.esdirk_step(dt, 3, **TIGHT)
+    assert st["converged"] == 1
+    assert _relerr(s.get_state().cpu().numpy(), ref) <= TOL
+    s.close()
+
+
 @pytest.mark.parametrize("dim,N,nel", [(2, 2, (4, 3)), (3, 1, (2, 2, 2))])
 def test_esdirk_parity_model2_multid(O, gpu, dim, N, nel):
     """Model II in 2D and 3D across both phases, 2 steps of 20 times the
