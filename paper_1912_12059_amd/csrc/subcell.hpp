@@ -114,10 +114,22 @@ __global__ void __launch_bounds__(kSubThreads) persson_kernel(const double* __re
     top_s[le][n] = kmax == NP - 1 ? c * c : 0.0;
   }
   __syncthreads();
-  // one thread per element sums its modes in a fixed order
+  // Modal energy sums in a fixed two-level order: NN / NP threads per
+  // element sum the NP modes along the slowest index (each thread reads only
+  // its own column, and writes its first entry), then one thread per element
+  // sums those partial sums.
+  constexpr int NC = NN / NP;
+  if (active && n < NC) {
+    double T0 = 0.0, T1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) { T0 += tot_s[le][n + k * NC]; T1 += top_s[le][n + k * NC]; }
+    tot_s[le][n] = T0;
+    top_s[le][n] = T1;
+  }
+  __syncthreads();
   if (t < EPG && blockIdx.x * EPG + t < msh.E) {
     double T0 = 0.0, T1 = 0.0;
-    for (int k = 0; k < NN; ++k) { T0 += tot_s[t][k]; T1 += top_s[t][k]; }
+    for (int k = 0; k < NC; ++k) { T0 += tot_s[t][k]; T1 += top_s[t][k]; }
     const double ind = (T1 > 0.0 && T0 > 0.0) ? log10(T1 / T0) : -99.0;
     sa.flags[blockIdx.x * EPG + t] = ind > sa.threshold ? 1 : 0;
   }
