@@ -86,16 +86,18 @@ __global__ void __launch_bounds__(kSubThreads) persson_kernel(const double* __re
   constexpr int NN = ipow<NP, DIM>::v, EPG = PerssonTile<DIM, NP>::EPG;
   __shared__ double a[EPG][NN], b[EPG][NN];
   __shared__ double tot_s[EPG][NN], top_s[EPG][NN];
+  __shared__ double sV[kMaxNP][kMaxNP];
   const int t = threadIdx.x, le = t / NN, n = t - (t / NN) * NN;
   const int e = blockIdx.x * EPG + le;
   const bool active = le < EPG && e < msh.E;
+  if (t < NP * NP) sV[t / NP][t % NP] = sa.V[t / NP][t % NP];
   if (active) a[le][n] = U[(long long)e * NN + n];
   __syncthreads();
   double* src = active ? a[le] : a[0];
   double* dst = active ? b[le] : b[0];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    if (active) sweep<DIM, NP>(sa.V, src, dst, d, n);
+    if (active) sweep<DIM, NP>(sV, src, dst, d, n);
     __syncthreads();
     double* x = src;
     src = dst;
@@ -151,24 +153,31 @@ __global__ void __launch_bounds__(kSubThreads) means_kernel(const double* __rest
                                                             MeshArgs msh) {
   constexpr int NN = ipow<NP, DIM>::v;
   constexpr int NV = DIM + 2;
-  __shared__ double a[NN], b[NN];
+  __shared__ double a[NV][NN], b[NV][NN];
+  __shared__ double sM[kMaxNP][kMaxNP];
   const int e = blockIdx.x, t = threadIdx.x;
   if (!sa.need[e]) return;  // uniform over the workgroup
-  for (int v = 0; v < NV; ++v) {
-    if (t < NN) a[t] = U[(long long)v * msh.S + (long long)e * NN + t];
-    __syncthreads();
-    double* src = a;
-    double* dst = b;
+  // all variables at once: one load latency and DIM + 1 barriers per element
+  if (t < NP * NP) sM[t / NP][t % NP] = sa.M[t / NP][t % NP];
+  if (t < NN) {
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      sweep<DIM, NP>(sa.M, src, dst, d, t);
-      __syncthreads();
-      double* x = src;
-      src = dst;
-      dst = x;
-    }
-    if (t < NN) sa.Ub[(long long)v * msh.S + (long long)e * NN + t] = src[t];
+    for (int v = 0; v < NV; ++v) a[v][t] = U[(long long)v * msh.S + (long long)e * NN + t];
+  }
+  __syncthreads();
+  double (*src)[NN] = a;
+  double (*dst)[NN] = b;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sweep<DIM, NP>(sM, src[v], dst[v], d, t);
     __syncthreads();
+    double (*x)[NN] = src;
+    src = dst;
+    dst = x;
+  }
+  if (t < NN) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sa.Ub[(long long)v * msh.S + (long long)e * NN + t] = src[v][t];
   }
 }
 
@@ -414,11 +423,13 @@ __global__ void __launch_bounds__(kSubThreads) fv_kernel(const double* __restric
   __shared__ double rs[NV][NN];                 // sub-cell rates
   __shared__ double Ff[NP + 1][NF][NV];         // face fluxes of one direction, by position along the lines
   __shared__ double Fg[2][NF][NV];              // DG face fluxes at the Gauss points of the two boundary faces
-  __shared__ double ta[NN], tb[NN];
+  __shared__ double tb[NV][NN];                 // second buffer of the inverse averaging
+  __shared__ double sMinv[kMaxNP][kMaxNP];
   const int e = blockIdx.x, t = threadIdx.x;
   if (!sa.flags[e]) return;  // uniform over the workgroup
   const double* Ub = sa.Ub;
   for (int i = t; i < NV * NN; i += kSubThreads) rs[i / NN][i % NN] = 0.0;
+  if (t < NP * NP) sMinv[t / NP][t % NP] = sa.Minv[t / NP][t % NP];
   __syncthreads();
 
 #pragma unroll
@@ -500,23 +511,24 @@ __global__ void __launch_bounds__(kSubThreads) fv_kernel(const double* __restric
     rs[NV - 1][t] += ph.ab * (rho - c);
   }
   __syncthreads();
-  // nodal rates and the stage update
-  for (int v = 0; v < NV; ++v) {
-    if (t < NN) ta[t] = rs[v][t];
-    __syncthreads();
-    double* src = ta;
-    double* dst = tb;
+  // nodal rates (the inverse averaging, all variables at once) and the
+  // stage update
+  double (*src)[NN] = rs;
+  double (*dst)[NN] = tb;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      sweep<DIM, NP>(sa.Minv, src, dst, d, t);
-      __syncthreads();
-      double* x = src;
-      src = dst;
-      dst = x;
-    }
-    if (t < NN) {
+  for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sweep<DIM, NP>(sMinv, src[v], dst[v], d, t);
+    __syncthreads();
+    double (*x)[NN] = src;
+    src = dst;
+    dst = x;
+  }
+  if (t < NN) {
+#pragma unroll 1
+    for (int v = 0; v < NV; ++v) {
       const long long o = (long long)v * msh.S + (long long)e * NN + t;
-      const double R = src[t];
+      const double R = src[v][t];
       if (st.mode == 0) {
         Uout[o] = R;
       } else {
@@ -525,7 +537,6 @@ __global__ void __launch_bounds__(kSubThreads) fv_kernel(const double* __restric
         Uout[o] = U[o] + st.B * du;
       }
     }
-    __syncthreads();
   }
   (void)NT;
 }
