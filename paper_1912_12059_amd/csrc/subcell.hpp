@@ -335,17 +335,10 @@ __device__ __forceinline__ void conv_numflux(int d, const double* uL, const doub
 // FV flux across the face between sub-cell a = (ea, ka) (left) and
 // b = (eb, kb) (right) in direction d
 template <int DIM, int NP, int FLUX>
-__device__ __forceinline__ void fv_face(const double* Ub, const double* Gb, const MeshArgs& m, const PhysArgs& ph,
-                                        int ea, int ka, int eb, int kb, int d, double* F) {
+__device__ __forceinline__ void fv_face(const double* w0, const double* w1, const double* w2, const double* w3,
+                                        const double* Gb, const MeshArgs& m, const PhysArgs& ph, int ea, int ka,
+                                        int eb, int kb, int d, double* F) {
   constexpr int NV = DIM + 2;
-  int eam, kam, ebp, kbp;
-  sub_nb<DIM, NP>(m, ea, ka, d, -1, eam, kam);
-  sub_nb<DIM, NP>(m, eb, kb, d, +1, ebp, kbp);
-  double w0[NV], w1[NV], w2[NV], w3[NV];
-  prim_at<DIM, NP>(Ub, m.S, eam, kam, w0);
-  prim_at<DIM, NP>(Ub, m.S, ea, ka, w1);
-  prim_at<DIM, NP>(Ub, m.S, eb, kb, w2);
-  prim_at<DIM, NP>(Ub, m.S, ebp, kbp, w3);
   double uL[NV], uR[NV];
   {
     double wL[NV], wR[NV];
@@ -425,6 +418,7 @@ __global__ void __launch_bounds__(kSubThreads) fv_kernel(const double* __restric
   __shared__ double Fg[2][NF][NV];              // DG face fluxes at the Gauss points of the two boundary faces
   __shared__ double tb[NV][NN];                 // second buffer of the inverse averaging
   __shared__ double sMinv[kMaxNP][kMaxNP];
+  __shared__ double sW[NF][NP + 4][NV];         // primitives along the lines of one direction, two beyond each end
   const int e = blockIdx.x, t = threadIdx.x;
   if (!sa.flags[e]) return;  // uniform over the workgroup
   const double* Ub = sa.Ub;
@@ -447,6 +441,17 @@ __global__ void __launch_bounds__(kSubThreads) fv_kernel(const double* __restric
 #pragma unroll
         for (int v = 0; v < NV; ++v) Fg[s][f][v] = F[v];
       }
+    }
+    // primitives of the sub-cells of every line of direction d, from
+    // position -2 (in the element before) to NP + 1 (in the element after):
+    // the four cells the MUSCL reconstruction of each face reads
+    for (int i = t; i < NF * (NP + 4); i += kSubThreads) {
+      const int line = i / (NP + 4), p = i % (NP + 4) - 2;
+      const int k0 = face_base<NP>(d, line);
+      int ec = e, kc = k0 + p * sd;
+      if (p < 0) { ec = en[0]; kc = k0 + (NP + p) * sd; }
+      if (p >= NP) { ec = en[1]; kc = k0 + (p - NP) * sd; }
+      prim_at<DIM, NP>(Ub, msh.S, ec, kc, sW[line][p + 2]);
     }
     __syncthreads();
     // face fluxes at every position 0..NP of every line of direction d
@@ -484,7 +489,8 @@ __global__ void __launch_bounds__(kSubThreads) fv_kernel(const double* __restric
           ka = k0 + (pos - 1) * sd;
           sub_nb<DIM, NP>(msh, e, ka, d, +1, eb, kb);
         }
-        fv_face<DIM, NP, FLUX>(Ub, sa.Gb, msh, ph, ea, ka, eb, kb, d, F);
+        fv_face<DIM, NP, FLUX>(sW[line][pos], sW[line][pos + 1], sW[line][pos + 2], sW[line][pos + 3], sa.Gb, msh, ph,
+                               ea, ka, eb, kb, d, F);
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) Ff[pos][line][v] = F[v];
