@@ -214,35 +214,48 @@ __device__ __forceinline__ void prim_at(const double* Ub, long long S, int e, in
 
 // central-difference gradient of (v, c) at sub-cell (e, k): q[dd][j]
 template <int DIM, int NP>
-__device__ __forceinline__ void sub_grad(const double* Ub, const MeshArgs& m, int e, int k, double q[DIM][DIM + 1]) {
-#pragma unroll
-  for (int dd = 0; dd < DIM; ++dd) {
-    int em, km, ep, kp;
-    sub_nb<DIM, NP>(m, e, k, dd, -1, em, km);
-    sub_nb<DIM, NP>(m, e, k, dd, +1, ep, kp);
-    double wm[DIM + 2], wp[DIM + 2];
-    prim_at<DIM, NP>(Ub, m.S, em, km, wm);
-    prim_at<DIM, NP>(Ub, m.S, ep, kp, wp);
-    // dx = h / NP along dd; h2 = 2/h
-    const int ed = dd == 0 ? e % m.nel[0] : (dd == 1 ? (e / m.nel[0]) % m.nel[1] : e / (m.nel[0] * m.nel[1]));
-    const double inv_dx = 0.5 * m.h2[dd][ed] * NP;
-#pragma unroll
-    for (int j = 0; j <= DIM; ++j) q[dd][j] = (wp[1 + j] - wm[1 + j]) * 0.5 * inv_dx;
-  }
-}
-
-template <int DIM, int NP>
 __global__ void __launch_bounds__(kSubThreads) grad_kernel(SubcellArgs sa, MeshArgs msh) {
-  constexpr int NN = Sub<DIM, NP>::NN;
+  // Central-difference gradients of (v, c) on the sub-cells of a troubled
+  // element: each sub-cell differences the primitives of its two
+  // neighbours along each direction.  The primitives of the element's own
+  // sub-cells and of the adjacent sub-cell layer of each neighbour element
+  // are formed once in LDS.
+  constexpr int NN = Sub<DIM, NP>::NN, NF = NN / NP, NW = DIM + 1;
+  __shared__ double sw[NN][NW];            // own sub-cells: (v, c)
+  __shared__ double sh[DIM][2][NF][NW];    // the neighbours' layers at the two d-faces
   const int e = blockIdx.x, t = threadIdx.x;
-  if (!sa.flags[e] || t >= NN) return;
-  double q[DIM][DIM + 1];
-  sub_grad<DIM, NP>(sa.Ub, msh, e, t, q);
+  if (!sa.flags[e]) return;  // uniform over the workgroup
+  double w[DIM + 2];
+  if (t < NN) {
+    prim_at<DIM, NP>(sa.Ub, msh.S, e, t, w);
+#pragma unroll
+    for (int j = 0; j < NW; ++j) sw[t][j] = w[1 + j];
+  }
+  for (int i = t; i < DIM * 2 * NF; i += kSubThreads) {
+    const int dd = i / (2 * NF), s = (i / NF) & 1, f = i % NF;
+    const int en = elem_step(msh, e, dd, s ? +1 : -1);
+    // the neighbour's sub-cell next to the face: last position before it, first after it
+    const int k = face_base<NP>(dd, f) + (s ? 0 : NP - 1) * dstride<NP>(dd);
+    prim_at<DIM, NP>(sa.Ub, msh.S, en, k, w);
+#pragma unroll
+    for (int j = 0; j < NW; ++j) sh[dd][s][f][j] = w[1 + j];
+  }
+  __syncthreads();
+  if (t >= NN) return;
   const long long o = (long long)e * NN + t;
 #pragma unroll
-  for (int dd = 0; dd < DIM; ++dd)
+  for (int dd = 0; dd < DIM; ++dd) {
+    const int sd = dstride<NP>(dd);
+    const int i = (t / sd) % NP;
+    const int f = face_of<NP>(dd, t);
+    const double* wm = i > 0 ? sw[t - sd] : sh[dd][0][f];
+    const double* wp = i < NP - 1 ? sw[t + sd] : sh[dd][1][f];
+    // dx = h / NP along dd; h2 = 2/h
+    const int ed = dd == 0 ? e % msh.nel[0] : (dd == 1 ? (e / msh.nel[0]) % msh.nel[1] : e / (msh.nel[0] * msh.nel[1]));
+    const double inv_dx = 0.5 * msh.h2[dd][ed] * NP;
 #pragma unroll
-    for (int j = 0; j <= DIM; ++j) sa.Gb[(long long)(dd * (DIM + 1) + j) * msh.S + o] = q[dd][j];
+    for (int j = 0; j < NW; ++j) sa.Gb[(long long)(dd * NW + j) * msh.S + o] = (wp[j] - wm[j]) * 0.5 * inv_dx;
+  }
 }
 
 // the stored sub-cell gradient of a troubled element's sub-cell
