@@ -197,3 +197,70 @@ def test_subcell_two_phase_riemann_problem(O, gpu):
     assert d["nonfinite"] == 0 and 0.2 < d["rho_min"] and d["rho_max"] < 2.2
     assert abs(d["mass"][0] - m0) <= 1e-13 * abs(m0)
     s.close()
+
+
+def test_subcell_full_size_3d_sampled(O, gpu):
+    """The 96x48x48, N = 4 collision (27.6M nodes) with sub-cells at
+    threshold -9 and the physics of the benchmark's sub-cell form: the GPU
+    flags equal the oracle's indicator decision for every element whose
+    indicator is not within 1e-9 of the threshold, and sampled elements
+    (troubled, DG next to troubled, random) match the oracle on a
+    5x5x5-element periodic patch centred on each (an element's rate depends
+    on elements at most two away: MUSCL and the neighbours' boundary
+    gradients reach two sub-cells into the neighbours, DG faces need the
+    neighbours' lifting)."""
+    import torch
+
+    nel = (96, 48, 48)
+    m, U = I.collision_3d(nel=nel, N=4, We=100.0)
+    kw = dict(alpha=1000.0, beta=1e-3, eps=1e-3, kappa=1e-5)
+    thr = -9.0
+    s = gpu.Solver(dim=3, N=4, nel=nel, lo=tuple(m.lo), hi=tuple(m.hi), subcell=1, subcell_threshold=thr, **kw)
+    Ut = torch.from_numpy(U.reshape(-1)).to("cuda:0")
+    R = torch.empty_like(Ut)
+    gpu.nsk_rhs(s.ctx, Ut.data_ptr(), R.data_ptr(), 0.0)
+    torch.cuda.synchronize()
+    R = R.reshape(U.shape)
+    flags = s.subcell_flags()
+    s.close()
+    h = [(m.hi[d] - m.lo[d]) / nel[d] for d in range(3)]
+    Pfull = O.Problem(dim=3, N=4, nel=nel, lo=tuple(m.lo), hi=tuple(m.hi), **kw)
+    ind = O.persson(Pfull, U)
+    clear = np.abs(ind - thr) > 1e-9
+    assert clear.mean() > 0.999
+    assert np.array_equal(flags[clear], (ind > thr)[clear])
+    assert 0.01 < flags.mean() < 0.2
+    # samples: troubled, DG elements with a troubled neighbour, random
+    g = np.random.Generator(np.random.PCG64(91))
+    ijk = np.stack(np.unravel_index(np.arange(m.nelem), nel[::-1])[::-1])  # (x, y, z) of each element
+
+    def eid(x, y, z):
+        return (x % nel[0]) + nel[0] * ((y % nel[1]) + nel[1] * (z % nel[2]))
+
+    nbr_troubled = np.zeros(m.nelem, dtype=bool)
+    for d in range(3):
+        for sgn in (-1, 1):
+            sh = [0, 0, 0]
+            sh[d] = sgn
+            nbr_troubled |= flags[eid(ijk[0] + sh[0], ijk[1] + sh[1], ijk[2] + sh[2])]
+    edge = np.where(~flags & nbr_troubled)[0]
+    samples = list(g.choice(np.where(flags)[0], 6, replace=False)) + list(g.choice(edge, 4, replace=False)) \
+        + list(g.integers(0, m.nelem, 2))
+    _, Mi = O.subcell_matrices(4)
+    amp = np.abs(Mi).sum(axis=1).max() ** 3
+    sc = term_scales(O, 4, min(h), U, kw["alpha"])
+    sc[-1] += kw["alpha"] / kw["beta"] * float(np.abs(U[[0, -1]]).max())
+    sc = sc * amp
+    centre = 2 + 5 * (2 + 5 * 2)
+    for e in samples:
+        ex, ey, ez = ijk[:, e]
+        near = [eid(ex + kx, ey + ky, ez + kz) for kz in range(-2, 3) for ky in range(-2, 3) for kx in range(-2, 3)]
+        if not clear[near].all():
+            continue
+        patch = np.ascontiguousarray(U[:, near, :])
+        P = O.Problem(dim=3, N=4, nel=(5, 5, 5), lo=(0, 0, 0), hi=(5 * h[0], 5 * h[1], 5 * h[2]), **kw)
+        Rp, fp = O.rhs_subcell(P, patch, thr)
+        assert fp[centre] == flags[e]
+        ulps = rhs_err_ulps(R[:, e, :].cpu().numpy(), Rp[:, centre, :], sc)
+        assert ulps <= RHS_ULPS, (e, bool(flags[e]), ulps)
+
