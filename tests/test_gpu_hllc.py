@@ -8,6 +8,7 @@ import pytest
 
 from paper_1912_12059_amd import inputs as I
 from test_gpu_parity import PHYS, TRAJ_TOL, _problem, _relerr_per_var, _rhs_check, _solver
+from tolerances import RHS_ULPS, rhs_err_ulps, term_scales
 
 pytestmark = pytest.mark.gpu
 
@@ -79,3 +80,40 @@ def test_hllc_mixed_precision(O, gpu):
     print(f"\nHLLC mixed vs FP64 oracle, rel L2(rho) after 100 steps: {rel:.3e}")
     assert rel <= 1e-6
     s.close()
+
+
+def test_hllc_full_size_3d_sampled(O, gpu):
+    """The 96x48x48, N = 4 collision (27.6M nodes) with the HLLC flux on the
+    GPU; sampled elements (most at the interfaces, where contacts of both
+    signs occur) are recomputed by the oracle on a 5x5x5-element periodic
+    patch centred on each (an element's right-hand side depends on elements
+    at most two away)."""
+    import torch
+
+    nel = (96, 48, 48)
+    m, U = I.collision_3d(nel=nel, N=4, We=100.0)
+    kw = dict(PHYS, alpha=1000.0)
+    s = _solver(gpu, m, flux=1, **kw)
+    Ut = torch.from_numpy(U.reshape(-1)).to("cuda:0")
+    R = torch.empty_like(Ut)
+    gpu.nsk_rhs(s.ctx, Ut.data_ptr(), R.data_ptr(), 0.0)
+    torch.cuda.synchronize()
+    R = R.reshape(U.shape)
+    s.close()
+    g = np.random.Generator(np.random.PCG64(83))
+    rho = U[0]
+    inter = np.where((rho.max(axis=1) > 1.0) & (rho.min(axis=1) < 1.0))[0]
+    samples = list(g.choice(inter, 12, replace=False)) + list(g.integers(0, m.nelem, 4))
+    h = [(m.hi[d] - m.lo[d]) / nel[d] for d in range(3)]
+    scales = term_scales(O, 4, min(h), U, kw["alpha"])
+    centre = 2 + 5 * (2 + 5 * 2)
+    for e in samples:
+        ex, ey, ez = e % nel[0], (e // nel[0]) % nel[1], e // (nel[0] * nel[1])
+        near = [((ex + kx) % nel[0]) + nel[0] * (((ey + ky) % nel[1]) + nel[1] * ((ez + kz) % nel[2]))
+                for kz in range(-2, 3) for ky in range(-2, 3) for kx in range(-2, 3)]
+        patch = np.ascontiguousarray(U[:, near, :])
+        P = O.Problem(dim=3, N=4, nel=(5, 5, 5), lo=(0, 0, 0), hi=(5 * h[0], 5 * h[1], 5 * h[2]), flux=1, **kw)
+        Rp = O.rhs(P, patch)
+        ulps = rhs_err_ulps(R[:, e, :].cpu().numpy(), Rp[:, centre, :], scales)
+        assert ulps <= RHS_ULPS, (e, ulps)
+
