@@ -598,11 +598,14 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
   for (int v = 0; v < NV; ++v) acc[v] = R(0);
 
   // Neighbour values of one direction (U and the direction's viscous
-  // components) in registers.  In FP64 the LDS holds the kernel at 2 waves
-  // per SIMD whatever its register count, so the next direction's values
-  // are fetched while the current one is computed; the mixed-precision
-  // kernel (3 waves per SIMD) fetches them when it stages them.
-  constexpr bool PREFETCH = !MIXED && FLUX != 1;  // the HLLC face code needs the registers
+  // components) in registers.  In FP64 model II the LDS holds the kernel at
+  // 2 waves per SIMD whatever its register count, so the next direction's
+  // values are fetched while the current one is computed.  The
+  // mixed-precision kernel (3 waves per SIMD) and the original NSK path
+  // (whose smaller LDS tile allows 5 elements per CU at 3 waves per SIMD,
+  // which the prefetch's registers would forbid) fetch them when they stage
+  // them; the HLLC face code needs the registers.
+  constexpr bool PREFETCH = !MIXED && FLUX != 1 && MODEL == 0;
   double nbv[2][NX];
   auto fetch_nb = [&](auto dc) {
     constexpr int dd = decltype(dc)::value;
@@ -831,8 +834,10 @@ lift_kernel(const double* __restrict__ U, GT* __restrict__ G, BasisArgs bas, Mes
   lift_block<DIM, NP, EPB, R, GT>(remap_block(blockIdx.x, gridDim.x, msh.nxcd), threadIdx.x, U, G, bas, msh, ph);
 }
 
+// The original NSK path's kernel is held to 3 waves per SIMD (it fits in
+// 168 VGPRs without its prefetch); the others keep the compiler's choice.
 template <int DIM, int NP, int EPB, typename R, typename GT, int FLUX = 0, int MODEL = 0>
-__global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
+__global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS)) __attribute__((amdgpu_waves_per_eu(MODEL == 1 ? 3 : 1)))
 rhs_kernel(const double* __restrict__ U, const GT* __restrict__ G, double* __restrict__ Uout,
            double* __restrict__ dU, BasisArgs bas, MeshArgs msh, PhysArgs ph, StageArgs st) {
   rhs_block<DIM, NP, EPB, R, GT, FLUX, MODEL>(remap_block(blockIdx.x, gridDim.x, msh.nxcd), threadIdx.x, U, G, Uout,
