@@ -9,10 +9,11 @@
 // by Newton's method, each correction from one cycle of right-preconditioned
 // GMRES with classical Gram-Schmidt (repeated when the projection cancels
 // most of the vector) and the Jacobian-vector product (R(X + s z) - R(X))/s;
-// then K_i = (X - B_i)/(dt gamma); U_{n+1} is the last stage's X.  Every right-hand side is nsk_rhs on the bound
-// context; the vector work runs in the kernels below, with fixed-order
-// reductions, so a run is bitwise reproducible.  The host reads back only
-// the dot products of each Arnoldi step.
+// then K_i = (X - B_i)/(dt gamma); U_{n+1} is the last stage's X.  Every
+// right-hand side is nsk_rhs on the bound context; the vector work runs in
+// the kernels below, with fixed-order reductions, so a run is bitwise
+// reproducible.  The host reads back only the dot products of each Arnoldi
+// step.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
