@@ -202,13 +202,15 @@ int nsk_set_tile(nsk_ctx* ctx, int variant, int order);
 
 /* Autotuner over the launch shapes of nsk_set_tile: times `reps`
  * right-hand-side evaluations of the bound state for each (variant, order)
- * pair with HIP events, keeps the fastest in the context and returns it;
- * ms_out (12 doubles, may be NULL) receives the mean ms per evaluation at
- * index variant * 6 + order (-1 for pairs skipped because they coincide with
- * another: tiled orders in 1D, and variant 1 where both variants put the same
- * number of elements in a workgroup; variant 0 is then returned).  Uses the workspace's second state
- * buffer as scratch, so it must be called between steps, and waits for the
- * stream. */
+ * pair with HIP events, keeps in the context the first pair (in index
+ * order) within 1% of the fastest, and returns it: near-equal timings are
+ * noise, and among the tiled orders the first is the smallest tile, which
+ * re-reads the fewest neighbour elements.  ms_out (12 doubles, may be NULL)
+ * receives the mean ms per evaluation at index variant * 6 + order (-1 for
+ * pairs skipped because they coincide with another: tiled orders in 1D, and
+ * variant 1 where both variants put the same number of elements in a
+ * workgroup).  Uses the workspace's second state buffer as scratch, so it
+ * must be called between steps, and waits for the stream. */
 int nsk_autotune(nsk_ctx* ctx, int reps, int* variant_out, int* order_out, double* ms_out);
 
 /* Changes alpha, beta, eps, kappa of an existing context (same mesh). */
