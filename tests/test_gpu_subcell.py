@@ -96,6 +96,39 @@ def test_subcell_degenerate_grids_parity(O, gpu, dim, N, nel, flux):
         s.close()
 
 
+@pytest.mark.parametrize("flux", [0, 1])
+def test_subcell_nonuniform_grid_parity(O, gpu, flux):
+    """Jittered element breakpoints in every direction (each element its own
+    widths, so the sub-cell widths and the central differences differ from
+    element to element) with a steep interface across x = 0.5."""
+    g = np.random.Generator(np.random.PCG64(17))
+    nel = (7, 5, 4)
+    xb = []
+    for d in range(3):
+        x = np.linspace(0.0, 1.0, nel[d] + 1)
+        x[1:-1] += g.uniform(-0.25, 0.25, nel[d] - 1) / nel[d]
+        xb.append(x)
+    m, U = I.smooth_random(3, 3, nel, seed=41, rho_range=(1.55, 1.75), xbreaks=xb)
+    X = I.node_coords(m)
+    step = 0.7 * np.tanh((X[0] - 0.5) / 0.01)
+    rho_old = U[0].copy()
+    U = U.copy()
+    U[0] = rho_old + step
+    for d in range(3):
+        U[1 + d] = U[1 + d] / rho_old * U[0]
+    U[-1] = U[-1] + step
+    P = O.Problem(dim=3, N=3, nel=nel, xbreaks=xb, flux=flux, **KW)
+    thr = _threshold(O.persson(P, U))
+    Rc, fc = O.rhs_subcell(P, U, thr)
+    assert 0 < fc.sum() < P.nelem
+    s = gpu.Solver(dim=3, N=3, nel=nel, xbreaks=xb, subcell=1, subcell_threshold=thr, flux=flux, **KW)
+    R = s.rhs(U).cpu().numpy()
+    assert np.array_equal(s.subcell_flags(), fc)
+    ulps = rhs_err_ulps(R, Rc, _scales(O, P, U))
+    assert ulps <= RHS_ULPS, f"{ulps:.1f} ulps"
+    s.close()
+
+
 def test_subcell_trajectory_shock_tube(O, gpu):
     """The oracle's p-system shock tube (N = 3, 40 elements, every element on
     sub-cells): 60 steps against the oracle."""
