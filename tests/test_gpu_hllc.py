@@ -25,6 +25,20 @@ def test_hllc_rhs_parity(O, gpu, dim, N, nel, diss_c):
     s.close()
 
 
+@pytest.mark.parametrize("diss_c", [0, 1])
+def test_hllc_rhs_parity_nonuniform(O, gpu, diss_c):
+    """Random element breakpoints in every direction."""
+    g = np.random.Generator(np.random.PCG64(13))
+    xb = [np.sort(np.concatenate([[0.0, 1.0], g.uniform(0.05, 0.95, 5)])) for _ in range(3)]
+    m, U = I.smooth_random(3, 3, (6, 6, 6), seed=19, xbreaks=xb, vmax=0.5)
+    phys = dict(PHYS, diss_c=diss_c)
+    s = _solver(gpu, m, flux=1, **phys)
+    R = s.rhs(U).cpu().numpy()
+    Rc = O.rhs(_problem(O, m, flux=1, **phys), U)
+    _rhs_check(O, m, U, R, Rc, PHYS["alpha"])
+    s.close()
+
+
 def test_hllc_rhs_parity_collision(O, gpu):
     """Moving droplets: contacts with both signs of S* inside the interfaces."""
     m, U = I.collision_3d(nel=(12, 6, 6), N=4, We=100.0, hi=(2.0, 1.0, 1.0), impact=0.1)
