@@ -129,11 +129,12 @@ __global__ void __launch_bounds__(kSubThreads) persson_kernel(const double* __re
     top_s[le][n] = T1;
   }
   __syncthreads();
-  if (t < EPG && blockIdx.x * EPG + t < msh.E) {
+  const int et = (int)blockIdx.x * EPG + t;  // element of thread t < EPG
+  if (t < EPG && et < msh.E) {
     double T0 = 0.0, T1 = 0.0;
     for (int k = 0; k < NC; ++k) { T0 += tot_s[t][k]; T1 += top_s[t][k]; }
     const double ind = (T1 > 0.0 && T0 > 0.0) ? log10(T1 / T0) : -99.0;
-    sa.flags[blockIdx.x * EPG + t] = ind > sa.threshold ? 1 : 0;
+    sa.flags[et] = ind > sa.threshold ? 1 : 0;
   }
 }
 
