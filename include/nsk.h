@@ -125,7 +125,8 @@ typedef struct {
 
 /* Creates a context for a mesh and parameter set (host only; no device
  * memory is touched).  Rejects dim outside 1..3, N outside 1..6, nel < 1,
- * (NSK_EUNSUPPORTED for dim = 3 with N = 6, whose element tile exceeds 64 KB
+ * (NSK_EUNSUPPORTED for dim = 3 with N = 6: not built, its 343-node element
+ * exceeds the sub-cell workgroups and its rhs tile would take about 105 KB
  * of LDS),
  * non-increasing breakpoints, T outside (0,1), eps < 0, kappa < 0, model
  * outside 0..1, and for model 0 alpha <= 6 (1 - T), beta <= 0 or flux

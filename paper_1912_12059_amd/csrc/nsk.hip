@@ -310,7 +310,10 @@ int nsk_create(const nsk_mesh* mesh, const nsk_params* params, nsk_ctx** out) {
   if (!mesh || !out) return NSK_EINVAL;
   *out = nullptr;
   if (mesh->dim < 1 || mesh->dim > 3 || mesh->N < 1 || mesh->N > kMaxNP - 1) return NSK_EINVAL;
-  if (mesh->dim == 3 && mesh->N > 5) return NSK_EUNSUPPORTED;  // LDS of one 3D element above 64 KB
+  // not built: a 3D element of degree 6 has 343 nodes, more than the 256
+  // threads of the sub-cell workgroups, and its rhs tile would take about
+  // 105 KB of LDS (one workgroup per CU)
+  if (mesh->dim == 3 && mesh->N > 5) return NSK_EUNSUPPORTED;
   int rc = check_params(params);
   if (rc) return rc;
   nsk_ctx* c = new (std::nothrow) nsk_ctx();
