@@ -542,7 +542,18 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
   __shared__ R sOwn[EPB][NX][NN];           // own U and (tau_{.d}, dc/dx_d)
   __shared__ R sNb[EPB][2][NX][NN];         // the same for the two neighbours in direction d
   __shared__ double sRho64[R64E][3][R64N];  // FP64 densities (mixed precision only)
-  __shared__ R sF[2][EPB][NV][NN];          // total flux Fc_d - Fv_d (double-buffered by direction)
+  // The nodal flux is double-buffered by direction (so that the
+  // accumulation of d and the staging of d+1 share a phase) only where the
+  // second buffer costs no workgroup per CU, or where at least 6 still fit
+  // (2-wave workgroups are then held by their registers first); otherwise one
+  // buffer and one more barrier per direction.
+  constexpr int kLdsCu = 163840;
+  constexpr int LDS_FIXED = int(sizeof(R)) * (EPB * 3 * NX * NN + EPB * 2 * NV * NF + NP * NP + 3 * NP) +
+                            int(sizeof(double)) * R64E * 3 * R64N + int(sizeof(ElemInfo<DIM, EPB>));
+  constexpr int LDS_F = int(sizeof(R)) * EPB * NV * NN;
+  constexpr bool PIPE = kLdsCu / (LDS_FIXED + 2 * LDS_F) == kLdsCu / (LDS_FIXED + LDS_F) ||
+                        kLdsCu / (LDS_FIXED + 2 * LDS_F) >= 6;
+  __shared__ R sF[PIPE ? 2 : 1][EPB][NV][NN];  // total flux Fc_d - Fv_d
   __shared__ R sFs[EPB][2][NV][NF];         // numerical flux on the two d-faces
   __shared__ R sD[NP][NP];
   __shared__ R sLm[NP], sLp[NP], sIw[NP];
@@ -639,7 +650,7 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
       for (int j = 0; j < DIM; ++j) F[1 + j] -= g[tau_index<DIM>(j, d)];
       if constexpr (MODEL == 0) F[DIM + 1] -= kb * g[NT + d];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) sF[d & 1][el][v][n] = F[v];
+      for (int v = 0; v < NV; ++v) sF[PIPE ? (d & 1) : 0][el][v][n] = F[v];
       // the two neighbours, coalesced
       if (!PREFETCH) fetch_nb(dc);
 #pragma unroll
@@ -774,7 +785,7 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
       for (int v = 0; v < NV; ++v) {
         R vol = R(0);
 #pragma unroll
-        for (int l = 0; l < NP; ++l) vol += Drow[l] * sF[d & 1][el][v][n + (l - i) * sd];
+        for (int l = 0; l < NP; ++l) vol += Drow[l] * sF[PIPE ? (d & 1) : 0][el][v][n + (l - i) * sd];
         acc[v] += h2 * (vol - (lp * sFs[el][1][v][f] - lm * sFs[el][0][v][f]));
       }
     }
@@ -787,6 +798,7 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
     __syncthreads();
     accum(dc);
     if constexpr (d + 1 < DIM) {
+      if constexpr (!PIPE) __syncthreads();  // the single nodal-flux buffer is reused
       stage(std::integral_constant<int, d + 1>{});
       __syncthreads();
     }
@@ -837,7 +849,7 @@ lift_kernel(const double* __restrict__ U, GT* __restrict__ G, BasisArgs bas, Mes
 // The original NSK path's kernel is held to 3 waves per SIMD (it fits in
 // 168 VGPRs without its prefetch); the others keep the compiler's choice.
 template <int DIM, int NP, int EPB, typename R, typename GT, int FLUX = 0, int MODEL = 0>
-__global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS)) __attribute__((amdgpu_waves_per_eu(MODEL == 1 ? 3 : 1)))
+__global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS)) __attribute__((amdgpu_waves_per_eu(MODEL == 1 ? 3 : 2)))
 rhs_kernel(const double* __restrict__ U, const GT* __restrict__ G, double* __restrict__ Uout,
            double* __restrict__ dU, BasisArgs bas, MeshArgs msh, PhysArgs ph, StageArgs st) {
   rhs_block<DIM, NP, EPB, R, GT, FLUX, MODEL>(remap_block(blockIdx.x, gridDim.x, msh.nxcd), threadIdx.x, U, G, Uout,

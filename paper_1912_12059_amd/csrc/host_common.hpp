@@ -298,7 +298,7 @@ struct Epb {
   using Sh = Shape<DIM, NP>;
   static constexpr int NX = Sh::NVAR + DIM + 1;
   static constexpr int lds(int epb) {
-    return 8 * epb * (3 * NX * Sh::NN + 2 * Sh::NVAR * Sh::NN + 2 * Sh::NVAR * Sh::NF) + 1024;
+    return 8 * epb * (3 * NX * Sh::NN + Sh::NVAR * Sh::NN + 2 * Sh::NVAR * Sh::NF) + 1024;
   }
   static constexpr int pick(int epb) { return (epb <= 1 || lds(epb) <= 40960) ? (epb < 1 ? 1 : epb) : pick(epb - 1); }
   static constexpr int V0 = pick(256 / Sh::NN);
