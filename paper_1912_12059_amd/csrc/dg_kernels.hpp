@@ -926,7 +926,7 @@ lift_kernel_batch1(const BatchInst* __restrict__ inst, const BatchItem* __restri
 }
 
 template <int DIM, int NP, int EPB, typename R, typename GT>
-__global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
+__global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS)) __attribute__((amdgpu_waves_per_eu(2)))
 rhs_kernel_batch1(const BatchInst* __restrict__ inst, const BatchItem* __restrict__ items, BasisArgs bas,
                   PhysArgs ph, StageArgs st) {
   const BatchItem w = items[remap_block(blockIdx.x, gridDim.x, kBatchXcds)];
@@ -962,7 +962,7 @@ lift_kernel_batch(const BatchInst* __restrict__ inst, const BatchItem* __restric
 }
 
 template <int DIM, int NP, int EPB, typename R, typename GT>
-__global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
+__global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS)) __attribute__((amdgpu_waves_per_eu(2)))
 rhs_kernel_batch(const BatchInst* __restrict__ inst, const BatchItem* __restrict__ items, int nitems,
                  BasisArgs bas, PhysArgs ph, StageArgs st) {
   const int slot = remap_block(blockIdx.x, gridDim.x, kBatchXcds);
