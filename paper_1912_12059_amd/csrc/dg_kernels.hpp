@@ -544,15 +544,16 @@ __device__ __forceinline__ void rhs_block(int L, int tid, const double* __restri
   __shared__ double sRho64[R64E][3][R64N];  // FP64 densities (mixed precision only)
   // The nodal flux is double-buffered by direction (so that the
   // accumulation of d and the staging of d+1 share a phase) only where the
-  // second buffer costs no workgroup per CU, or where at least 6 still fit
-  // (2-wave workgroups are then held by their registers first); otherwise one
-  // buffer and one more barrier per direction.
+  // second buffer costs no workgroup per CU, or where at least 5 still fit
+  // (measured: the original NSK kernel runs faster pipelined at 5 per CU than
+  // with one buffer at 6); otherwise one buffer and one more barrier per
+  // direction.
   constexpr int kLdsCu = 163840;
   constexpr int LDS_FIXED = int(sizeof(R)) * (EPB * 3 * NX * NN + EPB * 2 * NV * NF + NP * NP + 3 * NP) +
                             int(sizeof(double)) * R64E * 3 * R64N + int(sizeof(ElemInfo<DIM, EPB>));
   constexpr int LDS_F = int(sizeof(R)) * EPB * NV * NN;
   constexpr bool PIPE = kLdsCu / (LDS_FIXED + 2 * LDS_F) == kLdsCu / (LDS_FIXED + LDS_F) ||
-                        kLdsCu / (LDS_FIXED + 2 * LDS_F) >= 6;
+                        kLdsCu / (LDS_FIXED + 2 * LDS_F) >= 5;
   __shared__ R sF[PIPE ? 2 : 1][EPB][NV][NN];  // total flux Fc_d - Fv_d
   __shared__ R sFs[EPB][2][NV][NF];         // numerical flux on the two d-faces
   __shared__ R sD[NP][NP];
