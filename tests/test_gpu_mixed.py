@@ -39,7 +39,9 @@ def _l2_rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("dim,N,nel", [(1, 3, (64,)), (2, 4, (8, 7)), (3, 4, (5, 4, 3)), (3, 3, (6, 5, 4))])
+@pytest.mark.parametrize("dim,N,nel", [(1, 3, (64,)), (2, 4, (8, 7)), (3, 4, (5, 4, 3)), (3, 3, (6, 5, 4)),
+                                       # low and high degrees: several workgroups and a ragged tail
+                                       (1, 5, (100,)), (1, 6, (90,)), (2, 1, (9, 11)), (2, 2, (9, 7))])
 def test_mixed_rhs_within_fp32_rounding(O, gpu, dim, N, nel):
     m, U = I.smooth_random(dim, N, nel, seed=60 + N)
     s = _solver(gpu, m, precision=1, **PHYS)

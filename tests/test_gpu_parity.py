@@ -51,6 +51,8 @@ PHYS = dict(T=0.85, eps=1e-3, kappa=1e-5, alpha=500.0, beta=1e-3)
 
 @pytest.mark.parametrize("dim,N,nel", [
     (1, 1, (7,)), (1, 3, (64,)), (1, 6, (5,)),
+    # several workgroups of the 1D tiles (83, 51, 42 elements) and a ragged tail
+    (1, 2, (200,)), (1, 4, (130,)), (1, 5, (100,)),
     (2, 2, (5, 4)), (2, 4, (7, 6)), (2, 5, (3, 4)),
     (3, 1, (4, 3, 5)), (3, 2, (5, 3, 2)), (3, 3, (4, 3, 3)), (3, 4, (3, 4, 3)), (3, 5, (3, 2, 3)),
 ])
