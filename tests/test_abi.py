@@ -272,3 +272,49 @@ def test_subcell_host_side_checks():
     with pytest.raises(nsk.NskError) as e:
         nsk.nsk_batch_create([bm], nsk.make_params(flux=1))
     assert e.value.code == nsk.NSK_EUNSUPPORTED
+
+
+def test_core_host_side_checks():
+    """Argument and binding checks of the core entry points, taken before any
+    device work (the pointers below are never dereferenced)."""
+    m, keep = _ok_mesh()
+    ctx = nsk.nsk_create(m, nsk.make_params())
+    fake_u, fake_r = 0x1000, 0x2000
+    try:
+        # launch shape: 2 variants x 6 orders; an unbound context only stores it
+        for v, o in ((-1, 0), (2, 0), (0, -1), (0, 6)):
+            with pytest.raises(nsk.NskError) as e:
+                nsk.nsk_set_tile(ctx, v, o)
+            assert e.value.code == nsk.NSK_EINVAL
+        nsk.nsk_set_tile(ctx, 1, 5)
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_autotune(ctx, 0)
+        assert e.value.code == nsk.NSK_EINVAL
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_autotune(ctx, 3)
+        assert e.value.code == nsk.NSK_EUNBOUND
+        # rhs: output aliasing the input, null pointers, then the binding
+        for u, r in ((fake_u, fake_u), (0, fake_r), (fake_u, 0)):
+            with pytest.raises(nsk.NskError) as e:
+                nsk.nsk_rhs(ctx, u, r)
+            assert e.value.code == nsk.NSK_EINVAL
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_rhs(ctx, fake_u, fake_r)
+        assert e.value.code == nsk.NSK_EUNBOUND
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_diagnostics(ctx)
+        assert e.value.code == nsk.NSK_EUNBOUND
+        # sub-cell flags exist only in sub-cell contexts
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_subcell_flags(ctx, fake_u)
+        assert e.value.code == nsk.NSK_EINVAL
+        # the workspace layout fixes model, precision, closure and sub-cell flag
+        for kw in (dict(precision=1), dict(model=1, flux=2), dict(subcell=1)):
+            with pytest.raises(nsk.NskError) as e:
+                nsk.nsk_set_params(ctx, nsk.make_params(**kw))
+            assert e.value.code == nsk.NSK_EINVAL
+        nsk.nsk_set_params(ctx, nsk.make_params(alpha=800.0))
+        # nothing timed yet: zeros
+        assert nsk.nsk_timing_read(ctx) == (0.0, 0.0, 0, 0.0)
+    finally:
+        nsk.nsk_destroy(ctx)
