@@ -318,3 +318,47 @@ def test_core_host_side_checks():
         assert nsk.nsk_timing_read(ctx) == (0.0, 0.0, 0, 0.0)
     finally:
         nsk.nsk_destroy(ctx)
+
+
+def test_batch_host_side_checks():
+    """Packing of the batched state and the batch entry points' argument and
+    binding checks, before any device work."""
+    m1, k1 = nsk.make_mesh(3, 3, (4, 3, 2))
+    m2, k2 = nsk.make_mesh(3, 4, (3, 3, 3))
+    b = nsk.nsk_batch_create([m1, m2], nsk.make_params())
+    try:
+        # instance slices: in order, disjoint, 256-byte aligned
+        n0, n1 = 5 * 24 * 64, 5 * 27 * 125
+        o0, o1 = nsk.nsk_batch_state_offset(b, 0), nsk.nsk_batch_state_offset(b, 1)
+        assert o0 == 0 and o1 >= o0 + n0 and o1 % 32 == 0
+        assert nsk.nsk_batch_state_size(b) >= o1 + n1
+        assert [g["N"] for g in nsk.nsk_batch_groups(b)] == [3, 4]
+        assert nsk.nsk_batch_ctx(b, 1) != 0
+        for inst in (-1, 2):
+            with pytest.raises(nsk.NskError) as e:
+                nsk.nsk_batch_ctx(b, inst)
+            assert e.value.code == nsk.NSK_EINVAL
+        # group launch shapes: group index, variant, grid multiple, order, chunk
+        for args in ((2, 0, 0, 0, 0), (0, 2, 0, 0, 0), (0, 0, 3, 0, 0), (0, 0, 0, 6, 0), (0, 0, 0, 0, -1)):
+            with pytest.raises(nsk.NskError) as e:
+                nsk.nsk_batch_set_group(b, *args)
+            assert e.value.code == nsk.NSK_EINVAL
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_batch_set_group(b, 1, 1, 4, 3, 8)
+        assert e.value.code == nsk.NSK_EUNBOUND
+        for bad_dt in (0.0, -1e-6, float("nan"), float("inf")):
+            with pytest.raises(nsk.NskError) as e:
+                nsk.nsk_batch_rk_step(b, bad_dt, 1)
+            assert e.value.code == nsk.NSK_EINVAL
+        for fn, args in ((nsk.nsk_batch_rk_step, (1e-6, 2)), (nsk.nsk_batch_dt_estimate, (0.5,)),
+                         (nsk.nsk_batch_autotune, (2,))):
+            with pytest.raises(nsk.NskError) as e:
+                fn(b, *args)
+            assert e.value.code == nsk.NSK_EUNBOUND
+        # only 3D instances
+        m3, k3 = nsk.make_mesh(2, 4, (5, 5))
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_batch_create([m1, m3], nsk.make_params())
+        assert e.value.code == nsk.NSK_EUNSUPPORTED
+    finally:
+        nsk.nsk_batch_destroy(b)
