@@ -602,6 +602,8 @@ def main() -> int:
                     help="run only one implicit step of 100x the explicit step, no explicit reference (profiling)")
     ap.add_argument("--only-subcell", type=float, default=None, metavar="THRESHOLD",
                     help="run only the FV sub-cell form at this indicator threshold (profiling)")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the batched collision sweep and the 64 small collisions (prints their blocks)")
     ap.add_argument("--only-nsk", action="store_true",
                     help="run only the original NSK form on the workload (prints its block)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -630,6 +632,9 @@ def main() -> int:
 
     if args.only_closure:
         print(json.dumps({"closure": run_closure_form(nsk)}))
+        return 0
+    if args.only_batched:
+        print(json.dumps({"batched": run_batched(nsk, 10, 2), "batched_small": run_batched_small(nsk)}))
         return 0
     w = WORKLOADS[args.workload]
     print(f"[bench] building {args.workload} state", file=sys.stderr, flush=True)
