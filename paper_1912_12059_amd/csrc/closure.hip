@@ -185,16 +185,28 @@ mlp_train_kernel(const uint16_t* __restrict__ w, const float* __restrict__ X, co
   }
 }
 
-// Sum of the partial gradients (and loss) over the workgroups, in a fixed
-// order: one thread per parameter.
-__global__ void mlp_reduce_kernel(const float* __restrict__ part, int nparts, float* __restrict__ grad,
-                                  float* __restrict__ loss) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k > kMlpParams) return;
+// Sum of the partial gradients (and loss) over the training workgroups, in
+// a fixed order. A workgroup owns 64 consecutive parameters (one per lane, so
+// each partial row is read 256 bytes at a time); each of its waves sums one
+// contiguous range of the partials, and the wave sums are added in wave order.
+constexpr int kRedCols = 64, kRedWaves = 8;
+__global__ void __launch_bounds__(kRedCols * kRedWaves)
+mlp_reduce_kernel(const float* __restrict__ part, int nparts, float* __restrict__ grad, float* __restrict__ loss) {
+  __shared__ double sp[kRedWaves][kRedCols];
+  const int lane = (int)threadIdx.x % kRedCols, wv = (int)threadIdx.x / kRedCols;
+  const int k = (int)blockIdx.x * kRedCols + lane;
+  const int q = (nparts + kRedWaves - 1) / kRedWaves;
+  const int p0 = min(nparts, wv * q), p1 = min(nparts, p0 + q);
   double s = 0.0;
-  for (int p = 0; p < nparts; ++p) s += part[(long long)p * (kMlpParams + 1) + k];
-  if (k < kMlpParams) grad[k] = float(s);
-  else if (loss) *loss = float(s);
+  if (k <= kMlpParams)
+    for (int p = p0; p < p1; ++p) s += part[(long long)p * (kMlpParams + 1) + k];
+  sp[wv][lane] = s;
+  __syncthreads();
+  if (wv != 0 || k > kMlpParams) return;
+  double t = 0.0;
+  for (int w = 0; w < kRedWaves; ++w) t += sp[w][lane];
+  if (k < kMlpParams) grad[k] = float(t);
+  else if (loss) *loss = float(t);
 }
 
 // Adam (Kingma and Ba) on the FP32 master copy; the BF16 parameters the
@@ -364,8 +376,8 @@ int nsk_mlp_loss_grad(const uint16_t* d_w, const float* d_X, const float* d_Y, c
   float* part = static_cast<float*>(d_ws);
   hipLaunchKernelGGL(mlp_train_kernel, dim3((unsigned)tiles), dim3(kTrainThreads), 0, s, d_w, d_X, d_Y, d_idx, n,
                      float(1.0 / double(n)), tscale0, tscale1, part);
-  hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kMlpParams + 1 + 255) / 256), dim3(256), 0, s, part, (int)tiles, d_grad,
-                     d_loss);
+  hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kMlpParams + 1 + kRedCols - 1) / kRedCols), dim3(kRedCols * kRedWaves), 0,
+                     s, part, (int)tiles, d_grad, d_loss);
   return hipGetLastError() == hipSuccess ? NSK_OK : NSK_EHIP;
 }
 
