@@ -90,6 +90,32 @@ def test_loss_grad_matches_oracle(O, gpu):
     assert torch.equal(grad, grad2) and torch.equal(loss, loss2)
 
 
+
+@pytest.mark.parametrize("k", [3, 70])
+def test_loss_grad_reduction_over_many_partials(gpu, k):
+    """The loss and gradient are means over the sampled rows, so repeating one
+    64-row index block k times leaves them unchanged up to FP32 rounding. The
+    gradient is summed from 32-row partials: 2 partials for the block alone,
+    2k repeated (6 and 140: fewer partials than reducing waves, and many)."""
+    import torch
+
+    from paper_1912_12059_amd import closure as CL
+
+    w = CL.init_params(seed=9)
+    rng = np.random.default_rng(10)
+    n = 500
+    Xd = torch.from_numpy(rng.normal(0, 1.0, (n, 4)).astype(np.float32)).cuda()
+    Td = torch.from_numpy(rng.normal(0, 1.0, (n, 2)).astype(np.float32)).cuda()
+    base = rng.permutation(n)[:64].astype(np.int32)
+    net = _net(gpu, w)
+    q = (1.0, 1.0)
+    l1, g1 = net.loss_grad(Xd, Td, torch.from_numpy(base).cuda(), tscale=q)
+    lk, gk = net.loss_grad(Xd, Td, torch.from_numpy(np.tile(base, k)).cuda(), tscale=q)
+    g1 = g1.cpu().numpy().astype(np.float64)
+    gk = gk.cpu().numpy().astype(np.float64)
+    assert float(lk.item()) == pytest.approx(float(l1.item()), rel=1e-5)
+    assert np.linalg.norm(gk - g1) <= 1e-5 * np.linalg.norm(g1)
+
 def test_adam_matches_oracle(O, gpu):
     import torch
 
