@@ -159,26 +159,38 @@ int nsk_set_state(nsk_ctx* ctx, const double* d_src);
 /* Copies the bound state into a device array. */
 int nsk_get_state(nsk_ctx* ctx, double* d_dst);
 
-/* Semi-discrete right-hand side R = dU/dt of the device state d_U
- * (any array with the state layout, not necessarily the bound one), source
- * included.  d_R must not alias d_U.  The scheme is autonomous, t is unused. */
+/* Semi-discrete right-hand side R = dU/dt of the device state d_U (any
+ * array with the state layout, not necessarily the bound one): the DGSEM
+ * weak form of Sec. 3.1 on Gauss-Legendre nodes with BR1 lifting of (v, c),
+ * applied to relaxation model II of Sec. 2.3 (convective flux with the
+ * modified pressure p + alpha rho^2/2, viscous flux (tau, (kappa/beta) grad c),
+ * source (0, alpha rho grad c, (alpha/beta)(rho - c))), or to the original
+ * NSK equations of Sec. 2.2 when model = 1.  d_R must not alias d_U.  The
+ * scheme is autonomous, t is unused. */
 int nsk_rhs(nsk_ctx* ctx, const double* d_U, double* d_R, double t);
 
-/* Time-step estimate for the bound state:
+/* Time-step estimate for the bound state, after the parabolic bound of
+ * Sec. 3.1 with the relaxation source of Sec. 2.3 on the same equation:
  *   dt = cfl * min(1/((2N+1) max_e sum_d max(|v_d|+a)/h_d),
- *                  1/((2N+1)^2 max_e sum_d max(eps, kappa/beta)/h_d^2),
- *                  z_R beta/alpha)
+ *                  1/((2N+1)^2 eps max_e sum_d 1/h_d^2),
+ *                  1/((2N+1)^2 (kappa/beta) max_e sum_d 1/h_d^2 + alpha/(beta z_R)))
  * with a = sqrt(p'(rho) + alpha rho) and z_R the negative-real-axis
- * stability limit of the Runge-Kutta scheme.  Model 1:
+ * stability limit of the Runge-Kutta scheme.  The last bound is that of the
+ * equation for c: its diffusion and relaxation-source rates are both real
+ * and negative, so they add.  Model 1:
  *   dt = cfl * min(1/((2N+1) lam max_e sum_d 1/h_d),
  *                  1/((2N+1)^2 eps max_e sum_d 1/h_d^2),
  *                  (1/4)/((2N+1)^2 sqrt(kappa rho_max) max_e sum_d 1/h_d^2))
  * with lam the global Lax-Friedrichs speed (the last bound is that of the
- * capillary modes, frequencies sqrt(kappa rho) k^2).  Waits for the stream. */
+ * capillary modes, frequencies sqrt(kappa rho) k^2).  Waits for the stream.
+ * NSK_ENONPHYS if the state holds non-finite values. */
 int nsk_dt_estimate(nsk_ctx* ctx, double cfl, double* dt_out);
 
-/* Advances the bound state by nsteps steps of size dt (five stages each).
- * Asynchronous.  On return of the enqueued work the state is in d_U. */
+/* Advances the bound state by nsteps steps of size dt of the five-stage,
+ * fourth-order low-storage Runge-Kutta scheme of Sec. 3.1 (Carpenter-Kennedy
+ * 2N-storage coefficients): per stage dU <- A_s dU + dt R(U), U <- U + B_s dU,
+ * fused into the right-hand-side kernel.  Asynchronous.  On return of the
+ * enqueued work the state is in d_U. */
 int nsk_rk_step(nsk_ctx* ctx, double dt, int nsteps);
 
 /* Diagnostics of the bound state (quadrature over all elements, with the

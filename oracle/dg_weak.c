@@ -282,19 +282,25 @@ int or_run(const or_prob* P, double* U, double dt, int nsteps, double t0, or_for
 }
 
 /* ------------------------------------------------------------------------ */
-/* Time-step rule: CFL * min(dt_conv, dt_visc, dt_source) with
- *   dt_conv   = 1 / ((2N+1) max_e sum_d max_nodes(|v_d| + a) / h_d)
- *   dt_visc   = 1 / ((2N+1)^2 max_e sum_d lambda_v / h_d^2),
- *               lambda_v = max(eps, kappa/beta)   (parabolic bound, Sec. 3.1)
- *   dt_source = |z_R| beta / alpha, |z_R| the real-axis stability limit.    */
+/* Time-step rule (parabolic bound of Sec. 3.1, with the relaxation source of
+ * Sec. 2.3 acting on the same equation for c):
+ *   dt = CFL * min(dt_conv, dt_mom, dt_c)
+ *   dt_conv = 1 / ((2N+1) max_e sum_d max_nodes(|v_d| + a) / h_d)
+ *   dt_mom  = 1 / ((2N+1)^2 max_e sum_d eps / h_d^2)        (viscous momentum)
+ *   dt_c    = 1 / ((2N+1)^2 max_e sum_d (kappa/beta) / h_d^2 + alpha / (beta |z_R|))
+ * The screened heat equation beta c_t = kappa lap c + alpha (rho - c) has real
+ * negative eigenvalues: the diffusion's and the source's, which add.  Both
+ * must fit together inside the real-axis stability limit |z_R| of the
+ * Runge-Kutta scheme, so their rates are summed rather than bounded apart
+ * (bounded apart, the step leaves the stability region where the two are
+ * about equal). */
 double or_dt(const or_prob* P, const double* U, double cfl) {
   or_geom g;
   if (or_geom_init(&g, P)) return NAN;
   const size_t S = (size_t)g.E * g.nnode;
-  double lam_c = 0.0, lam_v = 0.0;
-  double lv = fmax(P->eps, P->kappa / P->beta);
+  double lam_c = 0.0, lam_m = 0.0, lam_k = 0.0;
   for (long e = 0; e < g.E; ++e) {
-    double sc = 0.0, sv = 0.0;
+    double sc = 0.0, sm = 0.0, sk = 0.0;
     for (int d = 0; d < g.dim; ++d) {
       double h = or_width(&g, e, d), mx = 0.0;
       for (int n = 0; n < g.nnode; ++n) {
@@ -303,17 +309,19 @@ double or_dt(const or_prob* P, const double* U, double cfl) {
         mx = fmax(mx, wave_speed(P, d, u));
       }
       sc += mx / h;
-      sv += lv / (h * h);
+      sm += P->eps / (h * h);
+      sk += (P->kappa / P->beta) / (h * h);
     }
     lam_c = fmax(lam_c, sc);
-    lam_v = fmax(lam_v, sv);
+    lam_m = fmax(lam_m, sm);
+    lam_k = fmax(lam_k, sk);
   }
-  int N2 = 2 * P->N + 1;
-  double dtc = 1.0 / (N2 * lam_c);
-  double dtv = 1.0 / ((double)N2 * N2 * lam_v);
-  double dts = or_lsrk_real_limit() * P->beta / P->alpha;
+  const double N2 = 2.0 * P->N + 1.0;
+  const double dtc = 1.0 / (N2 * lam_c);
+  const double dtm = 1.0 / (N2 * N2 * lam_m);
+  const double dtk = 1.0 / (N2 * N2 * lam_k + P->alpha / (P->beta * or_lsrk_real_limit()));
   or_geom_free(&g);
-  return cfl * fmin(dtc, fmin(dtv, dts));
+  return cfl * fmin(dtc, fmin(dtm, dtk));
 }
 
 /* ------------------------------------------------------------------------ */

@@ -591,20 +591,21 @@ int nsk_dt_estimate(nsk_ctx* c, double cfl, double* dt_out) {
     *dt_out = cfl * dt;
     return NSK_OK;
   }
+  // Sec. 3.1 bounds: convective, viscous momentum, and the equation for c,
+  // whose diffusion rate (2N+1)^2 sum_d (kappa/beta)/h_d^2 and relaxation
+  // source rate alpha/beta are both real and negative and so add against the
+  // real-axis stability limit z_R of the Runge-Kutta scheme
   const double lam_c = h[12];
-  double lam_v = 0.0;
-  const double lv = std::fmax(c->par.eps, c->par.kappa / c->par.beta);
-  // viscous bound: max over elements of sum_d lv / h_d^2 (widths are per
-  // direction index, so the maximum is the sum of the per-direction maxima)
+  double s2 = 0.0;  // max over elements of sum_d 1/h_d^2 (a tensor grid: the sum of per-direction maxima)
   for (int d = 0; d < c->dim; ++d) {
     double m = 0.0;
     for (double x : c->h2[d]) m = std::fmax(m, 0.25 * x * x);
-    lam_v += lv * m;
+    s2 += m;
   }
   double dt = INFINITY;
   if (lam_c > 0.0) dt = std::fmin(dt, 1.0 / (N2 * lam_c));
-  if (lam_v > 0.0) dt = std::fmin(dt, 1.0 / (N2 * N2 * lam_v));
-  dt = std::fmin(dt, c->zR * c->par.beta / c->par.alpha);
+  if (c->par.eps > 0.0) dt = std::fmin(dt, 1.0 / (N2 * N2 * c->par.eps * s2));
+  dt = std::fmin(dt, 1.0 / (N2 * N2 * (c->par.kappa / c->par.beta) * s2 + c->par.alpha / (c->par.beta * c->zR)));
   *dt_out = cfl * dt;
   return NSK_OK;
 }

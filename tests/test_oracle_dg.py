@@ -156,20 +156,95 @@ def test_mass_conservation_1d_config(O):
 
 
 def test_dt_rule_components(O):
-    """The time step is CFL times the smallest of the convective, viscous and
-    relaxation-source bounds; at the 1D workload the source bound
-    |z_R| beta / alpha is the active one."""
+    """The time step is CFL times the smallest of the convective bound, the
+    viscous momentum bound and the bound of the equation for c, in which the
+    diffusion rate (2N+1)^2 sum_d (kappa/beta)/h_d^2 and the source rate
+    alpha/(beta |z_R|) add.  At the 1D workload the c bound is the active one."""
     m, U = I.slab_1d()
     P = _prob(O, m, alpha=500.0, beta=1e-3, eps=1e-3, kappa=1e-5)
     zr = O.lsrk_real_limit()
-    assert O.dt(P, U, 0.5) == pytest.approx(0.5 * zr * 1e-3 / 500.0, rel=1e-14)
-    # switch to a convective limit: tiny alpha/beta ratio impossible without
-    # changing hyperbolicity; use large beta instead (source bound grows)
+    rate_c = 7 ** 2 * (1e-5 / 1e-3) * 64 ** 2 + 500.0 / (1e-3 * zr)
+    assert O.dt(P, U, 0.5) == pytest.approx(0.5 / rate_c, rel=1e-14)
+    # a convective limit: a large beta removes the stiffness of the c equation
     P2 = _prob(O, m, alpha=500.0, beta=10.0, eps=1e-3, kappa=1e-5)
     rho = U[0]
     a = np.sqrt(np.array([O.dpressure(T, r) for r in rho.ravel()]) + 500.0 * rho.ravel())
     lam = (np.abs(U[1] / U[0]).ravel() + a).max() * 64
     assert O.dt(P2, U, 0.5) == pytest.approx(0.5 / (7 * lam), rel=1e-12)
+    # a viscous momentum limit: large eps, weak c stiffness
+    P3 = _prob(O, m, alpha=500.0, beta=10.0, eps=5.0, kappa=1e-5)
+    assert O.dt(P3, U, 0.5) == pytest.approx(0.5 / (49 * 5.0 * 64 ** 2), rel=1e-12)
+
+
+def _jacobian(O, P, U0, h=1e-7):
+    u = U0.ravel().copy()
+    J = np.zeros((u.size, u.size))
+    for k in range(u.size):
+        up, um = u.copy(), u.copy()
+        up[k] += h
+        um[k] -= h
+        J[:, k] = (O.rhs(P, up.reshape(U0.shape)).ravel() - O.rhs(P, um.reshape(U0.shape)).ravel()) / (2 * h)
+    return J
+
+
+def _max_amplification(O, z):
+    """Largest |R(z)| / max(1, exp(Re z)) over the eigenvalues: above 1, a
+    numerical mode grows (or a physically growing mode grows too fast)."""
+    g = O.lsrk_stability_poly()
+    return (np.abs(np.polyval(g[::-1], z)) / np.maximum(1.0, np.exp(z.real))).max()
+
+
+# (dim, elements per direction, N, alpha, kappa, state); beta = eps = 1e-3
+DT_CASES = {
+    # source and c-diffusion bounds equal to 0.5% (h = 1/73, N = 4, alpha = 200)
+    "coinciding_liquid": (1, 73, 4, 200.0, 1e-4, "liquid"),
+    "coinciding_vapour": (1, 73, 4, 200.0, 1e-4, "vapour"),
+    "diffusion_limited": (1, 120, 4, 200.0, 1e-4, "liquid"),
+    "source_limited_1d_workload": (1, 64, 3, 500.0, 1e-5, "liquid"),
+    "source_limited_2d": (2, 6, 3, 200.0, 1e-4, "liquid"),
+    "interface_moving": (1, 40, 4, 200.0, 1e-4, "interface"),
+}
+
+
+def _dt_case(O, name):
+    dim, E, N, alpha, kappa, state = DT_CASES[name]
+    P = O.Problem(dim=dim, N=N, nel=(E, E if dim > 1 else 1, 1), alpha=alpha, beta=1e-3, eps=1e-3, kappa=kappa)
+    U = np.zeros(P.shape())
+    if state == "interface":
+        X = O.node_coords(P)[0]
+        w = 2 * np.sqrt(kappa)
+        rho = 0.32 + 0.5 * (1.81 - 0.32) * (np.tanh((X - 0.3) / w) - np.tanh((X - 0.7) / w))
+        U[0] = rho
+        U[1] = rho * 0.3 * np.sin(2 * np.pi * X)
+        U[-1] = rho
+    else:
+        U[0] = 1.8 if state == "liquid" else 0.32
+        U[-1] = U[0]
+    return P, U
+
+
+@pytest.mark.parametrize("case", sorted(DT_CASES))
+def test_dt_rule_inside_stability_region(O, case):
+    """Every eigenvalue z = dt lambda of the linearised model II operator
+    satisfies |R(z)| <= max(1, exp(Re z)) for the LSRK4(5) polynomial R at CFL
+    0.85 of the rule (the interface state has a physically growing mode); the
+    workloads run at CFL 0.5."""
+    P, U = _dt_case(O, case)
+    lam = np.linalg.eigvals(_jacobian(O, P, U))
+    assert _max_amplification(O, O.dt(P, U, 0.85) * lam) <= 1 + 1e-9
+
+
+def test_dt_separate_bounds_leave_stability_region(O):
+    """Where the c-diffusion and source bounds coincide, the smallest of the
+    separate bounds at CFL 0.5 gives a step outside the stability region, so
+    the rule must add the two rates (a mistake the test above would not see
+    at the source-limited workloads)."""
+    P, U = _dt_case(O, "coinciding_liquid")
+    lam = np.linalg.eigvals(_jacobian(O, P, U))
+    h, N2, zr = 1.0 / 73, 9.0, O.lsrk_real_limit()
+    dt_sep = min(1.0 / (N2 ** 2 * max(P.eps, P.kappa / P.beta) / h ** 2), zr * P.beta / P.alpha)
+    assert _max_amplification(O, 0.5 * dt_sep * lam) > 1.5
+    assert _max_amplification(O, O.dt(P, U, 0.5) * lam) <= 1 + 1e-9
 
 
 # --------------------------------------------------------------------------
