@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 from test_oracle_closure import NPARAM, routing_network
+from tolerances import record
 
 pytestmark = pytest.mark.gpu
 
@@ -58,9 +59,19 @@ def test_mlp_forward_matches_oracle(O, gpu, n):
     Yg = net.forward(torch.from_numpy(X).cuda()).cpu().numpy().astype(np.float64)
     Yc = O.mlp_forward(wb, X.astype(np.float64))
     err = np.abs(Yg - Yc)
+    record("forward, max error / max output", err.max() / np.abs(Yc).max(), 1e-2)
     assert err.max() <= 1e-2 * np.abs(Yc).max()
-    if n >= 256:  # the RMS bound is a statistical one
-        assert np.sqrt((err ** 2).mean()) <= 4e-3 * np.sqrt((Yc ** 2).mean())
+    # The RMS bound is statistical: each output's error is a sum of about 64
+    # independent BF16 rounding errors, and the 4e-3 ratio of error RMS to
+    # output RMS holds as an average over many outputs.  With 1 or 63 samples
+    # the sample RMS is that of one or a few outputs, where a single output
+    # formed as a small difference of larger terms (up to 3e-2 of the largest
+    # output in an FP64 emulation of the rounding) dominates it; the max bound
+    # above is the per-output statement that covers them.
+    if n >= 256:
+        rms = np.sqrt((err ** 2).mean()) / np.sqrt((Yc ** 2).mean())
+        record("forward, RMS error / RMS output", rms, 4e-3)
+        assert rms <= 4e-3
 
 
 def test_loss_grad_matches_oracle(O, gpu):
@@ -84,6 +95,7 @@ def test_loss_grad_matches_oracle(O, gpu):
     lc, gc = O.mlp_loss_grad(wb, X[idx].astype(np.float64), Tq)
     assert float(loss.item()) == pytest.approx(lc, rel=1e-2)
     g = grad.cpu().numpy().astype(np.float64)
+    record("gradient, relative L2", np.linalg.norm(g - gc) / np.linalg.norm(gc), 2e-2)
     assert np.linalg.norm(g - gc) <= 2e-2 * np.linalg.norm(gc)
     # the same call twice gives the same bits (fixed-order reduction)
     loss2, grad2 = net.loss_grad(Xd, Td, torch.from_numpy(idx).cuda(), tscale=q)

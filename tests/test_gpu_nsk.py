@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from paper_1912_12059_amd import inputs as I
-from tolerances import RHS_ULPS, rhs_err_ulps, term_scales_nsk
+from tolerances import RHS_ULPS, record, rhs_err_ulps, term_scales_nsk
 
 pytestmark = pytest.mark.gpu
 
@@ -46,6 +46,7 @@ def _relerr_per_var(a, b):
     for v in range(b.shape[0]):
         scale = np.max(np.abs(b[v]))
         out.append(np.max(np.abs(a[v] - b[v])) / (scale if scale > 0 else 1.0))
+    record("trajectory, relative error per variable", max(out), TRAJ_TOL)
     return max(out)
 
 

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_1912_12059_amd import inputs as I
-from tolerances import RHS_ULPS, rhs_err_ulps, term_scales
+from tolerances import RHS_ULPS, record, rhs_err_ulps, term_scales
 
 pytestmark = pytest.mark.gpu
 
@@ -37,12 +37,15 @@ def _solver(gpu, m, **kw):
                       hi=tuple(m.hi) + (1.0,) * 3, xbreaks=m.xbreaks, **kw)
 
 
-def _relerr_per_var(a, b):
+def _relerr_per_var(a, b, scale=None):
+    """max over variables of max|a_v - b_v| / max|b_v| (or / scale[v]),
+    recorded against TRAJ_TOL."""
     a = np.asarray(a).reshape(b.shape)
     out = []
     for v in range(b.shape[0]):
-        scale = np.max(np.abs(b[v]))
-        out.append(np.max(np.abs(a[v] - b[v])) / (scale if scale > 0 else 1.0))
+        sc = np.max(np.abs(b[v])) if scale is None else scale[v]
+        out.append(np.max(np.abs(a[v] - b[v])) / (sc if sc > 0 else 1.0))
+    record("trajectory, relative error per variable", max(out), TRAJ_TOL)
     return max(out)
 
 
@@ -292,3 +295,50 @@ def test_full_size_3d_sampled(O, gpu):
         ulps = rhs_err_ulps(got, ref, scales)
         assert ulps <= RHS_ULPS, (e, ulps)
     s.close()
+
+
+def _patch(U, nel, e, r):
+    """The (2r+1)^3-element block of U centred on element e (periodic)."""
+    ex, ey, ez = e % nel[0], (e // nel[0]) % nel[1], e // (nel[0] * nel[1])
+    ix = [(ex + k) % nel[0] for k in range(-r, r + 1)]
+    iy = [(ey + k) % nel[1] for k in range(-r, r + 1)]
+    iz = [(ez + k) % nel[2] for k in range(-r, r + 1)]
+    ids = [x + nel[0] * (y + nel[1] * z) for z in iz for y in iy for x in ix]
+    return U[:, ids, :]
+
+
+def test_full_size_3d_one_step_sampled(O, gpu):
+    """One LSRK4(5) step of the 96x48x48, N=4 collision (27.6M nodes) on the
+    GPU in the launch shape the benchmark times (autotuned), FP64.  A stage
+    reaches elements at most two away (lifting, then the neighbours' lifted
+    gradients), so the five stages of a step reach ten: sampled elements are
+    recomputed by the oracle on the periodic 23x23x23-element block centred on
+    each, whose wrapped boundary is eleven elements away.  Errors are relative
+    to each variable's largest magnitude on the whole mesh after the step."""
+    import torch
+
+    nel = (96, 48, 48)
+    r = 11
+    m, U = I.collision_3d(nel=nel, N=4, We=100.0)
+    kw = dict(PHYS, alpha=1000.0)
+    s = _solver(gpu, m, **kw)
+    s.set_state(torch.from_numpy(U.reshape(-1)).to("cuda:0"))
+    gpu.nsk_autotune(s.ctx, 2)
+    dt = s.dt_estimate(0.5)
+    s.rk_step(dt, 1)
+    got = s.get_state()
+    scale = [float(torch.max(torch.abs(got[v]))) for v in range(5)]
+    got = got.cpu().numpy()
+    s.close()
+    g = np.random.Generator(np.random.PCG64(78))
+    rho = U[0]
+    inter = np.where((rho.max(axis=1) > 1.0) & (rho.min(axis=1) < 1.0))[0]
+    samples = list(g.choice(inter, 2, replace=False)) + list(g.integers(0, m.nelem, 1))
+    h = [(m.hi[d] - m.lo[d]) / nel[d] for d in range(3)]
+    w = 2 * r + 1
+    P = O.Problem(dim=3, N=4, nel=(w, w, w), lo=(0, 0, 0), hi=(w * h[0], w * h[1], w * h[2]), **kw)
+    centre = r + w * (r + w * r)
+    for e in samples:
+        ref = O.run(P, _patch(U, nel, e, r), dt, 1)[:, centre, :]
+        err = _relerr_per_var(got[:, e, :], ref, scale)
+        assert err <= TRAJ_TOL, (e, err)
