@@ -103,20 +103,94 @@ def sample_block(U, nel, block):
     return np.ascontiguousarray(U[:, idx, :])
 
 
+_ORACLE = None
+
+
+def oracle():
+    """The CPU oracle for the timing legs: its sources built -O3
+    -march=native for this host (the checker the tests load is a portable
+    -O2 build of the same sources)."""
+    global _ORACLE
+    if _ORACLE is None:
+        import tempfile
+
+        from oracle import oracle as O
+
+        path = os.path.join(tempfile.mkdtemp(prefix="nsk_oracle_"), "liboracle_native.so")
+        O.build(path=path, native=True)
+        O.use(path)
+        _ORACLE = O
+    return _ORACLE
+
+
+def host_record() -> dict:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "omp_num_threads": os.environ.get("OMP_NUM_THREADS"), "cpu_model": model,
+            "oracle_build": "gcc -O3 -march=native -fopenmp (built on this host)"}
+
+
+def _oracle_rate_one_thread(P_kw: dict, sample, dt: float, steps: int) -> float | None:
+    """DOF-stage/s of the oracle on one thread: the same sample timed in a
+    child process started with OMP_NUM_THREADS=1."""
+    import subprocess
+    import tempfile
+
+    import numpy as np
+
+    O = oracle()
+    d = tempfile.mkdtemp(prefix="nsk_cpu1_")
+    np.save(os.path.join(d, "U.npy"), sample)
+    with open(os.path.join(d, "job.json"), "w") as fh:
+        json.dump({"P": P_kw, "dt": dt, "steps": steps, "lib": O._lib._name}, fh)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-one-thread", d], env=env,
+                           capture_output=True, text=True, timeout=300)
+        el = float(json.loads(r.stdout.strip().splitlines()[-1])["seconds"])
+    except Exception:  # the 1-thread figure is informative only
+        return None
+    return sample.shape[1] * sample.shape[2] * 5 * steps / el
+
+
+def cpu_one_thread_child(d: str) -> int:
+    import numpy as np
+
+    from oracle import oracle as O
+
+    with open(os.path.join(d, "job.json")) as fh:
+        job = json.load(fh)
+    O.use(job["lib"])
+    P = O.Problem(**{k: (tuple(v) if isinstance(v, list) else v) for k, v in job["P"].items()})
+    U = np.load(os.path.join(d, "U.npy"))
+    t0 = time.perf_counter()
+    O.run(P, U, job["dt"], job["steps"])
+    print(json.dumps({"seconds": time.perf_counter() - t0}))
+    return 0
+
+
 def cpu_baseline(name: str, sample, sub, budget_s: float = 20.0):
     """Time the CPU oracle (as it stands) on a bounded sample: a block of
     elements cut out of the same initial state, treated as a periodic box with
     the same element size, degree and physics; full LSRK4(5) steps; rate in
     DOF-stage updates per second."""
-    from oracle import oracle as O
+    O = oracle()
 
     w = WORKLOADS[name]
     dim = w["dim"]
     h = [(w["hi"][d] - w["lo"][d]) / w["nel"][d] for d in range(dim)]
     nel3 = tuple(sub) + (1,) * (3 - dim)
     hi3 = tuple(sub[d] * h[d] for d in range(dim)) + (1.0,) * (3 - dim)
-    P = O.Problem(dim=dim, N=w["N"], nel=nel3, lo=(0, 0, 0), hi=hi3, alpha=w["alpha"], beta=1e-3, eps=1e-3,
-                  kappa=1e-5)
+    P_kw = dict(dim=dim, N=w["N"], nel=nel3, lo=(0, 0, 0), hi=hi3, alpha=w["alpha"], beta=1e-3, eps=1e-3,
+                kappa=1e-5)
+    P = O.Problem(**P_kw)
     dt = O.dt(P, sample, 0.5)
     t0 = time.perf_counter()
     O.run(P, sample, dt, 1)
@@ -127,6 +201,8 @@ def cpu_baseline(name: str, sample, sub, budget_s: float = 20.0):
     el = time.perf_counter() - t0
     dofs = sample.shape[1] * sample.shape[2]
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # one thread: about 10 s of work
+    steps1 = int(max(1, min(steps, 10.0 // max(first * threads, 1e-3))))
     return {
         "value": dofs * 5 * steps / el,
         "unit": "DOF-stage/s",
@@ -134,6 +210,9 @@ def cpu_baseline(name: str, sample, sub, budget_s: float = 20.0):
         "kind": "oracle",
         "sample": f"{'x'.join(map(str, sub))}-element block of the same initial state (periodic, same "
                   f"element size, N={w['N']} and physics), {steps} LSRK4(5) steps in {el:.1f} s",
+        "value_one_thread": _oracle_rate_one_thread(P_kw, sample, dt, steps1),
+        "one_thread_steps": steps1,
+        "host": host_record(),
     }
 
 
@@ -585,6 +664,145 @@ def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20):
     }
 
 
+def _timed_steps(s, dt: float, steps: int) -> float:
+    """Milliseconds of `steps` steps on the solver's stream (HIP events)."""
+    import torch
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s.stream)
+    s.rk_step(dt, steps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def run_small_configs(nsk, with_oracle: bool = True) -> dict:
+    """The 1D slab workload (64 elements, N = 3, alpha = 500: a launch-latency
+    case, 256 nodes) in microseconds per step over its 2000 steps, with the
+    steps replayed as a captured graph (non-null stream) and launched stage
+    by stage; and the 2D droplet workload (96^2, N = 4, 230,400 nodes) rate
+    at alpha = 500 and 2000 over 200 steps.  The oracle is timed beside each:
+    the full 2000 1D steps, 40 steps in 2D."""
+    import torch
+
+    from paper_1912_12059_amd import inputs as I
+
+    out = {}
+    m, U = I.slab_1d()
+    res = {"workload": "1d-slab 64 N=3 alpha=500 beta=1e-3 eps=1e-3 kappa=1e-5, 2000 steps", "dofs": 256}
+    for name, stream in (("graph", torch.cuda.Stream()), ("stagewise", None)):
+        s = nsk.Solver(dim=1, N=3, nel=(64,), alpha=500.0, beta=1e-3, eps=1e-3, kappa=1e-5, stream=stream)
+        s.set_state(U)
+        dt = s.dt_estimate(0.5)
+        _timed_steps(s, dt, 200)
+        s.set_state(U)
+        ms = _timed_steps(s, dt, 2000)
+        res[f"us_per_step_{name}"] = 1e3 * ms / 2000
+        res["dt"] = dt
+        s.close()
+    res["value"] = 256 * 5 * 1e3 / res["us_per_step_graph"]
+    res["unit"] = "DOF-stage/s"
+    if with_oracle:
+        O = oracle()
+        P = O.Problem(dim=1, N=3, nel=(64, 1, 1), alpha=500.0, beta=1e-3, eps=1e-3, kappa=1e-5)
+        t0 = time.perf_counter()
+        O.run(P, U, res["dt"], 2000)
+        el = time.perf_counter() - t0
+        res["oracle"] = {"us_per_step": 1e6 * el / 2000, "value": 256 * 5 * 2000 / el,
+                         "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))}
+    out["1d_slab"] = res
+    m, U = I.droplets_2d()
+    U0 = torch.from_numpy(U.reshape(-1)).to("cuda:0")
+    dofs = m.nelem * m.nnode
+    for alpha in (500.0, 2000.0):
+        s = nsk.Solver(dim=2, N=4, nel=(96, 96), alpha=alpha, beta=1e-3, eps=1e-3, kappa=1e-5,
+                       stream=torch.cuda.Stream())
+        s.set_state(U0)
+        dt = s.dt_estimate(0.5)
+        variant, order, _ = nsk.nsk_autotune(s.ctx, 3)
+        _timed_steps(s, dt, 20)
+        s.set_state(U0)
+        ms = _timed_steps(s, dt, 200)
+        r = {"workload": f"2d-droplets 96x96 N=4 alpha={alpha:g} beta=1e-3 eps=1e-3 kappa=1e-5", "dofs": dofs,
+             "value": dofs * 5 * 200 / (ms * 1e-3), "unit": "DOF-stage/s", "ms_per_step": ms / 200, "dt": dt,
+             "tile": {"variant": variant, "order": order}}
+        s.close()
+        if with_oracle:
+            O = oracle()
+            P = O.Problem(dim=2, N=4, nel=(96, 96, 1), alpha=alpha, beta=1e-3, eps=1e-3, kappa=1e-5)
+            t0 = time.perf_counter()
+            O.run(P, U, dt, 40)
+            el = time.perf_counter() - t0
+            r["oracle"] = {"value": dofs * 5 * 40 / el, "steps": 40,
+                           "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))}
+        out[f"2d_droplets_alpha{int(alpha)}"] = r
+    return out
+
+
+def _long_run(nsk, s, U0, steps: int, chunk: int) -> dict:
+    """Steps in chunks with diagnostics after each, stopping at the first
+    non-physical state; returns how far the run got and its rate."""
+    s.set_state(U0)
+    dt = s.dt_estimate(0.5)
+    done, ms = 0, 0.0
+    while done < steps:
+        k = min(chunk, steps - done)
+        ms += _timed_steps(s, dt, k)
+        done += k
+        d = s.diagnostics()
+        if d["status"] != 0:
+            return {"finite_steps": done - k, "nonphysical_by_step": done, "t_finite": (done - k) * dt, "dt": dt}
+    return {"finite_steps": done, "t_finite": done * dt, "dt": dt, "ms_per_step": ms / done,
+            "rho_range": [d["rho_min"], d["rho_max"]], "e_kin": d["e_kin"]}
+
+
+def run_long_runs(nsk, U0_3d) -> dict:
+    """Run lengths the workloads reach.  2D droplets (96^2, N = 4): the
+    stated 20k steps at alpha = 500 and 2000 as configured (kappa = 1e-5, no
+    shock capturing), with FV sub-cells at kappa = 1e-5 (indicator threshold
+    -9) and with kappa = 1e-4 (the equilibrium interface width 2 sqrt(kappa)
+    equal to the initial 0.02).  3D collision (96x48x48, N = 4, kappa =
+    1e-5): FP64 and mixed over 2000 steps, and the relative L2 of rho between
+    them at the end.  Diagnostics every 1000 (2D) or 500 (3D) steps; a run
+    stops at its first non-physical state."""
+    import torch
+
+    from paper_1912_12059_amd import inputs as I
+
+    out = {}
+    m, U = I.droplets_2d()
+    U0 = torch.from_numpy(U.reshape(-1)).to("cuda:0")
+    for label, kappa, sc in (("kappa1e-5", 1e-5, None), ("kappa1e-5_subcells", 1e-5, -9.0),
+                             ("kappa1e-4", 1e-4, None)):
+        for alpha in (500.0, 2000.0):
+            kw = {} if sc is None else dict(subcell=1, subcell_threshold=sc)
+            s = nsk.Solver(dim=2, N=4, nel=(96, 96), alpha=alpha, beta=1e-3, eps=1e-3, kappa=kappa,
+                           stream=torch.cuda.Stream(), **kw)
+            r = _long_run(nsk, s, U0, 20000, 1000)
+            s.close()
+            if "ms_per_step" in r:
+                r["value"] = m.nelem * m.nnode * 5 / (r["ms_per_step"] * 1e-3)
+            out[f"2d_droplets_{label}_alpha{int(alpha)}"] = r
+            print(f"[bench] long run 2D {label} alpha={alpha:g}: {r['finite_steps']} finite steps", file=sys.stderr,
+                  flush=True)
+    del U0
+    fin = {}
+    for prec in (0, 1):
+        s = nsk.Solver(dim=3, N=4, nel=(96, 48, 48), lo=(0, 0, 0), hi=(2, 1, 1), alpha=1000.0, beta=1e-3, eps=1e-3,
+                       kappa=1e-5, precision=prec, stream=torch.cuda.Stream())
+        r = _long_run(nsk, s, U0_3d, 2000, 500)
+        if r["finite_steps"] == 2000:
+            fin[prec] = s.get_state()[0].reshape(-1).clone()
+        s.close()
+        out[f"3d_collision_{'fp64' if prec == 0 else 'mixed'}"] = r
+        print(f"[bench] long run 3D precision={prec}: {r['finite_steps']} finite steps", file=sys.stderr, flush=True)
+    if len(fin) == 2:
+        out["3d_collision_mixed_vs_fp64_l2_rel_rho"] = float(
+            torch.linalg.vector_norm(fin[1] - fin[0]) / torch.linalg.vector_norm(fin[0]))
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -606,11 +824,18 @@ def main() -> int:
                     help="run only the batched collision sweep and the 64 small collisions (prints their blocks)")
     ap.add_argument("--only-nsk", action="store_true",
                     help="run only the original NSK form on the workload (prints its block)")
+    ap.add_argument("--no-long-runs", action="store_true", help="skip the run-length form")
+    ap.add_argument("--only-long-runs", action="store_true", help="run only the run-length form")
+    ap.add_argument("--only-small-configs", action="store_true",
+                    help="run only the 1D latency and 2D rate form (with the oracle beside them)")
+    ap.add_argument("--cpu-one-thread", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="auto", help="auto (autotuner) or 'variant,order', e.g. 0,4")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (to scale HBM byte counters)")
     args = ap.parse_args()
+    if args.cpu_one_thread:
+        return cpu_one_thread_child(args.cpu_one_thread)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build", file=sys.stderr)
         return 2
@@ -636,6 +861,9 @@ def main() -> int:
     if args.only_batched:
         print(json.dumps({"batched": run_batched(nsk, 10, 2), "batched_small": run_batched_small(nsk)}))
         return 0
+    if args.only_small_configs:
+        print(json.dumps({"configs_small": run_small_configs(nsk, not args.no_cpu_baseline)}))
+        return 0
     w = WORKLOADS[args.workload]
     print(f"[bench] building {args.workload} state", file=sys.stderr, flush=True)
     m, U = build_state(args.workload)
@@ -652,6 +880,10 @@ def main() -> int:
     if args.only_implicit:
         del U
         print(json.dumps({"implicit_esdirk": run_implicit_form(nsk, m, U0, w, (100,), reference=False)}))
+        return 0
+    if args.only_long_runs:
+        del U
+        print(json.dumps({"long_runs": run_long_runs(nsk, U0)}))
         return 0
     if args.only_nsk:
         del U
@@ -770,6 +1002,10 @@ def main() -> int:
         out["forms"]["batched_small"] = run_batched_small(nsk)
     if not args.no_forms and not args.no_closure and args.workload == "3d-collision":
         out.setdefault("forms", {})["closure"] = run_closure_form(nsk)
+    if not args.no_forms and args.workload == "3d-collision":
+        out.setdefault("forms", {})["configs_small"] = run_small_configs(nsk, not args.no_cpu_baseline)
+        if not args.no_long_runs:
+            out["forms"]["long_runs"] = run_long_runs(nsk, U0)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, sample, sub)

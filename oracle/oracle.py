@@ -22,16 +22,20 @@ SOURCES = ["basis.c", "thermo.c", "lsrk.c", "dg_weak.c", "dg_strong.c", "nsk_ori
            "closure.c"]
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, OpenMP over elements)."""
-    if not force and os.path.exists(LIB_PATH):
-        return LIB_PATH
+def build(force: bool = True, path: str = LIB_PATH, native: bool = False) -> str:
+    """Compile the oracle with gcc (OpenMP over elements).  The checker the
+    tests load is built -O2 for any x86-64 host, since the library travels
+    between machines; native=True builds an -O3 -march=native copy for the
+    host it is built on (the CPU baseline's timing build, same sources)."""
+    if not force and os.path.exists(path):
+        return path
     srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
-    tmp = LIB_PATH + ".tmp"
-    cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp] + srcs + ["-lm"]
+    tmp = path + ".tmp"
+    opt = ["-O3", "-march=native"] if native else ["-O2"]
+    cmd = ["gcc", "-std=c11"] + opt + ["-fopenmp", "-fPIC", "-shared", "-o", tmp] + srcs + ["-lm"]
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+    os.replace(tmp, path)
+    return path
 
 
 _lib = None
@@ -45,6 +49,16 @@ def lib():
         _lib = C.CDLL(LIB_PATH)
         _declare(_lib)
     return _lib
+
+
+def use(path: str) -> None:
+    """Load the oracle from another build of the same sources (before any
+    other call of this module)."""
+    global _lib
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    _lib = C.CDLL(path)
+    _declare(_lib)
 
 
 class _Basis(C.Structure):

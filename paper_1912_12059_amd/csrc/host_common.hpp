@@ -167,6 +167,11 @@ struct nsk_ctx {
   // optional kernel timing
   std::vector<hipEvent_t> events;  // 4 per timed stage
   int timed = 0;                   // stages recorded since the last read
+  // two Runge-Kutta steps captured on the bound stream, and what the
+  // captured launches depend on (a different key re-captures)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<unsigned char> graph_key;
 };
 
 namespace {

@@ -289,6 +289,73 @@ bool variants_coincide(int dim, int N) {
   return dim == 1 ? variants_coincide_dim<1>(N) : dim == 2 ? variants_coincide_dim<2>(N) : variants_coincide_dim<3>(N);
 }
 
+// nsteps Runge-Kutta steps enqueued stage by stage on the bound stream
+int enqueue_steps(nsk_ctx* c, double dt, int nsteps) {
+  for (int step = 0; step < nsteps; ++step) {
+    for (int s = 0; s < 5; ++s) {
+      StageArgs st{kRkA[s], kRkB[s], dt, 1};
+      c->cl_stage = s;
+      int rc = dispatch(c, 0, state_buf(c, c->cur), state_buf(c, 1 - c->cur), c->dU, st);
+      c->cl_stage = -1;
+      if (rc) return rc;
+      c->cur = 1 - c->cur;
+    }
+  }
+  return NSK_OK;
+}
+
+void drop_step_graph(nsk_ctx* c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+  c->graph_key.clear();
+}
+
+// Everything the launches of a step take from the context: the step size,
+// the state buffer it starts from, the bound memory and stream, the launch
+// shape, the parameters and the closure network.
+std::vector<unsigned char> step_graph_key(const nsk_ctx* c, double dt) {
+  std::vector<unsigned char> k;
+  auto put = [&k](const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    k.insert(k.end(), b, b + n);
+  };
+  put(&dt, sizeof(dt));
+  put(&c->cur, sizeof(c->cur));
+  put(&c->U, sizeof(c->U));
+  put(&c->dU, sizeof(c->dU));
+  put(&c->work, sizeof(c->work));
+  put(&c->stream, sizeof(c->stream));
+  put(&c->tile, sizeof(c->tile));
+  put(&c->order, sizeof(c->order));
+  put(&c->par, sizeof(c->par));
+  put(&c->cl_w, sizeof(c->cl_w));
+  put(c->cl_norm, sizeof(c->cl_norm));
+  put(&c->cl_every_stage, sizeof(c->cl_every_stage));
+  return k;
+}
+
+int build_step_graph(nsk_ctx* c, double dt) {
+  drop_step_graph(c);
+  if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return NSK_EHIP;
+  const int cur0 = c->cur;
+  const int rc = enqueue_steps(c, dt, 2);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->stream, &g);
+  c->cur = cur0;  // capturing ran nothing
+  if (rc || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc ? rc : NSK_EHIP;
+  }
+  c->graph = g;
+  if (hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    drop_step_graph(c);
+    return NSK_EHIP;
+  }
+  return NSK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -412,6 +479,7 @@ int nsk_create(const nsk_mesh* mesh, const nsk_params* params, nsk_ctx** out) {
 void nsk_destroy(nsk_ctx* c) {
   if (!c) return;
   if (c->bound) (void)hipStreamSynchronize(c->stream);
+  drop_step_graph(c);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   delete c;
 }
@@ -526,16 +594,22 @@ int nsk_rk_step(nsk_ctx* c, double dt, int nsteps) {
   if (!c || nsteps < 0 || !(dt > 0.0) || !std::isfinite(dt)) return NSK_EINVAL;
   if (!c->bound) return NSK_EUNBOUND;
   if (c->par.closure == 1 && !c->cl_w) return NSK_EINVAL;  // closure enabled, no network set
-  for (int step = 0; step < nsteps; ++step) {
-    for (int s = 0; s < 5; ++s) {
-      StageArgs st{kRkA[s], kRkB[s], dt, 1};
-      c->cl_stage = s;
-      int rc = dispatch(c, 0, state_buf(c, c->cur), state_buf(c, 1 - c->cur), c->dU, st);
-      c->cl_stage = -1;
+  // Pairs of steps replay one captured graph (ten stages bring the state
+  // back to the buffer it started in); the null stream cannot be captured,
+  // and timed stages record events between the launches.
+  int left = nsteps;
+  if (nsteps >= 2 && c->stream != nullptr && c->events.empty()) {
+    const std::vector<unsigned char> key = step_graph_key(c, dt);
+    if (!c->graph_exec || key != c->graph_key) {
+      int rc = build_step_graph(c, dt);
       if (rc) return rc;
-      c->cur = 1 - c->cur;
+      c->graph_key = key;
     }
+    for (; left >= 2; left -= 2)
+      if (hipGraphLaunch(c->graph_exec, c->stream) != hipSuccess) return NSK_EHIP;
   }
+  int rc = enqueue_steps(c, dt, left);
+  if (rc) return rc;
   if (c->cur == 1) {
     if (hipMemcpyAsync(c->U, state_buf(c, 1), sizeof(double) * nsk_state_size(c), hipMemcpyDeviceToDevice,
                        c->stream) != hipSuccess)

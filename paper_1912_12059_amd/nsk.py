@@ -475,7 +475,18 @@ class Solver:
         self._work_ptr = (base + 255) // 256 * 256
         if self.stream is None:
             self.stream = torch.cuda.current_stream(dev)
+        self._after_torch()  # the zero fills above run on torch's current stream
         nsk_bind(self.ctx, self.U.data_ptr(), self.dU.data_ptr(), self._work_ptr, self.stream.cuda_stream)
+
+    def _after_torch(self) -> None:
+        """Order the bound stream after the work torch has enqueued on its
+        current stream (allocation fills, host copies of inputs): torch's side
+        streams do not synchronise with the null stream by themselves."""
+        import torch
+
+        cur = torch.cuda.current_stream(self.U.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream.wait_stream(cur)
 
     @property
     def shape(self):
@@ -487,14 +498,15 @@ class Solver:
         t = torch.as_tensor(U, dtype=torch.float64).reshape(-1).to(self.U.device).contiguous()
         if t.numel() != self.U.numel():
             raise ValueError("state size mismatch")
-        with torch.cuda.stream(self.stream):
-            nsk_set_state(self.ctx, t.data_ptr())
+        self._after_torch()
+        nsk_set_state(self.ctx, t.data_ptr())
         self.stream.synchronize()
 
     def get_state(self):
         import torch
 
         out = torch.empty_like(self.U)
+        self._after_torch()
         nsk_get_state(self.ctx, out.data_ptr())
         self.stream.synchronize()
         return out.reshape(self.shape)
@@ -504,6 +516,7 @@ class Solver:
 
         t = torch.as_tensor(U, dtype=torch.float64).reshape(-1).to(self.U.device).contiguous()
         R = torch.empty_like(t)
+        self._after_torch()
         nsk_rhs(self.ctx, t.data_ptr(), R.data_ptr(), 0.0)
         self.stream.synchronize()
         return R.reshape(self.shape)
@@ -519,6 +532,7 @@ class Solver:
         import torch
 
         f = torch.zeros(self.nelem, dtype=torch.int32, device=self.U.device)
+        self._after_torch()
         nsk_subcell_flags(self.ctx, f.data_ptr())
         self.stream.synchronize()
         return f.cpu().numpy().astype(bool)
@@ -534,6 +548,7 @@ class Solver:
             self._iwork = None
             self._iwork = torch.empty(need + 256, dtype=torch.uint8, device=self.U.device)
         ptr = (self._iwork.data_ptr() + 255) // 256 * 256
+        self._after_torch()
         return nsk_esdirk_step(self.ctx, ptr, dt, nsteps, o)
 
     def diagnostics(self) -> dict:

@@ -1,0 +1,70 @@
+"""Single-mesh steps replayed as a captured HIP graph (pairs of steps on a
+non-null bound stream) against the same steps launched one by one (the null
+stream cannot be captured): bitwise equal after every call, with eager torch
+work and synchronisations between the replays, across a change of step size
+and of launch shape (each re-captures)."""
+import numpy as np
+import pytest
+
+from paper_1912_12059_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+PHYS = dict(T=0.85, eps=1e-3, kappa=1e-5, alpha=1000.0, beta=1e-3)
+
+
+def _pair(gpu, m, **kw):
+    import torch
+
+    base = dict(dim=m.dim, N=m.N, nel=tuple(m.nel), lo=tuple(m.lo) + (0.0,) * 3, hi=tuple(m.hi) + (1.0,) * 3)
+    graphed = gpu.Solver(stream=torch.cuda.Stream(), **base, **kw)
+    eager = gpu.Solver(**base, **kw)
+    assert eager.stream.cuda_stream == 0  # the null stream: launched stage by stage
+    return graphed, eager
+
+
+@pytest.mark.parametrize("dim,N,nel,prec", [(1, 3, (64,), 0), (2, 4, (9, 7), 0), (3, 4, (5, 4, 3), 0),
+                                            (3, 3, (6, 5, 4), 1)])
+def test_graph_replay_equals_eager_steps(gpu, dim, N, nel, prec):
+    import torch
+
+    m, U = I.smooth_random(dim, N, nel, seed=90 + dim)
+    g, e = _pair(gpu, m, precision=prec, **PHYS)
+    for s in (g, e):
+        s.set_state(U)
+    # 2 and 4 steps replay the graph; 3 replays it once and adds one step
+    for k, (dt, n) in enumerate(((1e-6, 2), (1e-6, 4), (1e-6, 3), (7e-7, 2), (7e-7, 5))):
+        g.rk_step(dt, n)
+        e.rk_step(dt, n)
+        a = torch.randn(1 << 16, device="cuda:0")  # eager work between replays
+        float(a.sum())
+        torch.cuda.synchronize()
+        assert torch.equal(g.get_state(), e.get_state()), k
+        if k == 2:
+            gpu.nsk_set_tile(g.ctx, 1, 2)  # a new launch shape re-captures
+    fin = g.get_state().cpu().numpy()
+    assert np.all(np.isfinite(fin)) and not np.array_equal(fin, U.reshape(fin.shape))
+    g.close()
+    e.close()
+
+
+def test_side_stream_solver_full_size_3d_mixed(gpu):
+    """A solver bound to a side stream right after torch allocates its
+    multi-GB buffers (zero-filled on torch's current stream), stepped ten
+    times as graph replays, equals the null-stream solver bitwise: the
+    binding orders its stream after torch's work."""
+    import torch
+
+    m, U = I.collision_3d(nel=(96, 48, 48), N=4, We=100.0)
+    U0 = torch.from_numpy(U.reshape(-1)).to("cuda:0")
+    del U
+    outs = []
+    for stream in (torch.cuda.Stream(), None):
+        s = gpu.Solver(dim=3, N=4, nel=(96, 48, 48), lo=(0, 0, 0), hi=(2, 1, 1), precision=1, stream=stream,
+                       **PHYS)
+        s.set_state(U0)
+        s.rk_step(s.dt_estimate(0.5), 10)
+        outs.append(s.get_state()[0].reshape(-1).clone())
+        s.close()
+        del s
+    assert bool(torch.isfinite(outs[0]).all()) and torch.equal(outs[0], outs[1])

@@ -318,6 +318,37 @@ def test_mms_design_order_hllc(O, dim, N, Es):
 
 
 # --------------------------------------------------------------------------
+# interface resolution: the limit behind the workloads' finite run lengths
+# --------------------------------------------------------------------------
+def _nonphysical_time(O, nel, kappa, tend):
+    """The 1D slab (N = 3, alpha = 500, eps = beta = 1e-3) started from the
+    equilibrium interface width 2 sqrt(kappa): the time at which a state
+    leaves (0, 3) or turns non-finite, or None if it stays physical to tend."""
+    m, U = I.slab_1d(nel=nel, N=3, width=2 * np.sqrt(kappa))
+    P = _prob(O, m, alpha=500.0, beta=1e-3, eps=1e-3, kappa=kappa)
+    dt = O.dt(P, U, 0.5)
+    t, chunk = 0.0, 200
+    while t < tend:
+        U = O.run(P, U, dt, chunk)
+        t += chunk * dt
+        if not np.all(np.isfinite(U)) or U[0].min() <= 0.0 or U[0].max() >= 3.0:
+            return t
+    return None
+
+
+def test_under_resolved_interface_goes_nonphysical(O):
+    """Without shock capturing the DG scheme keeps an interface only if its
+    width 2 sqrt(kappa) spans enough nodes (Sec. 3.2 motivates the FV
+    sub-cells by this).  With N = 3 on [0, 1], kappa = 1e-5: 64 elements put
+    1.6 mean node spacings across 2 sqrt(kappa) and the slab turns
+    non-physical before t = 0.01; 128 elements (3.2 spacings) keep it
+    physical, and so does kappa = 1e-4 on 64 elements (5.1 spacings)."""
+    assert _nonphysical_time(O, 64, 1e-5, 0.01) is not None
+    assert _nonphysical_time(O, 128, 1e-5, 0.01) is None
+    assert _nonphysical_time(O, 64, 1e-4, 0.01) is None
+
+
+# --------------------------------------------------------------------------
 # planar interface: Maxwell densities, energy decay, surface tension
 # --------------------------------------------------------------------------
 def test_planar_interface_relaxes_to_maxwell(O):
