@@ -77,6 +77,7 @@ extern "C" {
 #define NSK_EUNBOUND (-4)  /* device memory not bound yet                    */
 #define NSK_EUNSUPPORTED (-5) /* degree/dimension combination not built      */
 #define NSK_ENOCONV (-6)   /* implicit stage equations did not converge      */
+#define NSK_ESCRATCH (-7)  /* problem too large for the static scratch of nsk_rhs_noalloc */
 
 typedef struct nsk_ctx nsk_ctx;
 
@@ -168,6 +169,24 @@ int nsk_get_state(nsk_ctx* ctx, double* d_dst);
  * NSK equations of Sec. 2.2 when model = 1.  d_R must not alias d_U.  The
  * scheme is autonomous, t is unused. */
 int nsk_rhs(nsk_ctx* ctx, const double* d_U, double* d_R, double t);
+
+/* nsk_rhs for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * right-hand side of d_U into d_R, computed by the same kernels, with the
+ * lifted gradients, the geometry and the element order in a file-scope
+ * static device array of NSK_NOALLOC_SCRATCH_BYTES (128 MiB, held by every
+ * GPU the library runs on until the process ends) instead of the bound
+ * workspace.  The context need not be bound; hip_stream is a hipStream_t
+ * (NULL = default stream) on the current device.  Allocates nothing (no
+ * hipMalloc, hipFree or host-to-device copy; the geometry is written by a
+ * kernel).  Needs about 8 (FP64) or 4 (mixed) bytes times
+ * (dim(dim+1)/2 + dim) per node plus the geometry: NSK_ESCRATCH if that
+ * exceeds the array (checked before any device call); NSK_EUNSUPPORTED for
+ * non-uniform meshes (breakpoints), the learned closure, FV sub-cells and
+ * the original NSK path (model 1).  All calls on one GPU share its array:
+ * calls that overlap on one GPU (other streams, other threads) race. */
+#define NSK_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int nsk_rhs_noalloc(nsk_ctx* ctx, const double* d_U, double* d_R, void* hip_stream);
 
 /* Time-step estimate for the bound state, after the parabolic bound of
  * Sec. 3.1 with the relaxation source of Sec. 2.3 on the same equation:

@@ -134,6 +134,7 @@ struct nsk_ctx {
   nsk_mesh mesh;
   nsk_params par;
   int dim = 0, N = 0, np = 0, nn = 0, nvar = 0, ng = 0;
+  bool uniform = true;  // no breakpoints: equal elements along every direction
   int nel[3] = {1, 1, 1};
   long long E = 0, S = 0;
   std::vector<double> h2[3];  // 2/h per element index

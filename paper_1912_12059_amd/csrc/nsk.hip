@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -356,6 +357,78 @@ int build_step_graph(nsk_ctx* c, double dt) {
   return NSK_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of nsk_rhs_noalloc: element widths, element order and lifted
+// gradients, in a static device array instead of a caller's workspace.  Host
+// code reaches it only through the per-device address hipGetSymbolAddress
+// returns (the array's name is a host-side stand-in, not a device address).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[NSK_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+unsigned char* g_scratch[kMaxDevices] = {};
+
+// the array's address on the current device, looked up once per device
+int scratch_address(unsigned char** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return NSK_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return NSK_EHIP;
+    g_scratch[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch[dev];
+  return NSK_OK;
+}
+
+struct NoallocLayout {
+  size_t off_h2[3], off_order, off_G, bytes;
+};
+
+NoallocLayout noalloc_layout(const nsk_ctx* c) {
+  NoallocLayout l;
+  const size_t gsz = c->par.precision == 0 ? sizeof(double) : sizeof(float);
+  size_t off = 0;
+  for (int d = 0; d < 3; ++d) {
+    l.off_h2[d] = off;
+    off = align256(off + sizeof(double) * (size_t)c->nel[d]);
+  }
+  l.off_order = off;
+  off = align256(off + sizeof(int) * (size_t)c->E);
+  l.off_G = off;
+  off = align256(off + gsz * (size_t)c->ng * (size_t)c->S);
+  l.bytes = off;
+  return l;
+}
+
+// 2/h per element index along each direction of a uniform mesh, with the
+// host's arithmetic of nsk_create (the same bits), and the natural element
+// order
+__global__ void noalloc_geometry_kernel(double* __restrict__ h2x, double* __restrict__ h2y,
+                                        double* __restrict__ h2z, int* __restrict__ order, int dim, int nx, int ny,
+                                        int nz, double lo0, double hi0, double lo1, double hi1, double lo2,
+                                        double hi2, int E) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < E) order[i] = i;
+  const int nel[3] = {nx, ny, nz};
+  const double lo[3] = {lo0, lo1, lo2}, hi[3] = {hi0, hi1, hi2};
+  double* h2[3] = {h2x, h2y, h2z};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (i >= nel[d]) continue;
+    if (d >= dim) {
+      h2[d][i] = 1.0;
+      continue;
+    }
+    const double L = hi[d] - lo[d];
+    const double a = lo[d] + L * i / nel[d];
+    const double b = lo[d] + L * (i + 1) / nel[d];
+    h2[d][i] = 2.0 / (b - a);
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -369,6 +442,7 @@ const char* nsk_strerror(int code) {
     case NSK_EUNBOUND: return "device memory not bound";
     case NSK_EUNSUPPORTED: return "unsupported dimension/degree";
     case NSK_ENOCONV: return "implicit stage equations did not converge";
+    case NSK_ESCRATCH: return "problem too large for the static scratch of nsk_rhs_noalloc";
   }
   return "unknown error";
 }
@@ -396,6 +470,7 @@ int nsk_create(const nsk_mesh* mesh, const nsk_params* params, nsk_ctx** out) {
   c->ng = c->dim * (c->dim + 1) / 2 + c->dim;
   c->E = 1;
   for (int d = 0; d < 3; ++d) {
+    if (d < c->dim && mesh->xbreaks[d]) c->uniform = false;
     c->mesh.xbreaks[d] = nullptr;  // not kept: copied into h2 below
     if (d >= c->dim) {
       c->nel[d] = 1;
@@ -588,6 +663,47 @@ int nsk_rhs(nsk_ctx* c, const double* d_U, double* d_R, double t) {
   if (c->par.closure == 1 && !c->cl_w) return NSK_EINVAL;  // closure enabled, no network set
   StageArgs st{0.0, 0.0, 0.0, 0};
   return dispatch(c, 0, d_U, d_R, nullptr, st);
+}
+
+int nsk_rhs_noalloc(nsk_ctx* c, const double* d_U, double* d_R, void* hip_stream) {
+  if (!c || !d_U || !d_R || d_U == d_R) return NSK_EINVAL;
+  if (c->par.model != 0 || c->par.closure != 0 || c->par.subcell != 0 || !c->uniform) return NSK_EUNSUPPORTED;
+  const NoallocLayout l = noalloc_layout(c);
+  if (l.bytes > NSK_NOALLOC_SCRATCH_BYTES) return NSK_ESCRATCH;
+  unsigned char* base = nullptr;
+  int rc = scratch_address(&base);
+  if (rc) return rc;
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  const int span = (int)std::max<long long>(c->E, std::max(c->nel[0], std::max(c->nel[1], c->nel[2])));
+  hipLaunchKernelGGL(noalloc_geometry_kernel, dim3((span + 255) / 256), dim3(256), 0, stream,
+                     reinterpret_cast<double*>(base + l.off_h2[0]), reinterpret_cast<double*>(base + l.off_h2[1]),
+                     reinterpret_cast<double*>(base + l.off_h2[2]), reinterpret_cast<int*>(base + l.off_order),
+                     c->dim, c->nel[0], c->nel[1], c->nel[2], c->mesh.lo[0], c->mesh.hi[0], c->mesh.lo[1],
+                     c->mesh.hi[1], c->mesh.lo[2], c->mesh.hi[2], (int)c->E);
+  if (hipGetLastError() != hipSuccess) return NSK_EHIP;
+  // the stage launchers read the workspace, stream and order from the
+  // context: point them at the scratch for this call (a context is not
+  // reentrant), then restore them
+  char* work = c->work;
+  const size_t off_G = c->off_G, off_order = c->off_order;
+  const size_t off_h2[3] = {c->off_h2[0], c->off_h2[1], c->off_h2[2]};
+  hipStream_t bound_stream = c->stream;
+  const int order = c->order;
+  c->work = reinterpret_cast<char*>(base);
+  c->off_G = l.off_G;
+  c->off_order = l.off_order;
+  for (int d = 0; d < 3; ++d) c->off_h2[d] = l.off_h2[d];
+  c->stream = stream;
+  c->order = 1;  // natural order, one contiguous range per XCD
+  StageArgs st{0.0, 0.0, 0.0, 0};
+  rc = dispatch(c, 0, d_U, d_R, nullptr, st);
+  c->work = work;
+  c->off_G = off_G;
+  c->off_order = off_order;
+  for (int d = 0; d < 3; ++d) c->off_h2[d] = off_h2[d];
+  c->stream = bound_stream;
+  c->order = order;
+  return rc;
 }
 
 int nsk_rk_step(nsk_ctx* c, double dt, int nsteps) {

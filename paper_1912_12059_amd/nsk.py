@@ -21,6 +21,8 @@ NSK_EHIP = -3
 NSK_EUNBOUND = -4
 NSK_EUNSUPPORTED = -5
 NSK_ENOCONV = -6
+NSK_ESCRATCH = -7
+NSK_NOALLOC_SCRATCH_BYTES = 128 << 20
 NSK_GMRES_MAX = 64
 
 
@@ -125,6 +127,7 @@ def load() -> C.CDLL:
         L.nsk_set_state.argtypes = [vp, vp]
         L.nsk_get_state.argtypes = [vp, vp]
         L.nsk_rhs.argtypes = [vp, vp, vp, C.c_double]
+        L.nsk_rhs_noalloc.argtypes = [vp, vp, vp, vp]
         L.nsk_dt_estimate.argtypes = [vp, C.c_double, dp]
         L.nsk_rk_step.argtypes = [vp, C.c_double, C.c_int]
         L.nsk_diagnostics.argtypes = [vp, C.POINTER(nsk_diag)]
@@ -245,6 +248,10 @@ def nsk_get_state(ctx: int, d_dst: int) -> None:
 
 def nsk_rhs(ctx: int, d_U: int, d_R: int, t: float = 0.0) -> None:
     _check("nsk_rhs", load().nsk_rhs(ctx, d_U, d_R, t))
+
+
+def nsk_rhs_noalloc(ctx: int, d_U: int, d_R: int, stream: int = 0) -> None:
+    _check("nsk_rhs_noalloc", load().nsk_rhs_noalloc(ctx, d_U, d_R, stream))
 
 
 def nsk_dt_estimate(ctx: int, cfl: float) -> float:

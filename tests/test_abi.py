@@ -104,6 +104,34 @@ def test_unbound_calls_fail_cleanly():
         nsk.nsk_destroy(ctx)
 
 
+def test_rhs_noalloc_host_side_checks():
+    """nsk_rhs_noalloc refuses, before any device call, problems whose
+    gradients and geometry exceed its static scratch, the options it does not
+    cover, and bad pointers."""
+    big, keep = nsk.make_mesh(3, 4, (64, 64, 64))  # 32.8M nodes: 2.4 GB of FP64 gradients
+    ctx = nsk.nsk_create(big, nsk.make_params())
+    small, keep2 = _ok_mesh()
+    ok = nsk.nsk_create(small, nsk.make_params())
+    nub, keep3 = nsk.make_mesh(1, 3, (3,), xbreaks=[[0.0, 0.3, 0.5, 1.0]])
+    nonuni = nsk.nsk_create(nub, nsk.make_params())
+    sc = nsk.nsk_create(small, nsk.make_params(subcell=1, subcell_threshold=-9.0))
+    try:
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_rhs_noalloc(ctx, 8, 16)
+        assert e.value.code == nsk.NSK_ESCRATCH and "scratch" in nsk.nsk_strerror(nsk.NSK_ESCRATCH)
+        for c in (nonuni, sc):
+            with pytest.raises(nsk.NskError) as e:
+                nsk.nsk_rhs_noalloc(c, 8, 16)
+            assert e.value.code == nsk.NSK_EUNSUPPORTED
+        for args in ((0, 16), (8, 0), (8, 8)):
+            with pytest.raises(nsk.NskError) as e:
+                nsk.nsk_rhs_noalloc(ok, *args)
+            assert e.value.code == nsk.NSK_EINVAL
+    finally:
+        for c in (ctx, ok, nonuni, sc):
+            nsk.nsk_destroy(c)
+
+
 def test_strerror():
     assert "invalid" in nsk.nsk_strerror(nsk.NSK_EINVAL)
     assert nsk.nsk_strerror(12345) == "unknown error"
