@@ -364,6 +364,41 @@ typedef struct {
  * of a closure context return NSK_EINVAL until a network is set.  Host only. */
 int nsk_closure_set(nsk_ctx* ctx, const uint16_t* d_w_bf16, const nsk_closure_norm* norm, int every_stage);
 
+/* Why nsk_closure_run left the closure run (nsk_closure_report.reason). */
+#define NSK_CLOSURE_KEPT 0      /* the closure run reached the end            */
+#define NSK_CLOSURE_PARAMS 1    /* a network parameter is not finite          */
+#define NSK_CLOSURE_NONPHYS 2   /* the state turned non-physical (diagnostics) */
+#define NSK_CLOSURE_ENERGY 3    /* the energy grew beyond the tolerance       */
+
+typedef struct {
+  int fell_back;             /* 1: the run finished on the fallback context      */
+  int reason;                /* NSK_CLOSURE_* above                              */
+  long long closure_steps;   /* steps of size dt kept from the closure run       */
+  long long fallback_steps;  /* steps of size dt / ratio on the fallback context */
+  double e_start;            /* e_total of the initial state                     */
+  double e_last;             /* e_total at the last check of the closure run     */
+} nsk_closure_report;
+
+/* The closure run with the plain large-alpha run as its fallback and judge.
+ * Advances the bound state of cl (params.closure = 1, network set, model
+ * II at the moderate alpha) by nsteps steps of dt, checking its diagnostics
+ * every check_every steps and copying every state that passes into the
+ * bound state of ref (params.closure = 0, the plain run at the large alpha
+ * whose relaxation limit the closure imitates (alpha -> infinity recovers
+ * the NSK equations, Sec. 2.3), same mesh).  If a network parameter is not
+ * finite (checked first), the state turns non-physical (NSK_ENONPHYS of the
+ * diagnostics), or, with energy_tol >= 0, e_total exceeds its initial value
+ * by more than energy_tol |e_start|, the remaining time is run on ref from
+ * the last state that passed, in steps of dt / ratio (ratio >= 1: ref's step
+ * is that fraction of cl's), and the result is copied back into cl.  Either
+ * way the final state is cl's bound state; *report says which run produced
+ * it.  Returns NSK_ENONPHYS if the initial state or the fallback run is
+ * non-physical, NSK_EINVAL for mismatched contexts or arguments (checked
+ * before any device call), NSK_EUNBOUND if either context is not bound.
+ * Waits for both streams. */
+int nsk_closure_run(nsk_ctx* cl, nsk_ctx* ref, double dt, int nsteps, int ratio, int check_every,
+                    double energy_tol, nsk_closure_report* report);
+
 /* One nudging step on the bound state of any context (training pairs):
  * with the reference state d_Uref (layout of the state, device) mapped into
  * this model's frame, U* = (rho_r, m_r, rho_r + cmap (c_r - rho_r)), and the

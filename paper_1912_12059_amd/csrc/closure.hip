@@ -4,6 +4,7 @@
 // the network and the features is in closure.hpp.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -319,9 +320,108 @@ int launch_nudge_np(nsk_ctx* c, const ClosureArgs& ca, const double* Ur, double 
   return NSK_EUNSUPPORTED;
 }
 
+// number of parameters whose BF16 exponent is all ones (infinite or NaN),
+// as a double in *out; one workgroup
+constexpr int kParamCheckThreads = 256;
+__global__ void __launch_bounds__(kParamCheckThreads)
+param_nonfinite_kernel(const uint16_t* __restrict__ w, int n, double* __restrict__ out) {
+  __shared__ int red[kParamCheckThreads / 64];
+  int cnt = 0;
+  for (int i = threadIdx.x; i < n; i += kParamCheckThreads) cnt += (w[i] & 0x7F80u) == 0x7F80u ? 1 : 0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int k = 0; k < kParamCheckThreads / 64; ++k) t += red[k];
+    *out = (double)t;
+  }
+}
+
+bool same_mesh(const nsk_ctx* a, const nsk_ctx* b) {
+  if (a->dim != b->dim || a->N != b->N || a->E != b->E || a->nvar != b->nvar) return false;
+  for (int d = 0; d < 3; ++d)
+    if (a->nel[d] != b->nel[d] || a->h2[d] != b->h2[d]) return false;
+  return true;
+}
+
+// D2D copy of one context's state into another's, finished before return
+// (the two contexts may be bound to different streams)
+int copy_state(nsk_ctx* dst, nsk_ctx* src) {
+  if (hipStreamSynchronize(src->stream) != hipSuccess) return NSK_EHIP;
+  int rc = nsk_set_state(dst, src->U);
+  if (rc) return rc;
+  return hipStreamSynchronize(dst->stream) == hipSuccess ? NSK_OK : NSK_EHIP;
+}
+
 }  // namespace
 
 extern "C" {
+
+int nsk_closure_run(nsk_ctx* cl, nsk_ctx* ref, double dt, int nsteps, int ratio, int check_every,
+                    double energy_tol, nsk_closure_report* report) {
+  if (!cl || !ref || cl == ref || !report) return NSK_EINVAL;
+  if (cl->par.closure != 1 || !cl->cl_w || ref->par.closure != 0) return NSK_EINVAL;
+  if (cl->par.model != 0 || ref->par.model != 0 || !same_mesh(cl, ref)) return NSK_EINVAL;
+  if (!(dt > 0.0) || !std::isfinite(dt) || nsteps < 0 || ratio < 1 || check_every < 1) return NSK_EINVAL;
+  if (!std::isfinite(energy_tol)) return NSK_EINVAL;
+  if (!cl->bound || !ref->bound) return NSK_EUNBOUND;
+  std::memset(report, 0, sizeof(*report));
+  // the parameters, counted on the device
+  double* out = reinterpret_cast<double*>(cl->work + cl->off_out) + kDiagSlots;
+  hipLaunchKernelGGL(param_nonfinite_kernel, dim3(1), dim3(kParamCheckThreads), 0, cl->stream, cl->cl_w,
+                     kMlpParams, out);
+  double bad = 0.0;
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(&bad, out, sizeof(double), hipMemcpyDeviceToHost, cl->stream) != hipSuccess ||
+      hipStreamSynchronize(cl->stream) != hipSuccess)
+    return NSK_EHIP;
+  nsk_diag d;
+  int rc = nsk_diagnostics(cl, &d);
+  if (rc) return rc;  // NSK_ENONPHYS: no state to start either run from
+  report->e_start = report->e_last = d.e_total;
+  rc = copy_state(ref, cl);
+  if (rc) return rc;
+  long long done = 0;
+  int reason = bad > 0.0 ? NSK_CLOSURE_PARAMS : NSK_CLOSURE_KEPT;
+  while (reason == NSK_CLOSURE_KEPT && done < nsteps) {
+    const int n = (int)std::min<long long>(check_every, nsteps - done);
+    rc = nsk_rk_step(cl, dt, n);
+    if (rc) return rc;
+    rc = nsk_diagnostics(cl, &d);  // waits for cl's stream
+    if (rc == NSK_ENONPHYS) {
+      reason = NSK_CLOSURE_NONPHYS;
+    } else if (rc) {
+      return rc;
+    } else if (energy_tol >= 0.0 && d.e_total > report->e_start + energy_tol * std::fabs(report->e_start)) {
+      reason = NSK_CLOSURE_ENERGY;
+    } else {
+      done += n;
+      report->e_last = d.e_total;
+      rc = copy_state(ref, cl);  // the last state that passed
+      if (rc) return rc;
+    }
+  }
+  report->closure_steps = done;
+  report->reason = reason;
+  if (reason == NSK_CLOSURE_KEPT) return NSK_OK;
+  // the rest of the time on the large-alpha run, from the last state that passed
+  report->fell_back = 1;
+  long long left = (nsteps - done) * (long long)ratio;
+  report->fallback_steps = left;
+  const double dtr = dt / ratio;
+  while (left > 0) {
+    const int n = (int)std::min<long long>(left, 1 << 30);
+    rc = nsk_rk_step(ref, dtr, n);
+    if (rc) return rc;
+    left -= n;
+  }
+  rc = nsk_diagnostics(ref, &d);
+  if (rc) return rc;
+  return copy_state(cl, ref);
+}
+
 
 int nsk_closure_set(nsk_ctx* c, const uint16_t* d_w_bf16, const nsk_closure_norm* norm, int every_stage) {
   if (!c || !d_w_bf16 || !norm || (every_stage != 0 && every_stage != 1)) return NSK_EINVAL;

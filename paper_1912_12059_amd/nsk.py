@@ -65,6 +65,12 @@ class nsk_closure_norm(C.Structure):
 
 
 NSK_MLP_NPARAM = 8770
+NSK_CLOSURE_KEPT, NSK_CLOSURE_PARAMS, NSK_CLOSURE_NONPHYS, NSK_CLOSURE_ENERGY = 0, 1, 2, 3
+
+
+class nsk_closure_report(C.Structure):
+    _fields_ = [("fell_back", C.c_int), ("reason", C.c_int), ("closure_steps", C.c_longlong),
+                ("fallback_steps", C.c_longlong), ("e_start", C.c_double), ("e_last", C.c_double)]
 
 
 class nsk_implicit_opts(C.Structure):
@@ -162,6 +168,8 @@ def load() -> C.CDLL:
         L.nsk_closure_set.argtypes = [vp, vp, C.POINTER(nsk_closure_norm), C.c_int]
         L.nsk_closure_nudge.argtypes = [vp, C.POINTER(nsk_closure_norm), vp, C.c_double, C.c_double, C.c_double, vp,
                                         vp]
+        L.nsk_closure_run.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int, C.c_int, C.c_double,
+                                      C.POINTER(nsk_closure_report)]
         L.nsk_mlp_forward.argtypes = [vp, vp, C.c_longlong, vp, vp]
         L.nsk_mlp_workspace_bytes.argtypes = [C.c_longlong]
         L.nsk_mlp_workspace_bytes.restype = C.c_size_t
@@ -401,6 +409,14 @@ def _norm_struct(norm: dict) -> nsk_closure_norm:
     full = {k: 0.0 for k in ("s0", "k0", "s1", "k1", "k2", "k3", "g0", "out_m", "out_c")}
     full.update(norm)
     return nsk_closure_norm(**{k: float(v) for k, v in full.items()})
+
+
+def nsk_closure_run(cl: int, ref: int, dt: float, nsteps: int, ratio: int, check_every: int,
+                    energy_tol: float = -1.0) -> dict:
+    rep = nsk_closure_report()
+    _check("nsk_closure_run", load().nsk_closure_run(cl, ref, dt, nsteps, ratio, check_every, energy_tol,
+                                                     C.byref(rep)))
+    return {k: getattr(rep, k) for k, _ in nsk_closure_report._fields_}
 
 
 def nsk_closure_nudge(ctx: int, norm: dict, d_Uref: int, dt: float, tau: float, cmap: float, d_X: int,

@@ -132,6 +132,39 @@ def test_rhs_noalloc_host_side_checks():
             nsk.nsk_destroy(c)
 
 
+def test_closure_run_host_side_checks():
+    """nsk_closure_run validates its two contexts and arguments on the host
+    before touching a device."""
+    m, keep = _ok_mesh()
+    m2, keep2 = _ok_mesh(nel=(4, 3, 3))
+    cl = nsk.nsk_create(m, nsk.make_params(alpha=200.0, closure=1))
+    cl_nonet = nsk.nsk_create(m, nsk.make_params(alpha=200.0, closure=1))
+    ref = nsk.nsk_create(m, nsk.make_params(alpha=2000.0))
+    ref_other = nsk.nsk_create(m2, nsk.make_params(alpha=2000.0))
+    ref_cl = nsk.nsk_create(m, nsk.make_params(alpha=2000.0, closure=1))
+    norm = dict(s0=1.0, k0=1.0, s1=1.0, k1=1.0, k2=1.0, k3=1.0, g0=0.1, out_m=1.0, out_c=1.0)
+    try:
+        nsk.nsk_closure_set(cl, 256, norm, 1)  # a device address, never read by the checks
+        nsk.nsk_closure_set(ref_cl, 256, norm, 1)
+        bad = [(cl_nonet, ref, 1e-6, 4, 2, 2), (ref, ref, 1e-6, 4, 2, 2), (cl, ref_other, 1e-6, 4, 2, 2),
+               (cl, ref_cl, 1e-6, 4, 2, 2), (cl, cl, 1e-6, 4, 2, 2), (cl, ref, 0.0, 4, 2, 2),
+               (cl, ref, float("nan"), 4, 2, 2), (cl, ref, 1e-6, -1, 2, 2), (cl, ref, 1e-6, 4, 0, 2),
+               (cl, ref, 1e-6, 4, 2, 0)]
+        for args in bad:
+            with pytest.raises(nsk.NskError) as e:
+                nsk.nsk_closure_run(*args)
+            assert e.value.code == nsk.NSK_EINVAL, args
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_closure_run(cl, ref, 1e-6, 4, 2, 2, float("inf"))
+        assert e.value.code == nsk.NSK_EINVAL
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_closure_run(cl, ref, 1e-6, 4, 2, 2)
+        assert e.value.code == nsk.NSK_EUNBOUND
+    finally:
+        for c in (cl, cl_nonet, ref, ref_other, ref_cl):
+            nsk.nsk_destroy(c)
+
+
 def test_strerror():
     assert "invalid" in nsk.nsk_strerror(nsk.NSK_EINVAL)
     assert nsk.nsk_strerror(12345) == "unknown error"

@@ -339,3 +339,116 @@ def test_trained_closure_gains_over_plain_alpha200(gpu):
     assert np.all(np.isfinite(Uc)) and np.all(np.isfinite(Uc1))
     assert ec[0] < 0.8 * ep[0] and ec1[0] < 0.8 * ep[0]
     assert ec[1] < ep[1] and ec1[1] < ep[1]
+
+
+# --------------------------------------------------------------------------
+# the closure run with the plain large-alpha run as fallback (nsk_closure_run)
+# --------------------------------------------------------------------------
+def _fallback_case(gpu, out_m, out_c=1e-3, nan_param=False, nel=16):
+    """2D droplets (kappa = 1e-4, N = 3), an alpha = 200 closure context with
+    a seeded random network and output scales out_m, out_c, and the plain
+    alpha = 2000 context; returns them, the state and the step sizes."""
+    import torch
+
+    from paper_1912_12059_amd import closure as CL
+    from paper_1912_12059_amd import inputs as I
+
+    kappa = 1e-4
+    mesh = dict(dim=2, N=3, nel=(nel, nel))
+    _, U = I.droplets_2d(nel=nel, N=3)
+    U0 = torch.from_numpy(U.reshape(-1)).cuda()
+    w = CL.init_params(seed=4)
+    if nan_param:
+        w[123] = np.nan
+    net = CL.Network(params=w)
+    norm = dict(CL.default_norm(kappa), out_m=out_m, out_c=out_c)
+    cl = CL.closure_solver(net, norm, alpha=200.0, kappa=kappa, **mesh)
+    ref = gpu.Solver(alpha=2000.0, kappa=kappa, **mesh)
+    cl.set_state(U0)
+    ref.set_state(U0)
+    dt_ref = ref.dt_estimate(0.5)
+    ratio = max(1, int(cl.dt_estimate(0.5) / dt_ref))
+    return cl, ref, U0, ratio * dt_ref, ratio, (net, norm, kappa, mesh)
+
+
+def _plain(gpu, U0, kappa, mesh, alpha, dt, n):
+    s = gpu.Solver(alpha=alpha, kappa=kappa, **mesh)
+    s.set_state(U0)
+    s.rk_step(dt, n)
+    out = s.get_state()
+    s.close()
+    return out
+
+
+def test_closure_run_falls_back_on_nonfinite_parameters(gpu):
+    """A NaN parameter: the whole run is the alpha = 2000 run, bit for bit."""
+    import torch
+
+    cl, ref, U0, dt, ratio, (net, norm, kappa, mesh) = _fallback_case(gpu, 1.0, nan_param=True)
+    rep = gpu.nsk_closure_run(cl.ctx, ref.ctx, dt, 20, ratio, 5)
+    assert rep["fell_back"] == 1 and rep["reason"] == gpu.NSK_CLOSURE_PARAMS
+    assert rep["closure_steps"] == 0 and rep["fallback_steps"] == 20 * ratio
+    want = _plain(gpu, U0, kappa, mesh, 2000.0, dt / ratio, 20 * ratio)
+    assert torch.equal(cl.get_state(), want)
+    cl.close()
+    ref.close()
+
+
+def test_closure_run_falls_back_when_state_turns_nonphysical(gpu):
+    """An output scale of 1e7 drives the closure run out of (0, 3); the run
+    continues on alpha = 2000 from the last state that passed a check, and
+    equals that split run done by hand."""
+    import torch
+
+    from paper_1912_12059_amd import closure as CL
+
+    cl, ref, U0, dt, ratio, (net, norm, kappa, mesh) = _fallback_case(gpu, 1e7, 1e7)
+    rep = gpu.nsk_closure_run(cl.ctx, ref.ctx, dt, 40, ratio, 4)
+    assert rep["fell_back"] == 1 and rep["reason"] == gpu.NSK_CLOSURE_NONPHYS
+    k = rep["closure_steps"]
+    assert k % 4 == 0 and k < 40 and rep["fallback_steps"] == (40 - k) * ratio
+    got = cl.get_state()
+    assert bool(torch.isfinite(got).all()) and cl.diagnostics()["status"] == 0
+    hand = CL.closure_solver(net, norm, alpha=200.0, kappa=kappa, **mesh)
+    hand.set_state(U0)
+    hand.rk_step(dt, k)
+    mid = hand.get_state().reshape(-1).clone()
+    hand.close()
+    want = _plain(gpu, mid, kappa, mesh, 2000.0, dt / ratio, (40 - k) * ratio)
+    assert torch.equal(got, want)
+    cl.close()
+    ref.close()
+
+
+def test_closure_run_falls_back_on_energy_growth(gpu):
+    """A momentum output scale of 1e3 injects kinetic energy: with a zero
+    tolerance a check sees e_total above its start and the run falls back
+    from the last state that passed (whose energy was at most the start's)."""
+    cl, ref, U0, dt, ratio, _ = _fallback_case(gpu, 1e3)
+    rep = gpu.nsk_closure_run(cl.ctx, ref.ctx, dt, 10, ratio, 2, 0.0)
+    assert rep["fell_back"] == 1 and rep["reason"] == gpu.NSK_CLOSURE_ENERGY
+    k = rep["closure_steps"]
+    assert k % 2 == 0 and k < 10 and rep["fallback_steps"] == (10 - k) * ratio
+    assert rep["e_last"] <= rep["e_start"]
+    assert cl.diagnostics()["status"] == 0
+    cl.close()
+    ref.close()
+
+
+def test_closure_run_keeps_a_sound_closure(gpu):
+    """Small outputs: every check passes and the result is the closure run
+    itself, bit for bit."""
+    import torch
+
+    from paper_1912_12059_amd import closure as CL
+
+    cl, ref, U0, dt, ratio, (net, norm, kappa, mesh) = _fallback_case(gpu, 1e-3)
+    rep = gpu.nsk_closure_run(cl.ctx, ref.ctx, dt, 13, ratio, 5)
+    assert rep["fell_back"] == 0 and rep["reason"] == gpu.NSK_CLOSURE_KEPT and rep["closure_steps"] == 13
+    hand = CL.closure_solver(net, norm, alpha=200.0, kappa=kappa, **mesh)
+    hand.set_state(U0)
+    hand.rk_step(dt, 13)
+    assert torch.equal(cl.get_state(), hand.get_state())
+    hand.close()
+    cl.close()
+    ref.close()
