@@ -511,17 +511,25 @@ def run_batched_small(nsk, steps: int = 20, n: int = 64):
             "sequential_host_ms": wall_s}
 
 
-def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20):
+def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20, full_mesh: bool = False):
     """Closure form, kappa = 1e-4 (interface width 2 sqrt(kappa) = 0.02).
     A network is trained here, from seeded initial weights, on nudged
     alpha = 200 / 2000 pairs of two 3D collisions on [0,1]x[0,0.5]^2 with
     48x24x24 elements, N = 4 (the element size of the full collision mesh),
-    R = 0.1, to t_end.  Accuracy: a held-out collision of the same size runs
-    to t_end at alpha = 2000, alpha = 200 and alpha = 200 with the closure;
-    errors are the L2 of rho against the alpha = 2000 run over the L2 of its
-    change.  Speed: the three runs are timed per step on the full
-    96x48x48 mesh; the effective rate counts the alpha = 2000 DOF-stages to
-    t_end over the time the run needs to reach t_end."""
+    R = 0.1, to t_end.
+
+    Accuracy: a held-out collision runs to t_end at alpha = 2000 (the judge),
+    1000, 400 and 200, and at alpha = 200 with the closure (every stage, and
+    once per step) through nsk_closure_run, whose fallback is the alpha = 2000
+    run.  By default the held-out collision is a 48x24x24 one (We = 70,
+    impact 0.03); with full_mesh it is the benchmark collision itself on
+    96x48x48 (We = 100), and every run's time to t_end is measured.  Errors
+    of rho against the alpha = 2000 run: the quadrature-weighted L2 over
+    the weighted L2 of rho_ref, and over that of rho_ref's change from the
+    initial state.  Speed-ups are times to t_end against the alpha = 2000
+    run; on the 48x24x24 collision they are the full mesh's measured time
+    per step times each run's step count."""
+    import numpy as np
     import torch
 
     from paper_1912_12059_amd import closure as CL
@@ -529,6 +537,8 @@ def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20):
 
     kappa, N = 1e-4, 4
     small = dict(dim=3, N=N, nel=(48, 24, 24), hi=(1.0, 0.5, 0.5))
+    w = WORKLOADS["3d-collision"]
+    full = dict(dim=3, N=N, nel=w["nel"], lo=w["lo"], hi=w["hi"])
     norm = CL.default_norm(kappa)
 
     def small_ic(We, b):
@@ -553,115 +563,148 @@ def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20):
     del X, Y
     print(f"[bench] closure trained on {nsamp} samples in {train_s:.1f} s", file=sys.stderr, flush=True)
 
-    # accuracy on a held-out collision
-    dt_ref, M, n_mod = info["dt_ref"], info["M"], info["steps"]
+    # the alpha = 200 runs take their own step dt and the alpha = 2000 judge
+    # M steps of dt / M per step (within its own limit dt_ref_own)
+    dt_mod, M = info["dt"], info["M"]
+    dt_ref = dt_mod / M
+    n_mod = int(round(tend / dt_mod))
     n_ref = M * n_mod
-    U0 = small_ic(70.0, 0.03)
-    ref = nsk.Solver(alpha=2000.0, kappa=kappa, **small)
-    ref.set_state(U0)
-    ref.rk_step(dt_ref, n_ref)
-    Ur = ref.get_state()
-    ref.close()
-    plain = nsk.Solver(alpha=200.0, kappa=kappa, **small)
-    plain.set_state(U0)
-    plain.rk_step(M * dt_ref, n_mod)
-    Up = plain.get_state()
-    plain.close()
-    cl = CL.closure_solver(net, norm, alpha=200.0, kappa=kappa, **small)
-    cl.set_state(U0)
-    cl.rk_step(M * dt_ref, n_mod)
-    Uc = cl.get_state()
-    cl.close()
-    cl1 = CL.closure_solver(net, norm, every_stage=0, alpha=200.0, kappa=kappa, **small)
-    cl1.set_state(U0)
-    cl1.rk_step(M * dt_ref, n_mod)
-    Uc1 = cl1.get_state()
-    cl1.close()
-    U0r = U0.reshape(Ur.shape)
-    change = float(torch.linalg.vector_norm(Ur[0] - U0r[0]))
-
-    def err(U):
-        return float(torch.linalg.vector_norm(U[0] - Ur[0])) / change
-
-    # plain runs at intermediate alpha to the same time: the error each
-    # reaches and the steps it takes (its own CFL 0.5 step)
-    tend_run = n_ref * dt_ref
-    between = []
-    for a in (1000.0, 400.0):
-        sa = nsk.Solver(alpha=a, kappa=kappa, **small)
-        sa.set_state(U0)
-        na = int(math.ceil(tend_run / sa.dt_estimate(0.5) - 1e-9))
-        sa.rk_step(tend_run / na, na)
-        between.append((a, na, err(sa.get_state())))
-        sa.close()
-
-    # speed on the full mesh
-    w = WORKLOADS["3d-collision"]
-    full = dict(dim=3, N=N, nel=w["nel"], lo=w["lo"], hi=w["hi"])
-    _, Uf = I.collision_3d(nel=w["nel"], N=N, We=w["We"], lo=w["lo"], hi=w["hi"], device="cuda:0")
-    Uf = Uf.reshape(-1)
-    dofs = Uf.numel() // 5
+    tend_run = n_mod * dt_mod
+    if full_mesh:
+        mesh = full
+        _, U0 = I.collision_3d(nel=w["nel"], N=N, We=w["We"], lo=w["lo"], hi=w["hi"], device="cuda:0")
+        U0 = U0.reshape(-1)
+    else:
+        mesh = small
+        U0 = small_ic(70.0, 0.03)
+    wq = np.polynomial.legendre.leggauss(N + 1)[1]
+    wn = torch.from_numpy(np.einsum("i,j,k->kji", wq, wq, wq).reshape(-1)).cuda()  # node weights, i fastest
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
-    def ms_per_step(s, dt):
-        s.set_state(Uf)
-        nsk.nsk_autotune(s.ctx, 2)
-        s.rk_step(dt, 2)
-        s.set_state(Uf)
+    def run(fn, s):
         torch.cuda.synchronize()
         e0.record(s.stream)
-        s.rk_step(dt, timing_steps)
+        extra = fn()
         e1.record(s.stream)
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / timing_steps
+        return s.get_state()[0].reshape(-1, wn.numel()).clone(), e0.elapsed_time(e1), extra
 
-    sref = nsk.Solver(alpha=2000.0, kappa=kappa, **full)
-    ms_ref = ms_per_step(sref, dt_ref)
-    sref.close()
-    splain = nsk.Solver(alpha=200.0, kappa=kappa, **full)
-    ms_plain = ms_per_step(splain, M * dt_ref)
-    splain.close()
-    scl = CL.closure_solver(net, norm, alpha=200.0, kappa=kappa, **full)
-    scl.set_state(Uf)
-    nsk.nsk_autotune(scl.ctx, 2)
-    nsk.nsk_timing_enable(scl.ctx, 1)
-    ms_cl = ms_per_step(scl, M * dt_ref)
-    ms_lift, ms_rhs, nst, ms_cls = nsk.nsk_timing_read(scl.ctx)
-    nsk.nsk_timing_enable(scl.ctx, 0)
-    scl.close()
-    scl1 = CL.closure_solver(net, norm, every_stage=0, alpha=200.0, kappa=kappa, **full)
-    ms_cl1 = ms_per_step(scl1, M * dt_ref)
-    scl1.close()
-    work = dofs * 5 * n_ref  # alpha = 2000 DOF-stages to t_end
+    def plain(alpha, judge=False):
+        """The plain run at alpha to t_end: with judge, the alpha = 2000 run
+        in the steps of the closure runs' fallback (dt / M); otherwise in the
+        fewest equal steps within its own limit."""
+        s = nsk.Solver(alpha=alpha, kappa=kappa, **mesh)
+        s.set_state(U0)
+        n = n_ref if judge else int(math.ceil(tend_run / s.dt_estimate(0.5) - 1e-9))
+        dt = dt_ref if judge else tend_run / n
 
-    def rate(ms, nsteps):
-        return work / (ms * nsteps * 1e-3)
+        def steps():
+            for k in range(0, n, 2000):  # a progress line per 2000 steps
+                s.rk_step(dt, min(2000, n - k))
+                s.stream.synchronize()
+                print(f"[bench] closure form: plain alpha={alpha:g} {min(k + 2000, n)}/{n} steps", file=sys.stderr,
+                      flush=True)
 
-    return {
-        "workload": f"3d-collision {'x'.join(map(str, w['nel']))} N={N} kappa={kappa:g} t_end={n_ref * dt_ref:.4g}; "
-                    "accuracy on a held-out 48x24x24 collision (same element size), speed on the full mesh",
-        "alpha": 200.0, "alpha_ref": 2000.0, "dt_ref": dt_ref, "dt": M * dt_ref,
-        "steps_ref": n_ref, "steps": n_mod,
-        "ref_fp64": {"value": rate(ms_ref, n_ref), "ms_per_step": ms_ref},
-        "plain_alpha200": {"value": rate(ms_plain, n_mod), "ms_per_step": ms_plain,
-                           "l2_rel_rho_vs_ref": err(Up), "speedup_vs_ref": ms_ref * n_ref / (ms_plain * n_mod)},
-        "closure_alpha200": {"value": rate(ms_cl, n_mod), "ms_per_step": ms_cl,
-                             "l2_rel_rho_vs_ref": err(Uc), "speedup_vs_ref": ms_ref * n_ref / (ms_cl * n_mod),
-                             "closure_kernel_ms": ms_cls / max(nst, 1), "rhs_ms": ms_rhs / max(nst, 1),
-                             "lift_ms": ms_lift / max(nst, 1)},
-        "closure_alpha200_once_per_step": {"value": rate(ms_cl1, n_mod), "ms_per_step": ms_cl1,
-                                           "l2_rel_rho_vs_ref": err(Uc1),
-                                           "speedup_vs_ref": ms_ref * n_ref / (ms_cl1 * n_mod),
-                                           "note": "closure source of each step's first stage reused in its "
-                                                   "other four stages"},
-        "plain_intermediate_alpha": [
-            {"alpha": a, "steps": na, "l2_rel_rho_vs_ref": e, "speedup_vs_ref": ms_ref * n_ref / (ms_plain * na),
-             "note": "step cost taken from the plain alpha = 200 run (same kernels)"} for a, na, e in between],
-        "value_note": "effective DOF-stage/s: alpha=2000 DOF-stages to t_end / time to reach t_end",
+        rho, ms, _ = run(steps, s)
+        s.close()
+        return rho, ms, n
+
+    def with_closure(every_stage):
+        s = CL.closure_solver(net, norm, every_stage=every_stage, alpha=200.0, kappa=kappa, **mesh)
+        fb = nsk.Solver(alpha=2000.0, kappa=kappa, **mesh)
+        s.set_state(U0)
+        fb.set_state(U0)
+        rho, ms, rep = run(lambda: nsk.nsk_closure_run(s.ctx, fb.ctx, dt_mod, n_mod, M, 200), s)
+        s.close()
+        fb.close()
+        return rho, ms, rep
+
+    rho0 = U0.reshape(5, -1)[0].reshape(-1, wn.numel())
+    rho_ref, ms_ref, _ = plain(2000.0, judge=True)
+
+    def wl2(a):
+        return float(torch.sqrt(torch.sum(wn * a * a)))
+
+    ref_norm, change_norm = wl2(rho_ref), wl2(rho_ref - rho0)
+
+    def errors(rho):
+        e = wl2(rho - rho_ref)
+        return {"l2_rho_rel_to_ref": e / ref_norm, "l2_rho_rel_to_ref_change": e / change_norm}
+
+    results = {}
+    for alpha in (2000.0, 1000.0, 400.0, 200.0):
+        rho, ms, n = plain(alpha)
+        results[f"plain_alpha{int(alpha)}"] = dict(errors(rho), alpha=alpha, steps=n, ms_to_tend=ms)
+        print(f"[bench] closure form: plain alpha={alpha:g} done", file=sys.stderr, flush=True)
+    for every_stage, name in ((1, "closure_alpha200"), (0, "closure_alpha200_once_per_step")):
+        rho, ms, rep = with_closure(every_stage)
+        results[name] = dict(errors(rho), alpha=200.0, steps=n_mod, ms_to_tend=ms, fallback_report=rep)
+        print(f"[bench] closure form: {name} done (fell back: {rep['fell_back']})", file=sys.stderr, flush=True)
+
+    # time per step on the full mesh (the speed-ups of the 48x24x24 runs)
+    per_step = {}
+    if not full_mesh:
+        _, Uf = I.collision_3d(nel=w["nel"], N=N, We=w["We"], lo=w["lo"], hi=w["hi"], device="cuda:0")
+        Uf = Uf.reshape(-1)
+
+        def ms_per_step(s, dt):
+            s.set_state(Uf)
+            nsk.nsk_autotune(s.ctx, 2)
+            s.rk_step(dt, 2)
+            s.set_state(Uf)
+            return _timed_steps(s, dt, timing_steps) / timing_steps
+
+        for alpha in (2000.0, 1000.0, 400.0, 200.0):
+            s = nsk.Solver(alpha=alpha, kappa=kappa, stream=torch.cuda.Stream(), **full)
+            per_step[f"plain_alpha{int(alpha)}"] = ms_per_step(s, dt_mod if alpha == 200.0 else dt_ref)
+            s.close()
+        for every_stage, name in ((1, "closure_alpha200"), (0, "closure_alpha200_once_per_step")):
+            s = CL.closure_solver(net, norm, every_stage=every_stage, alpha=200.0, kappa=kappa,
+                                  stream=torch.cuda.Stream(), **full)
+            per_step[name] = ms_per_step(s, dt_mod)
+            if every_stage:
+                s.set_state(Uf)
+                nsk.nsk_timing_enable(s.ctx, 1)
+                _timed_steps(s, dt_mod, timing_steps)
+                ms_lift, ms_rhs, nst, ms_cls = nsk.nsk_timing_read(s.ctx)
+                nsk.nsk_timing_enable(s.ctx, 0)
+                per_step["closure_kernel_ms_per_stage"] = ms_cls / max(nst, 1)
+            s.close()
+    # the cost to beat: the plain alpha = 2000 run at its own step limit
+    n2000 = results["plain_alpha2000"]["steps"]
+    if not full_mesh:
+        ms_ref_full = per_step["plain_alpha2000"] * n2000
+    else:
+        ms_ref_full = results["plain_alpha2000"]["ms_to_tend"]
+    dofs_full = int(np.prod(w["nel"])) * (N + 1) ** 3
+    for name, r in results.items():
+        if full_mesh:
+            t = r["ms_to_tend"]
+        else:
+            t = per_step[name] * r["steps"]
+            r["ms_per_step_full_mesh"] = per_step[name]
+        r["speedup_vs_alpha2000"] = ms_ref_full / t
+        r["value"] = dofs_full * 5 * n2000 / (t * 1e-3)
+    out = {
+        "workload": (f"3d-collision {'x'.join(map(str, w['nel']))} N={N} kappa={kappa:g} t_end={tend_run:.4g}; "
+                     + ("every run on the full mesh" if full_mesh else
+                        "accuracy on a held-out 48x24x24 collision (same element size), speed on the full mesh")),
+        "alpha": 200.0, "alpha_ref": 2000.0, "dt": dt_mod, "ratio": M, "dt_judge": dt_ref,
+        "steps": n_mod, "steps_judge": n_ref,
+        "judge_note": "errors are against the alpha = 2000 run in steps dt / ratio (the closure runs' fallback); "
+                      "speed-ups against the plain alpha = 2000 run at its own step limit (plain_alpha2000)",
+        **results,
+        "value_note": "effective DOF-stage/s of the 96x48x48 mesh: DOF-stages of the plain alpha = 2000 run to "
+                      "t_end / time to t_end",
+        "error_note": "quadrature-weighted L2 of rho - rho_ref (alpha = 2000, same t_end) over that of rho_ref "
+                      "(rel_to_ref) and of rho_ref - rho_initial (rel_to_ref_change)",
         "training": {"samples": nsamp, "seconds": train_s, "steps": 3000, "batch": 32768,
                      "pairs": "nudged alpha=200 toward alpha=2000 (tau = 100 steps), collisions We=40 b=0 and "
                               "We=100 b=0.05R on 48x24x24"},
     }
+    if per_step:
+        out["closure_kernel_ms_per_stage"] = per_step.get("closure_kernel_ms_per_stage")
+    return out
 
 
 def _timed_steps(s, dt: float, steps: int) -> float:
@@ -816,6 +859,9 @@ def main() -> int:
     ap.add_argument("--no-implicit", action="store_true", help="skip the implicit ESDIRK form")
     ap.add_argument("--no-closure", action="store_true", help="skip the closure form")
     ap.add_argument("--only-closure", action="store_true", help="run only the closure form (prints its block)")
+    ap.add_argument("--closure-full-mesh", action="store_true",
+                    help="with --only-closure: run every accuracy run of the closure form on the full mesh")
+    ap.add_argument("--closure-tend", type=float, default=0.01, help="t_end of the closure form")
     ap.add_argument("--only-implicit", action="store_true",
                     help="run only one implicit step of 100x the explicit step, no explicit reference (profiling)")
     ap.add_argument("--only-subcell", type=float, default=None, metavar="THRESHOLD",
@@ -856,7 +902,8 @@ def main() -> int:
     from paper_1912_12059_amd import nsk
 
     if args.only_closure:
-        print(json.dumps({"closure": run_closure_form(nsk)}))
+        print(json.dumps({"closure": run_closure_form(nsk, tend=args.closure_tend,
+                                                      full_mesh=args.closure_full_mesh)}))
         return 0
     if args.only_batched:
         print(json.dumps({"batched": run_batched(nsk, 10, 2), "batched_small": run_batched_small(nsk)}))

@@ -117,19 +117,24 @@ class Network:
                          self.t, lr, beta1, beta2, eps, self.stream.cuda_stream)
 
     def train(self, X, Y, steps: int, batch: int = 32768, lr: float = 2e-3, lr_final: float = 2e-4,
-              tscale=(1.0, 1.0), seed: int = 0, log_every: int = 0):
-        """Adam on random minibatches (indices drawn by torch with a seeded
-        generator); learning rate decays geometrically from lr to lr_final.
-        Returns the sampled losses."""
+              tscale=(1.0, 1.0), seed: int = 0, log_every: int = 0, chunk: int = 256):
+        """Adam on random minibatches; learning rate decays geometrically
+        from lr to lr_final.  The minibatch indices are drawn on the host
+        (numpy PCG64 with the given seed) and uploaded `chunk` steps at a
+        time.  Returns the sampled losses."""
         import torch
 
-        gen = torch.Generator(device=self.device)
-        gen.manual_seed(seed)
+        g = np.random.Generator(np.random.PCG64(seed))
         ws = torch.empty(nsk.nsk_mlp_workspace_bytes(batch), dtype=torch.uint8, device=self.device)
         n = X.shape[0]
         losses = []
+        idx_all = None
         for k in range(steps):
-            idx = torch.randint(0, n, (batch,), device=self.device, generator=gen, dtype=torch.int32)
+            if k % chunk == 0:
+                m = min(chunk, steps - k)
+                draw = g.integers(0, n, size=(m, batch), dtype=np.int32)
+                idx_all = torch.from_numpy(draw).to(self.device)
+            idx = idx_all[k % chunk]
             loss, grad = self.loss_grad(X, Y, idx, tscale, ws)
             rate = lr * (lr_final / lr) ** (k / max(steps - 1, 1))
             self.adam(grad, rate)
@@ -167,21 +172,21 @@ def moments(Y):
 def nudged_pairs(mesh: dict, U0, alpha_ref: float, alpha: float, kappa: float, tend: float, norm: dict,
                  tau_steps: float = 100.0, record_every: int = 40, cfl: float = 0.5, **phys):
     """Training pairs from one nudged run.  mesh: Solver mesh keywords (dim,
-    N, nel, lo, hi); U0: initial state.  The alpha_ref run uses its own time
-    step dt_ref; the alpha run uses the largest multiple M dt_ref within its
-    own limit and is nudged after every step toward the reference at the
-    same time, with tau = tau_steps * M dt_ref.  Returns (X, Y) on the
-    device, one row per node of every recorded step."""
+    N, nel, lo, hi); U0: initial state.  The alpha run takes its own time
+    step dt; the alpha_ref run takes M = ceil(dt / dt_ref) steps of dt / M
+    (within its own limit dt_ref) per alpha step, and the alpha run is nudged
+    after every step toward the reference at the same time, with
+    tau = tau_steps * dt.  Returns (X, Y) on the device, one row per node of
+    every recorded step, and the step sizes (info["dt_ref"] = dt / M)."""
     import torch
 
     ref = nsk.Solver(alpha=alpha_ref, kappa=kappa, **mesh, **phys)
     mod = nsk.Solver(alpha=alpha, kappa=kappa, **mesh, **phys)
     ref.set_state(U0)
     mod.set_state(U0)
-    dt_ref = ref.dt_estimate(cfl)
-    # the ratio of the two source limits is alpha_ref / alpha up to rounding
-    M = max(1, int(mod.dt_estimate(cfl) / dt_ref * (1.0 + 1e-9)))
-    dt = M * dt_ref
+    dt = mod.dt_estimate(cfl)
+    M = max(1, math.ceil(dt / ref.dt_estimate(cfl) * (1.0 - 1e-12)))
+    dt_ref = dt / M
     nsteps = int(round(tend / dt))
     S = ref.nelem * ref.nnode
     nrec = nsteps // record_every
