@@ -371,12 +371,14 @@ def run_implicit_form(nsk, m, U0, w, factors=(100, 200), reference: bool = True)
     return out
 
 
-def run_batched(nsk, steps: int, warmup: int):
+def run_batched(nsk, steps: int, warmup: int, compare_steps: int = 20):
     """The batched collision sweep: 24 3D head-on collisions (n_x x 32 x 32
     elements, n_x in 32..64, N in {3,4,5}, We ~ U[5,150], impact ~ U[0,0.5] R,
     alpha = 1000) in mixed precision, advanced as one batch (per-degree
-    persistent kernels, two steps per graph replay), against the same 24
-    instances run one after another in plain FP64."""
+    persistent kernels, two steps per graph replay) for `steps` steps,
+    against the same 24 instances run one after another, mixed and plain
+    FP64, for the first compare_steps of them (rates, and the L2 of rho
+    against FP64 at that step)."""
     import torch
 
     from paper_1912_12059_amd import inputs as I
@@ -400,14 +402,25 @@ def run_batched(nsk, steps: int, warmup: int):
     b.rk_step(dt, warmup + warmup % 2)
     for i, u in enumerate(init):
         b.set_state(i, u)
+    compare_steps = min(compare_steps + compare_steps % 2, steps)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(b.stream)
-    b.rk_step(dt, steps)
+    b.rk_step(dt, compare_steps)
     e1.record(b.stream)
     torch.cuda.synchronize()
     ms_batch = e0.elapsed_time(e1)
     finals = [b.get_state(i) for i in range(len(sweep))]
+    if steps > compare_steps:
+        e0.record(b.stream)
+        b.rk_step(dt, steps - compare_steps)
+        e1.record(b.stream)
+        torch.cuda.synchronize()
+        ms_batch += e0.elapsed_time(e1)
+    physical = True
+    for i in range(len(sweep)):
+        rho = b.get_state(i).reshape(5, -1)[0]
+        physical &= bool(torch.isfinite(rho).all()) and float(rho.min()) > 0.0 and float(rho.max()) < 3.0
     b.close()
     del b
     # the same instances one after another (single-mesh launches), same
@@ -423,7 +436,7 @@ def run_batched(nsk, steps: int, warmup: int):
             sv.set_state(init[i])
             torch.cuda.synchronize()
             e0.record(sv.stream)
-            sv.rk_step(dt, steps)
+            sv.rk_step(dt, compare_steps)
             e1.record(sv.stream)
             torch.cuda.synchronize()
             ms_seq[prec] += e0.elapsed_time(e1)
@@ -435,6 +448,7 @@ def run_batched(nsk, steps: int, warmup: int):
                 l2max = max(l2max, l2)
             sv.close()
     work = sum(dofs) * 5 * steps
+    seq_work = sum(dofs) * 5 * compare_steps
     return {
         "instances": len(sweep),
         "dofs": sum(dofs),
@@ -444,11 +458,14 @@ def run_batched(nsk, steps: int, warmup: int):
         "value": work / (ms_batch * 1e-3),
         "unit": "DOF-stage/s",
         "ms_per_step": ms_batch / steps,
-        "sequential_mixed_value": work / (ms_seq[1] * 1e-3),
-        "sequential_fp64_value": work / (ms_seq[0] * 1e-3),
-        "speedup_vs_sequential_mixed": ms_seq[1] / ms_batch,
-        "speedup_vs_sequential_fp64": ms_seq[0] / ms_batch,
+        "all_physical_after_steps": physical,
+        "compare_steps": compare_steps,
+        "sequential_mixed_value": seq_work / (ms_seq[1] * 1e-3),
+        "sequential_fp64_value": seq_work / (ms_seq[0] * 1e-3),
+        "speedup_vs_sequential_mixed": (work / (ms_batch * 1e-3)) / (seq_work / (ms_seq[1] * 1e-3)),
+        "speedup_vs_sequential_fp64": (work / (ms_batch * 1e-3)) / (seq_work / (ms_seq[0] * 1e-3)),
         "max_l2_rel_rho_vs_fp64": l2max,
+        "l2_note": f"relative L2 of rho, batched mixed against sequential FP64, after {compare_steps} steps",
         "groups": groups,
         "autotune_ms": tune_ms[: nsk.BATCH_TUNE_SLOTS * len(groups)],
     }
@@ -511,7 +528,8 @@ def run_batched_small(nsk, steps: int = 20, n: int = 64):
             "sequential_host_ms": wall_s}
 
 
-def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20, full_mesh: bool = False):
+def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20, full_mesh: bool = False,
+                     train_full: bool = False):
     """Closure form, kappa = 1e-4 (interface width 2 sqrt(kappa) = 0.02).
     A network is trained here, from seeded initial weights, on nudged
     alpha = 200 / 2000 pairs of two 3D collisions on [0,1]x[0,0.5]^2 with
@@ -528,7 +546,13 @@ def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20, full_mesh:
     the weighted L2 of rho_ref, and over that of rho_ref's change from the
     initial state.  Speed-ups are times to t_end against the alpha = 2000
     run; on the 48x24x24 collision they are the full mesh's measured time
-    per step times each run's step count."""
+    per step times each run's step count.
+
+    train_full (with full_mesh): the training pairs come from two collisions
+    on the full 96x48x48 mesh instead (R = 0.2: We = 40 head-on and We = 150
+    with impact 0.1 R; the benchmark's We = 100 head-on collision stays held
+    out), and the plain alpha = 1000 and 2000 runs are not repeated to t_end
+    (their times to t_end come from timed steps)."""
     import numpy as np
     import torch
 
@@ -545,10 +569,20 @@ def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20, full_mesh:
         _, U = I.collision_3d(nel=small["nel"], N=N, We=We, radius=0.1, hi=small["hi"], impact=b, device="cuda:0")
         return U.reshape(-1)
 
+    def full_ic(We, b):
+        _, U = I.collision_3d(nel=w["nel"], N=N, We=We, lo=w["lo"], hi=w["hi"], impact=b, device="cuda:0")
+        return U.reshape(-1)
+
+    def progress(step, nsteps):
+        print(f"[bench] closure pairs: step {step}/{nsteps}", file=sys.stderr, flush=True)
+
     t0 = time.perf_counter()
     Xs, Ys = [], []
-    for We, b in ((40.0, 0.0), (100.0, 0.05)):
-        X, Y, info = CL.nudged_pairs(small, small_ic(We, b), 2000.0, 200.0, kappa, tend, norm, record_every=100)
+    pairs = ((full, full_ic, ((40.0, 0.0), (150.0, 0.02)), 200) if train_full else
+             (small, small_ic, ((40.0, 0.0), (100.0, 0.05)), 100))
+    for We, b in pairs[2]:
+        X, Y, info = CL.nudged_pairs(pairs[0], pairs[1](We, b), 2000.0, 200.0, kappa, tend, norm,
+                                     record_every=pairs[3], progress=progress)
         Xs.append(X)
         Ys.append(Y)
     X, Y = torch.cat(Xs), torch.cat(Ys)
@@ -633,6 +667,16 @@ def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20, full_mesh:
 
     results = {}
     for alpha in (2000.0, 1000.0, 400.0, 200.0):
+        if train_full and alpha in (2000.0, 1000.0):
+            # time 200 steps at the run's own limit; its error is not needed
+            s = nsk.Solver(alpha=alpha, kappa=kappa, stream=torch.cuda.Stream(), **mesh)
+            s.set_state(U0)
+            n = int(math.ceil(tend_run / s.dt_estimate(0.5) - 1e-9))
+            ms200 = _timed_steps(s, tend_run / n, 200)
+            s.close()
+            results[f"plain_alpha{int(alpha)}"] = dict(alpha=alpha, steps=n, ms_to_tend=ms200 / 200 * n,
+                                                      note="time to t_end from 200 timed steps")
+            continue
         rho, ms, n = plain(alpha)
         results[f"plain_alpha{int(alpha)}"] = dict(errors(rho), alpha=alpha, steps=n, ms_to_tend=ms)
         print(f"[bench] closure form: plain alpha={alpha:g} done", file=sys.stderr, flush=True)
@@ -699,8 +743,9 @@ def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20, full_mesh:
         "error_note": "quadrature-weighted L2 of rho - rho_ref (alpha = 2000, same t_end) over that of rho_ref "
                       "(rel_to_ref) and of rho_ref - rho_initial (rel_to_ref_change)",
         "training": {"samples": nsamp, "seconds": train_s, "steps": 3000, "batch": 32768,
-                     "pairs": "nudged alpha=200 toward alpha=2000 (tau = 100 steps), collisions We=40 b=0 and "
-                              "We=100 b=0.05R on 48x24x24"},
+                     "pairs": ("nudged alpha=200 toward alpha=2000 (tau = 100 steps), collisions "
+                               + ("R=0.2 We=40 b=0 and We=150 b=0.1R on 96x48x48" if train_full else
+                                  "R=0.1 We=40 b=0 and We=100 b=0.05R on 48x24x24"))},
     }
     if per_step:
         out["closure_kernel_ms_per_stage"] = per_step.get("closure_kernel_ms_per_stage")
@@ -862,6 +907,8 @@ def main() -> int:
     ap.add_argument("--closure-full-mesh", action="store_true",
                     help="with --only-closure: run every accuracy run of the closure form on the full mesh")
     ap.add_argument("--closure-tend", type=float, default=0.01, help="t_end of the closure form")
+    ap.add_argument("--closure-train-full", action="store_true",
+                    help="with --closure-full-mesh: train on two full-mesh collisions (the benchmark's held out)")
     ap.add_argument("--only-implicit", action="store_true",
                     help="run only one implicit step of 100x the explicit step, no explicit reference (profiling)")
     ap.add_argument("--only-subcell", type=float, default=None, metavar="THRESHOLD",
@@ -903,10 +950,11 @@ def main() -> int:
 
     if args.only_closure:
         print(json.dumps({"closure": run_closure_form(nsk, tend=args.closure_tend,
-                                                      full_mesh=args.closure_full_mesh)}))
+                                                      full_mesh=args.closure_full_mesh or args.closure_train_full,
+                                                      train_full=args.closure_train_full)}))
         return 0
     if args.only_batched:
-        print(json.dumps({"batched": run_batched(nsk, 10, 2), "batched_small": run_batched_small(nsk)}))
+        print(json.dumps({"batched": run_batched(nsk, 200, 2), "batched_small": run_batched_small(nsk)}))
         return 0
     if args.only_small_configs:
         print(json.dumps({"configs_small": run_small_configs(nsk, not args.no_cpu_baseline)}))
@@ -1045,7 +1093,7 @@ def main() -> int:
         out["forms"]["subcell_fp64"] = run_subcell_form(nsk, m, U0, w, dict(f64, steps=args.steps))
     del forms
     if not args.no_forms and not args.no_batched and args.workload == "3d-collision":
-        out.setdefault("forms", {})["batched"] = run_batched(nsk, 10, 2)
+        out.setdefault("forms", {})["batched"] = run_batched(nsk, 200, 2)
         out["forms"]["batched_small"] = run_batched_small(nsk)
     if not args.no_forms and not args.no_closure and args.workload == "3d-collision":
         out.setdefault("forms", {})["closure"] = run_closure_form(nsk)

@@ -170,14 +170,15 @@ def moments(Y):
 
 
 def nudged_pairs(mesh: dict, U0, alpha_ref: float, alpha: float, kappa: float, tend: float, norm: dict,
-                 tau_steps: float = 100.0, record_every: int = 40, cfl: float = 0.5, **phys):
+                 tau_steps: float = 100.0, record_every: int = 40, cfl: float = 0.5, progress=None, **phys):
     """Training pairs from one nudged run.  mesh: Solver mesh keywords (dim,
     N, nel, lo, hi); U0: initial state.  The alpha run takes its own time
     step dt; the alpha_ref run takes M = ceil(dt / dt_ref) steps of dt / M
     (within its own limit dt_ref) per alpha step, and the alpha run is nudged
     after every step toward the reference at the same time, with
     tau = tau_steps * dt.  Returns (X, Y) on the device, one row per node of
-    every recorded step, and the step sizes (info["dt_ref"] = dt / M)."""
+    every recorded step, and the step sizes (info["dt_ref"] = dt / M). progress(step, nsteps), if given, is called after every
+    recorded step."""
     import torch
 
     ref = nsk.Solver(alpha=alpha_ref, kappa=kappa, **mesh, **phys)
@@ -203,6 +204,9 @@ def nudged_pairs(mesh: dict, U0, alpha_ref: float, alpha: float, kappa: float, t
         yp = Y[k * S:].data_ptr() if rec else 0
         nsk.nsk_closure_nudge(mod.ctx, norm, ref.U.data_ptr(), dt, tau, cmap, xp, yp)
         k += int(rec)
+        if rec and progress is not None:
+            torch.cuda.synchronize()
+            progress(step, nsteps)
     torch.cuda.synchronize()
     info = {"dt_ref": dt_ref, "dt": dt, "M": M, "steps": nsteps, "records": nrec}
     ref.close()
