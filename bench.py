@@ -907,6 +907,9 @@ def main() -> int:
     ap.add_argument("--closure-full-mesh", action="store_true",
                     help="with --only-closure: run every accuracy run of the closure form on the full mesh")
     ap.add_argument("--closure-tend", type=float, default=0.01, help="t_end of the closure form")
+    ap.add_argument("--closure-kernel-steps", type=int, default=0, metavar="K",
+                    help="only K closure steps (every stage) on the full collision with a seeded untrained network "
+                         "(profiling the closure kernel)")
     ap.add_argument("--closure-train-full", action="store_true",
                     help="with --closure-full-mesh: train on two full-mesh collisions (the benchmark's held out)")
     ap.add_argument("--only-implicit", action="store_true",
@@ -948,6 +951,21 @@ def main() -> int:
 
     from paper_1912_12059_amd import nsk
 
+    if args.closure_kernel_steps:
+        from paper_1912_12059_amd import closure as CL
+
+        w = WORKLOADS["3d-collision"]
+        m, U = build_state("3d-collision")
+        net = CL.Network(seed=0)
+        norm = dict(CL.default_norm(1e-4), out_m=1e-3, out_c=1e-3)  # small outputs keep the state physical
+        s = CL.closure_solver(net, norm, alpha=200.0, kappa=1e-4, dim=3, N=w["N"], nel=w["nel"], lo=w["lo"],
+                              hi=w["hi"])
+        s.set_state(U)
+        dt = s.dt_estimate(0.5)
+        ms = _timed_steps(s, dt, args.closure_kernel_steps)
+        s.close()
+        print(json.dumps({"closure_kernel_steps": args.closure_kernel_steps, "ms_per_step": ms / args.closure_kernel_steps}))
+        return 0
     if args.only_closure:
         print(json.dumps({"closure": run_closure_form(nsk, tend=args.closure_tend,
                                                       full_mesh=args.closure_full_mesh or args.closure_train_full,

@@ -68,3 +68,30 @@ def test_side_stream_solver_full_size_3d_mixed(gpu):
         s.close()
         del s
     assert bool(torch.isfinite(outs[0]).all()) and torch.equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("every_stage", [1, 0])
+def test_graph_replay_with_closure(gpu, every_stage):
+    """Steps of a closure context (closure kernel every stage, or once per
+    step with its source reused by the later stages) captured into the step
+    graph equal stage-by-stage launches bit for bit."""
+    import torch
+
+    from paper_1912_12059_amd import closure as CL
+
+    m, U = I.smooth_random(3, 4, (5, 4, 3), seed=95)
+    net = CL.Network(seed=2)
+    norm = dict(CL.default_norm(1e-4), out_m=1e-2, out_c=1e-2)
+    base = dict(dim=3, N=4, nel=(5, 4, 3), alpha=200.0, kappa=1e-4, every_stage=every_stage)
+    g = CL.closure_solver(net, norm, stream=torch.cuda.Stream(), **base)
+    e = CL.closure_solver(net, norm, **base)
+    for s in (g, e):
+        s.set_state(U)
+    for n in (2, 3, 4):
+        g.rk_step(2e-6, n)
+        e.rk_step(2e-6, n)
+        torch.cuda.synchronize()
+        assert torch.equal(g.get_state(), e.get_state()), n
+    assert bool(torch.isfinite(g.get_state()).all())
+    g.close()
+    e.close()
