@@ -327,7 +327,7 @@ int nsk_esdirk_step(nsk_ctx* ctx, void* d_iwork, double dt, int nsteps, const ns
 /* ------------------------------------------------------------------------
  * Learned closure (no counterpart in the paper; the paper's model II is the
  * closure-free method).  A per-node network
- *   x -> 64 -> 64 -> 64 -> y,  GELU (erf form) on the hidden layers,
+ *   x -> 64 -> 64 -> 64 -> y,  ReLU on the hidden layers,
  * with BF16 parameters and FP32 accumulation, adds to the right-hand side
  *   momentum: out_m y_0 n,   c: out_c y_1,   n = g / sqrt(|g|^2 + g0^2),
  * from element-local features of the state (g = grad rho and lap = the
@@ -352,15 +352,16 @@ typedef struct {
 } nsk_closure_norm;
 
 /* Sets the network of a context created with params.closure = 1.  d_w_bf16
- * is a device pointer to NSK_MLP_NPARAM BF16 values that the caller keeps
- * valid and unchanged while the context steps (it is read, not copied).
+ * is a 16-byte aligned device pointer to NSK_MLP_NPARAM BF16 values that the
+ * caller keeps valid and unchanged while the context steps (it is read, not
+ * copied).
  * A closure kernel (features + network, FP32 result in the workspace) then
  * runs before the right-hand-side kernel, which adds the source in FP64:
  * in every stage (every_stage = 1), or in the first stage of each
  * nsk_rk_step step only, its source serving the step's five stages
  * (every_stage = 0; nsk_rhs always evaluates it).  NSK_EINVAL if the
- * context has closure = 0, an argument is NULL, every_stage is not 0 or 1,
- * a scale is not finite or g0 <= 0.  nsk_rhs, nsk_rk_step and nsk_autotune
+ * context has closure = 0, an argument is NULL or d_w_bf16 misaligned,
+ * every_stage is not 0 or 1, a scale is not finite or g0 <= 0.  nsk_rhs, nsk_rk_step and nsk_autotune
  * of a closure context return NSK_EINVAL until a network is set.  Host only. */
 int nsk_closure_set(nsk_ctx* ctx, const uint16_t* d_w_bf16, const nsk_closure_norm* norm, int every_stage);
 
@@ -411,9 +412,10 @@ int nsk_closure_run(nsk_ctx* cl, nsk_ctx* ref, double dt, int nsteps, int ratio,
 int nsk_closure_nudge(nsk_ctx* ctx, const nsk_closure_norm* norm, const double* d_Uref, double dt, double tau,
                       double cmap, float* d_X, float* d_Y);
 
-/* Network outputs y (unscaled) of n feature vectors: d_X[n][4] (16-byte
- * aligned) -> d_Y[n][2], with the inference kernel of the closure (BF16
- * MFMA).  Device pointers; asynchronous on hip_stream. */
+/* Network outputs y (unscaled) of n feature vectors: d_X[n][4] -> d_Y[n][2],
+ * with the inference kernel of the closure (BF16 MFMA).  d_w_bf16 and d_X
+ * are 16-byte aligned (else NSK_EINVAL).  Device pointers; asynchronous on
+ * hip_stream. */
 int nsk_mlp_forward(const uint16_t* d_w_bf16, const float* d_X, long long n, float* d_Y, void* hip_stream);
 
 /* Bytes of device workspace for nsk_mlp_loss_grad with n <= batch samples

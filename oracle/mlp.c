@@ -10,7 +10,7 @@
  *   z3 = W3 h2 + b3, h3 = g(z3)          (64 -> 64)
  *   y  = W4 h3 + b4                      (64 -> 2)
  *
- * with g the GELU in its erf form, g(z) = z (1 + erf(z / sqrt 2)) / 2.
+ * with g the rectifier g(z) = max(z, 0) (derivative 1 for z > 0, else 0).
  * Parameters are packed in one array, weights row-major [out][in]:
  *   W1[64][4] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[2][64] b4[2]
  * (8770 values).  The loss of a batch is L = 1/(2n) sum_s sum_o (y_so - t_so)^2
@@ -37,14 +37,9 @@ enum {
   OFF_END = OFF_B4 + OR_MLP_OUT
 };
 
-double or_gelu(double z) { return 0.5 * z * (1.0 + erf(z / sqrt(2.0))); }
+double or_relu(double z) { return z > 0.0 ? z : 0.0; }
 
-double or_gelu_d(double z) {
-  /* d/dz [z Phi(z)] = Phi(z) + z phi(z) */
-  const double Phi = 0.5 * (1.0 + erf(z / sqrt(2.0)));
-  const double phi = exp(-0.5 * z * z) / sqrt(2.0 * 3.14159265358979323846);
-  return Phi + z * phi;
-}
+double or_relu_d(double z) { return z > 0.0 ? 1.0 : 0.0; }
 
 /* one dense layer: out[o] = b[o] + sum_i W[o][i] in[i] */
 static void dense(const double* W, const double* b, int nout, int nin, const double* in, double* out) {
@@ -59,11 +54,11 @@ static void dense(const double* W, const double* b, int nout, int nin, const dou
 static void forward1(const double* w, const double* x, double z1[H], double z2[H], double z3[H], double y[2]) {
   double h[H];
   dense(w + OFF_W1, w + OFF_B1, H, OR_MLP_IN, x, z1);
-  for (int k = 0; k < H; ++k) h[k] = or_gelu(z1[k]);
+  for (int k = 0; k < H; ++k) h[k] = or_relu(z1[k]);
   dense(w + OFF_W2, w + OFF_B2, H, H, h, z2);
-  for (int k = 0; k < H; ++k) h[k] = or_gelu(z2[k]);
+  for (int k = 0; k < H; ++k) h[k] = or_relu(z2[k]);
   dense(w + OFF_W3, w + OFF_B3, H, H, h, z3);
-  for (int k = 0; k < H; ++k) h[k] = or_gelu(z3[k]);
+  for (int k = 0; k < H; ++k) h[k] = or_relu(z3[k]);
   dense(w + OFF_W4, w + OFF_B4, OR_MLP_OUT, H, h, y);
 }
 
@@ -84,9 +79,9 @@ double or_mlp_loss_grad(const double* w, const double* X, const double* Yt, long
     forward1(w, x, z1, z2, z3, y);
     double h1[H], h2[H], h3[H];
     for (int k = 0; k < H; ++k) {
-      h1[k] = or_gelu(z1[k]);
-      h2[k] = or_gelu(z2[k]);
-      h3[k] = or_gelu(z3[k]);
+      h1[k] = or_relu(z1[k]);
+      h2[k] = or_relu(z2[k]);
+      h3[k] = or_relu(z3[k]);
     }
     /* dL/dy */
     double dy[OR_MLP_OUT];
@@ -107,7 +102,7 @@ double or_mlp_loss_grad(const double* w, const double* X, const double* Yt, long
       dh[k] = t;
     }
     /* third layer */
-    for (int k = 0; k < H; ++k) dz[k] = dh[k] * or_gelu_d(z3[k]);
+    for (int k = 0; k < H; ++k) dz[k] = dh[k] * or_relu_d(z3[k]);
     for (int o = 0; o < H; ++o) {
       grad[OFF_B3 + o] += dz[o];
       for (int k = 0; k < H; ++k) grad[OFF_W3 + o * H + k] += dz[o] * h2[k];
@@ -118,7 +113,7 @@ double or_mlp_loss_grad(const double* w, const double* X, const double* Yt, long
       dh[k] = t;
     }
     /* second layer */
-    for (int k = 0; k < H; ++k) dz[k] = dh[k] * or_gelu_d(z2[k]);
+    for (int k = 0; k < H; ++k) dz[k] = dh[k] * or_relu_d(z2[k]);
     for (int o = 0; o < H; ++o) {
       grad[OFF_B2 + o] += dz[o];
       for (int k = 0; k < H; ++k) grad[OFF_W2 + o * H + k] += dz[o] * h1[k];
@@ -129,7 +124,7 @@ double or_mlp_loss_grad(const double* w, const double* X, const double* Yt, long
       dh[k] = t;
     }
     /* first layer */
-    for (int k = 0; k < H; ++k) dz[k] = dh[k] * or_gelu_d(z1[k]);
+    for (int k = 0; k < H; ++k) dz[k] = dh[k] * or_relu_d(z1[k]);
     for (int o = 0; o < H; ++o) {
       grad[OFF_B1 + o] += dz[o];
       for (int i = 0; i < OR_MLP_IN; ++i) grad[OFF_W1 + o * OR_MLP_IN + i] += dz[o] * x[i];

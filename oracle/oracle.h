@@ -141,8 +141,8 @@ int or_rhs_subcell(const or_prob* P, const double* U, double threshold, double* 
 #define OR_MLP_HIDDEN 64
 #define OR_MLP_OUT 2
 #define OR_MLP_NPARAM 8770
-double or_gelu(double z);
-double or_gelu_d(double z);
+double or_relu(double z);
+double or_relu_d(double z);
 long or_mlp_nparam(void);
 /* Y[n][2] = network(X[n][4]) with parameters w (layout in mlp.c). */
 void or_mlp_forward(const double* w, const double* X, long n, double* Y);

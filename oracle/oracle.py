@@ -125,10 +125,10 @@ def _declare(L):
     L.or_subcell_matrices.argtypes = [C.c_int, _dp, _dp]
     L.or_persson.argtypes = [C.POINTER(_Prob), _dp, _dp]
     L.or_rhs_subcell.argtypes = [C.POINTER(_Prob), _dp, C.c_double, _dp, C.POINTER(C.c_int)]
-    L.or_gelu.argtypes = [C.c_double]
-    L.or_gelu.restype = C.c_double
-    L.or_gelu_d.argtypes = [C.c_double]
-    L.or_gelu_d.restype = C.c_double
+    L.or_relu.argtypes = [C.c_double]
+    L.or_relu.restype = C.c_double
+    L.or_relu_d.argtypes = [C.c_double]
+    L.or_relu_d.restype = C.c_double
     L.or_mlp_nparam.restype = C.c_long
     L.or_mlp_forward.argtypes = [_dp, _dp, C.c_long, _dp]
     L.or_mlp_loss_grad.argtypes = [_dp, _dp, _dp, C.c_long, _dp]
@@ -447,12 +447,12 @@ MLP_NPARAM = 8770
 CLOSURE_NORM_KEYS = ("s0", "k0", "s1", "k1", "k2", "k3", "g0", "out_m", "out_c")
 
 
-def gelu(z: float) -> float:
-    return lib().or_gelu(z)
+def relu(z: float) -> float:
+    return lib().or_relu(z)
 
 
-def gelu_d(z: float) -> float:
-    return lib().or_gelu_d(z)
+def relu_d(z: float) -> float:
+    return lib().or_relu_d(z)
 
 
 def mlp_forward(w, X) -> np.ndarray:

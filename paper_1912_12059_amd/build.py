@@ -25,6 +25,9 @@ FLAGS = [
     "-shared",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in VGPRs (the closure network applies its activation
+    # to them with VALU instructions; in AGPRs each would first be copied out)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 

@@ -39,12 +39,14 @@ def bf16_bits_to_f64(b) -> np.ndarray:
 
 
 def init_params(seed: int = 0) -> np.ndarray:
-    """Glorot-uniform weights, zero biases (numpy PCG64)."""
+    """He-uniform weights for the layers followed by a ReLU (limit
+    sqrt(6 / fan_in)), Glorot-uniform for the output layer, zero biases
+    (numpy PCG64)."""
     g = np.random.Generator(np.random.PCG64(seed))
     out = []
     for name, shape in LAYOUT:
         if name.startswith("W"):
-            lim = math.sqrt(6.0 / (shape[0] + shape[1]))
+            lim = math.sqrt(6.0 / (shape[0] + shape[1])) if name == "W4" else math.sqrt(6.0 / shape[1])
             out.append(g.uniform(-lim, lim, size=shape).ravel())
         else:
             out.append(np.zeros(shape[0]))

@@ -23,7 +23,7 @@ __global__ void __launch_bounds__(kClosureThreads)
 mlp_forward_kernel(const uint16_t* __restrict__ w, const float* __restrict__ X, long long n, float* __restrict__ Y) {
   __shared__ float4 sX[kClosureThreads];
   __shared__ __attribute__((aligned(16))) uint16_t sW[2 * kMlpHid * kWPad];
-  __shared__ float sP[kCSmall];
+  __shared__ __attribute__((aligned(16))) float sP[kCSmall];
   mlp_stage_params(w, sW, sP);
   const int t = threadIdx.x;
   const long long s = (long long)blockIdx.x * kClosureThreads + t;
@@ -73,7 +73,7 @@ mlp_train_kernel(const uint16_t* __restrict__ w, const float* __restrict__ X, co
     float z = W(kOffB1 + u);
     for (int i = 0; i < kMlpIn; ++i) z += W(kOffW1 + u * kMlpIn + i) * sX[s][i];
     sZ1[s][u] = z;
-    sH1[s][u] = bf16_round(gelu_f(z));
+    sH1[s][u] = bf16_round(act_f(z));
   }
   __syncthreads();
   for (int p = t; p < T * Hd; p += kTrainThreads) {
@@ -81,7 +81,7 @@ mlp_train_kernel(const uint16_t* __restrict__ w, const float* __restrict__ X, co
     float z = W(kOffB2 + u);
     for (int k = 0; k < Hd; ++k) z += W(kOffW2 + u * Hd + k) * sH1[s][k];
     sZ2[s][u] = z;
-    sH2[s][u] = bf16_round(gelu_f(z));
+    sH2[s][u] = bf16_round(act_f(z));
   }
   __syncthreads();
   for (int p = t; p < T * Hd; p += kTrainThreads) {
@@ -89,7 +89,7 @@ mlp_train_kernel(const uint16_t* __restrict__ w, const float* __restrict__ X, co
     float z = W(kOffB3 + u);
     for (int k = 0; k < Hd; ++k) z += W(kOffW3 + u * Hd + k) * sH2[s][k];
     sZ3[s][u] = z;
-    sH3[s][u] = gelu_f(z);
+    sH3[s][u] = act_f(z);
   }
   __syncthreads();
   if (t < T * kMlpOut) {
@@ -121,7 +121,7 @@ mlp_train_kernel(const uint16_t* __restrict__ w, const float* __restrict__ X, co
     const int s = p / Hd, u = p - s * Hd;
     float dh = 0.f;
     for (int oo = 0; oo < kMlpOut; ++oo) dh += W(kOffW4 + oo * Hd + u) * sDy[s][oo];
-    sD[s][u] = dh * gelu_df(sZ3[s][u]);
+    sD[s][u] = dh * act_df(sZ3[s][u]);
   }
   __syncthreads();
   // gradients of layer 3; dz2 = (W3^T dz3) g'(z2) into sZ3 (no longer needed)
@@ -141,7 +141,7 @@ mlp_train_kernel(const uint16_t* __restrict__ w, const float* __restrict__ X, co
     const int s = p / Hd, j = p - s * Hd;
     float dh = 0.f;
     for (int u = 0; u < Hd; ++u) dh += W(kOffW3 + u * Hd + j) * sD[s][u];
-    sZ3[s][j] = dh * gelu_df(sZ2[s][j]);
+    sZ3[s][j] = dh * act_df(sZ2[s][j]);
   }
   __syncthreads();
   // gradients of layer 2; dz1 = (W2^T dz2) g'(z1) into sD
@@ -162,7 +162,7 @@ mlp_train_kernel(const uint16_t* __restrict__ w, const float* __restrict__ X, co
     const int s = p / Hd, j = p - s * Hd;
     float dh = 0.f;
     for (int u = 0; u < Hd; ++u) dh += W(kOffW2 + u * Hd + j) * sZ3[s][u];
-    sD[s][j] = dh * gelu_df(sZ1[s][j]);
+    sD[s][j] = dh * act_df(sZ1[s][j]);
   }
   __syncthreads();
   // gradients of layer 1
@@ -425,6 +425,7 @@ int nsk_closure_run(nsk_ctx* cl, nsk_ctx* ref, double dt, int nsteps, int ratio,
 
 int nsk_closure_set(nsk_ctx* c, const uint16_t* d_w_bf16, const nsk_closure_norm* norm, int every_stage) {
   if (!c || !d_w_bf16 || !norm || (every_stage != 0 && every_stage != 1)) return NSK_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(d_w_bf16) & 15) != 0) return NSK_EINVAL;  // staged 8 values at a time
   if (c->par.closure != 1 || !norm_ok(norm)) return NSK_EINVAL;
   c->cl_every_stage = every_stage;
   const float q[9] = {norm->s0, norm->k0, norm->s1, norm->k1, norm->k2, norm->k3, norm->g0, norm->out_m, norm->out_c};
@@ -449,7 +450,7 @@ int nsk_closure_nudge(nsk_ctx* c, const nsk_closure_norm* norm, const double* d_
 
 int nsk_mlp_forward(const uint16_t* d_w, const float* d_X, long long n, float* d_Y, void* hip_stream) {
   if (!d_w || n < 0 || (n > 0 && (!d_X || !d_Y))) return NSK_EINVAL;
-  if ((reinterpret_cast<uintptr_t>(d_X) & 15) != 0) return NSK_EINVAL;
+  if (((reinterpret_cast<uintptr_t>(d_X) | reinterpret_cast<uintptr_t>(d_w)) & 15) != 0) return NSK_EINVAL;
   if (n == 0) return NSK_OK;
   const long long blocks = (n + kClosureThreads - 1) / kClosureThreads;
   if (blocks > (1LL << 31) - 1) return NSK_EINVAL;

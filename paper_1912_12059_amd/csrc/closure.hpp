@@ -1,5 +1,5 @@
 // Device code of the learned closure: a per-node network
-//   x (4 features) -> 64 -> 64 -> 64 -> y (2), GELU (erf form),
+//   x (4 features) -> 64 -> 64 -> 64 -> y (2), ReLU on the hidden layers,
 // with BF16 parameters and FP32 accumulation, whose outputs add
 //   S_m = out_m y_0 n,  S_c = out_c y_1,   n = grad rho / sqrt(|grad rho|^2 + g0^2)
 // to the momentum and c equations of relaxation model II.  The paper defines
@@ -61,30 +61,15 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) { return __builtin_bit_
 
 __device__ __forceinline__ float bf16_round(float f) { return bf16_to_f32(f32_to_bf16(f)); }
 
-// ---- GELU (erf form) --------------------------------------------------------
-// g(z) = z Phi(z), Phi the standard normal CDF (Phi(z) = (1 + erf(z/sqrt 2))/2).
-// Phi(z) - 1/2 ~ z Q(z^2) on |z| <= 3.7 (z clamped there), Q of degree 6
-// fitted by least squares at Chebyshev nodes (fit_erf.py): error <= 6.2e-5,
-// far below the 2^-9 rounding of the BF16 activations, in 10 instructions
-// and no transcendental one.
-__device__ __forceinline__ float phi_poly(float z) {
-  const float zc = fminf(fmaxf(z, -3.7f), 3.7f);
-  const float u = zc * zc;
-  float q = 4.179373891e-08f;
-  q = fmaf(q, u, -2.488350468e-06f);
-  q = fmaf(q, u, 6.416094105e-05f);
-  q = fmaf(q, u, -9.583462844e-04f);
-  q = fmaf(q, u, 9.417267311e-03f);
-  q = fmaf(q, u, -6.588417949e-02f);
-  q = fmaf(q, u, 3.987580534e-01f);
-  return fmaf(zc, q, 0.5f);
-}
+// ---- activation ---------------------------------------------------------------
+// ReLU, g(z) = max(z, 0), with derivative 1 for z > 0 and 0 otherwise.  On
+// the bit pattern of an IEEE value it is the signed-integer maximum with 0
+// (negative values, -0 included, have the sign bit set and become +0): one
+// v_max_i32, without the quieting of signalling NaNs that fmaxf adds for
+// operands the compiler cannot prove canonical, such as MFMA results.
+__device__ __forceinline__ float act_f(float z) { return __int_as_float(max(__float_as_int(z), 0)); }
 
-__device__ __forceinline__ float gelu_f(float z) { return z * phi_poly(z); }
-
-__device__ __forceinline__ float gelu_df(float z) {
-  return phi_poly(z) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
-}
+__device__ __forceinline__ float act_df(float z) { return z > 0.f ? 1.f : 0.f; }
 
 // ---- element-local features ---------------------------------------------------
 template <int DIM, int NP>
@@ -145,12 +130,16 @@ __device__ __forceinline__ void closure_features(int t, long long e, bool active
       lap += h2[d] * s;
     }
   }
-  const double den = sqrt(gg + double(ca.g0) * double(ca.g0));
+  // the direction and |g| feed FP32 values only: FP32 square roots (the
+  // differences and sums above stay FP64, which keeps small gradients of a
+  // near-constant density resolved)
+  const float ggf = float(gg);
+  const float inv = rsqrtf(fmaf(ca.g0, ca.g0, ggf));
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) nvec[d] = active ? g[d] / den : 0.0;
+  for (int d = 0; d < DIM; ++d) nvec[d] = active ? double(float(g[d]) * inv) : 0.0;
   x[0] = active ? float((rho - double(ca.s0)) * double(ca.k0)) : 0.f;
   x[1] = active ? float((c - double(ca.s1)) * double(ca.k1)) : 0.f;
-  x[2] = active ? float(sqrt(gg) * double(ca.k2)) : 0.f;
+  x[2] = active ? sqrtf(ggf) * ca.k2 : 0.f;
   x[3] = active ? float(lap * double(ca.k3)) : 0.f;
 }
 
@@ -159,6 +148,21 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ short bf16_bits(float f) { return short(f32_to_bf16(f)); }
+
+// four FP32 values rounded to BF16 (nearest even), two per v_cvt_pk_bf16_f32
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ bf16x4 bf16_pack4(float a, float b, float c, float d) {
+  const bf16x2_t lo = __builtin_convertvector((f32x2_t){a, b}, bf16x2_t);
+  const bf16x2_t hi = __builtin_convertvector((f32x2_t){c, d}, bf16x2_t);
+  typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+  const u32x2_t w = {__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi)};
+  return __builtin_bit_cast(bf16x4, w);
+}
+
+// ReLU of four BF16 values (two v_pk_max_i16).  BF16 rounding keeps the
+// sign, so this equals rounding the FP32 ReLU.
+__device__ __forceinline__ bf16x4 act_bf16x4(bf16x4 v) { return __builtin_elementwise_max(v, (bf16x4){0, 0, 0, 0}); }
 
 // Row of output unit of accumulator register r in lane l of a 32x32 block.
 __device__ __forceinline__ int mfma_row(int r, int half) { return (r >> 2) * 8 + half * 4 + (r & 3); }
@@ -184,23 +188,36 @@ __device__ __forceinline__ void mlp_wave(const float4* sX, const uint16_t* sW, c
     const float4 x = sX[slot0 + jb * 32 + col];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
+      float h[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int u = 8 * s + 4 * half + q;
-        const float* w1 = sP + kCW1 + u * kMlpIn;
-        const float z = sP[kCB1 + u] + w1[0] * x.x + w1[1] * x.y + w1[2] * x.z + w1[3] * x.w;
-        bop[s][q] = bf16_bits(gelu_f(z));
+        const float4 w1 = *reinterpret_cast<const float4*>(sP + kCW1 + u * kMlpIn);
+        float z = fmaf(w1.x, x.x, sP[kCB1 + u]);
+        z = fmaf(w1.y, x.y, z);
+        z = fmaf(w1.z, x.z, z);
+        h[q] = fmaf(w1.w, x.w, z);
       }
+      bop[s] = act_bf16x4(bf16_pack4(h[0], h[1], h[2], h[3]));
     }
     // layers 2 and 3
     f32x16 acc[2];
 #pragma unroll
     for (int layer = 0; layer < 2; ++layer) {
       const uint16_t* W = sW + layer * kMlpHid * kWPad;
+      // the accumulators start from the bias: registers 4g..4g+3 of block ib
+      // hold rows ib 32 + 8g + 4 half + (0..3), four consecutive units
+      const float* bias = sP + (layer == 0 ? kCB2 : kCB3);
 #pragma unroll
       for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[ib][r] = 0.f;
+        for (int g = 0; g < 4; ++g) {
+          const float4 b = *reinterpret_cast<const float4*>(bias + ib * 32 + 8 * g + 4 * half);
+          acc[ib][4 * g + 0] = b.x;
+          acc[ib][4 * g + 1] = b.y;
+          acc[ib][4 * g + 2] = b.z;
+          acc[ib][4 * g + 3] = b.w;
+        }
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
 #pragma unroll
@@ -209,11 +226,6 @@ __device__ __forceinline__ void mlp_wave(const float4* sX, const uint16_t* sW, c
           acc[ib] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bop[s], acc[ib], 0, 0, 0);
         }
       }
-      const float* bias = sP + (layer == 0 ? kCB2 : kCB3);
-#pragma unroll
-      for (int ib = 0; ib < 2; ++ib)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[ib][r] = gelu_f(acc[ib][r] + bias[ib * 32 + mfma_row(r, half)]);
       if (layer == 0) {
         // accumulator rows 8(r/4) + 4 half + r%4 of block ib are exactly the
         // units of k-step 4 ib + r/4 of the next layer's B operand
@@ -221,8 +233,13 @@ __device__ __forceinline__ void mlp_wave(const float4* sX, const uint16_t* sW, c
         for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
           for (int s = 0; s < 4; ++s)
+            bop[4 * ib + s] = act_bf16x4(
+                bf16_pack4(acc[ib][4 * s], acc[ib][4 * s + 1], acc[ib][4 * s + 2], acc[ib][4 * s + 3]));
+      } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) bop[4 * ib + s][q] = bf16_bits(acc[ib][4 * s + q]);
+        for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[ib][r] = act_f(acc[ib][r]);
       }
     }
     // layer 4: FP32 dot over this lane's 32 units, then across the half-waves
@@ -246,20 +263,25 @@ __device__ __forceinline__ void mlp_wave(const float4* sX, const uint16_t* sW, c
 
 // Stage the parameters the network reads from LDS: W2, W3 as BF16 with
 // padded rows, and W1, b1, b2, b3, W4, b4 as FP32 in the compact block.
+// W2 and W3 move 8 values (16 bytes) per load; w is 16-byte aligned and both
+// blocks start at multiples of 8 values.
 __device__ __forceinline__ void mlp_stage_params(const uint16_t* __restrict__ w, uint16_t* sW, float* sP) {
-  for (int k = threadIdx.x; k < 2 * kMlpHid * kMlpHid; k += blockDim.x) {
-    const int l = k / (kMlpHid * kMlpHid), rem = k - l * kMlpHid * kMlpHid;
-    const int r = rem / kMlpHid, cc = rem - r * kMlpHid;
-    sW[l * kMlpHid * kWPad + r * kWPad + cc] = w[(l ? kOffW3 : kOffW2) + rem];
+  static_assert(kOffW2 % 8 == 0 && kOffW3 % 8 == 0 && kMlpHid % 8 == 0 && kWPad % 4 == 0, "staging layout");
+  constexpr int CH = kMlpHid / 8;  // 16-byte chunks per row
+  for (int k = threadIdx.x; k < 2 * kMlpHid * CH; k += blockDim.x) {
+    const int l = k / (kMlpHid * CH), r = (k / CH) % kMlpHid, cc = k % CH;
+    const uint4 v = *reinterpret_cast<const uint4*>(w + (l ? kOffW3 : kOffW2) + r * kMlpHid + 8 * cc);
+    uint2* dst = reinterpret_cast<uint2*>(sW + l * kMlpHid * kWPad + r * kWPad + 8 * cc);
+    dst[0] = make_uint2(v.x, v.y);
+    dst[1] = make_uint2(v.z, v.w);
   }
+  // the compact block is three contiguous runs of the parameter array:
+  // W1 b1 | b2 | b3 W4 b4
+  static_assert(kCW1 == kOffW1 && kCB1 == kOffB1 && kOffB4 == kOffW4 + kMlpOut * kMlpHid &&
+                    kOffW4 == kOffB3 + kMlpHid && kCW4 == kCB3 + kMlpHid,
+                "compact block layout");
   for (int k = threadIdx.x; k < kCSmall; k += blockDim.x) {
-    int src;
-    if (k < kCB1) src = kOffW1 + k;
-    else if (k < kCB2) src = kOffB1 + (k - kCB1);
-    else if (k < kCB3) src = kOffB2 + (k - kCB2);
-    else if (k < kCW4) src = kOffB3 + (k - kCB3);
-    else if (k < kCB4) src = kOffW4 + (k - kCW4);
-    else src = kOffB4 + (k - kCB4);
+    const int src = k < kCB2 ? k : (k < kCB3 ? kOffB2 + (k - kCB2) : kOffB3 + (k - kCB3));
     sP[k] = bf16_to_f32(w[src]);
   }
 }
@@ -277,7 +299,7 @@ closure_kernel(const double* __restrict__ U, float* __restrict__ Sc, MeshArgs ms
   __shared__ float4 sX[kClosureThreads];
   __shared__ float sN[DIM][kClosureThreads];
   __shared__ __attribute__((aligned(16))) uint16_t sW[2 * kMlpHid * kWPad];
-  __shared__ float sP[kCSmall];
+  __shared__ __attribute__((aligned(16))) float sP[kCSmall];
   mlp_stage_params(ca.w, sW, sP);
   const int t = threadIdx.x;
   const long long S = msh.S;

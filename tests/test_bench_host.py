@@ -61,5 +61,9 @@ def test_counter_record_only_for_its_own_shape():
     """The committed counter record is reported only for its workload,
     precision and launch shape."""
     assert bench.counter_traffic("2d-droplets", "fp64", (0, 3)) is None
-    assert bench.counter_traffic("3d-collision", "mixed", (0, 3)) is None
     assert bench.counter_traffic("3d-collision", "fp64", (1, 5)) is None
+    assert bench.counter_traffic("3d-collision", "mixed", (1, 5)) is None
+    # each precision gets its own record, where one exists
+    f, m = (bench.counter_traffic("3d-collision", p, (0, 3)) for p in ("fp64", "mixed"))
+    if f is not None and m is not None:
+        assert f["source"] != m["source"] and "fp64" in f["source"] and "mixed" in m["source"]

@@ -22,17 +22,16 @@ def test_parameter_count(O):
     assert NPARAM == O.MLP_NPARAM == O.lib().or_mlp_nparam() == 8770
 
 
-def test_gelu_values_and_identity(O):
-    # g(z) = z Phi(z): g(1) = Phi(1), the standard normal CDF at 1
-    assert O.gelu(1.0) == pytest.approx(0.8413447460685429, rel=0, abs=1e-15)
-    assert O.gelu(0.0) == 0.0
-    assert O.gelu_d(0.0) == pytest.approx(0.5, abs=1e-16)
+def test_relu_values_and_identity(O):
+    assert O.relu(1.0) == 1.0 and O.relu(-1.0) == 0.0 and O.relu(0.0) == 0.0
+    # the derivative at the kink is taken as 0, on both sides of the boundary
+    assert O.relu_d(0.0) == 0.0 and O.relu_d(0.3) == 1.0 and O.relu_d(-0.3) == 0.0
     for z in (-3.2, -0.7, 0.1, 0.9, 2.5, 6.0):
-        # Phi(z) + Phi(-z) = 1  =>  g(z) - g(-z) = z
-        assert O.gelu(z) - O.gelu(-z) == pytest.approx(z, abs=1e-15)
+        # g(z) - g(-z) = z, the identity the routing network below relies on
+        assert O.relu(z) - O.relu(-z) == z
         h = 1e-5
-        fd = (O.gelu(z + h) - O.gelu(z - h)) / (2 * h)
-        assert O.gelu_d(z) == pytest.approx(fd, rel=1e-8, abs=1e-10)
+        fd = (O.relu(z + h) - O.relu(z - h)) / (2 * h)
+        assert O.relu_d(z) == pytest.approx(fd, rel=1e-8, abs=1e-10)
 
 
 def routing_network():
