@@ -26,6 +26,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "dg_kernels.hpp"
 
 namespace nsk {
@@ -79,10 +81,19 @@ struct ClosureShape {
   static constexpr int SLOTS = EPB * NN;
 };
 
-__device__ __forceinline__ int elem_index_dir(const MeshArgs& m, long long e, int d) {
-  if (d == 0) return int(e % m.nel[0]);
-  if (d == 1) return int((e / m.nel[0]) % m.nel[1]);
-  return int(e / ((long long)m.nel[0] * m.nel[1]));
+// Element coordinates (x fastest).  A context holds at most 2^30 elements,
+// so 32-bit unsigned division suffices: two divisions for all directions.
+template <int DIM>
+__device__ __forceinline__ void elem_coords(const MeshArgs& m, long long e, int ic[DIM]) {
+  const unsigned eu = unsigned(e), n0 = unsigned(m.nel[0]);
+  const unsigned q0 = eu / n0;
+  ic[0] = int(eu - q0 * n0);
+  if constexpr (DIM > 1) {
+    const unsigned n1 = unsigned(m.nel[1]);
+    const unsigned q1 = q0 / n1;
+    ic[1] = int(q0 - q1 * n1);
+    if constexpr (DIM > 2) ic[2] = int(q1);
+  }
 }
 
 // Per node thread t < SLOTS: gradient, unit direction and features of the
@@ -99,6 +110,8 @@ __device__ __forceinline__ void closure_features(int t, long long e, bool active
   __syncthreads();
   double g[DIM], h2[DIM];
   double gg = 0.0;
+  int ic[DIM];
+  elem_coords<DIM>(msh, active ? e : 0, ic);
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     g[d] = 0.0;
@@ -107,7 +120,7 @@ __device__ __forceinline__ void closure_features(int t, long long e, bool active
       const int sd = dstride<NP>(d);
       const int i = (n / sd) % NP;
       const int base = el * NN + n - i * sd;
-      h2[d] = msh.h2[d][elem_index_dir(msh, e, d)];
+      h2[d] = msh.h2[d][ic[d]];
       double s = 0.0;
 #pragma unroll
       for (int j = 0; j < NP; ++j) s += ca.D[i][j] * sRho[base + j * sd];
@@ -289,6 +302,15 @@ __device__ __forceinline__ void mlp_stage_params(const uint16_t* __restrict__ w,
 // ---- inference kernels -----------------------------------------------------------
 // Closure source of every node of the mesh: Sc[d] = out_m y0 n_d (d < DIM),
 // Sc[DIM] = out_c y1, FP32, layout [comp][elem][node].
+//
+// Persistent: a grid of (at most) as many workgroups as fit on the device at
+// once, each staging the parameters into LDS once and then taking blocks of
+// EPB elements gridDim.x apart.  Every block passes three barriers (two in
+// the features, one before the network), so a block's LDS writes cannot
+// overtake the previous block's reads: the writes of sRho come after the
+// previous block's network, and those of sDer, sX and sN after this block's
+// first barrier, which every thread reaches only when done with the
+// previous block.
 template <int DIM, int NP>
 __global__ void __launch_bounds__(kClosureThreads)
 closure_kernel(const double* __restrict__ U, float* __restrict__ Sc, MeshArgs msh, ClosureArgs ca) {
@@ -303,28 +325,56 @@ closure_kernel(const double* __restrict__ U, float* __restrict__ Sc, MeshArgs ms
   mlp_stage_params(ca.w, sW, sP);
   const int t = threadIdx.x;
   const long long S = msh.S;
-  const long long e = (long long)blockIdx.x * CS::EPB + t / NN;
-  const bool active = t < SLOTS && e < msh.E;
-  const long long o = active ? e * NN + (t - (t / NN) * NN) : 0;
-  const double rho = active ? U[o] : 0.0;
-  const double c = active ? U[(DIM + 1) * S + o] : 0.0;
-  float x[4];
-  double nv[DIM];
-  closure_features<DIM, NP>(t, e, active, rho, c, msh, ca, sRho, sDer, x, nv);
-  sX[t] = make_float4(x[0], x[1], x[2], x[3]);
+  const long long nblk = (msh.E + CS::EPB - 1) / CS::EPB;
+  for (long long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const long long e = blk * CS::EPB + t / NN;
+    const bool active = t < SLOTS && e < msh.E;
+    const long long o = active ? e * NN + (t - (t / NN) * NN) : 0;
+    const double rho = active ? U[o] : 0.0;
+    const double c = active ? U[(DIM + 1) * S + o] : 0.0;
+    float x[4];
+    double nv[DIM];
+    closure_features<DIM, NP>(t, e, active, rho, c, msh, ca, sRho, sDer, x, nv);
+    sX[t] = make_float4(x[0], x[1], x[2], x[3]);
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) sN[d][t] = float(nv[d]);
-  __syncthreads();
-  // every wave runs the network on its 64 slots (inactive slots compute on
-  // zero features and are not written)
-  float y[2];
-  mlp_wave(sX, sW, sP, (t >> 6) << 6, y);
-  if (active) {
-    const float sm = ca.out_m * y[0];
+    for (int d = 0; d < DIM; ++d) sN[d][t] = float(nv[d]);
+    __syncthreads();
+    // every wave runs the network on its 64 slots (inactive slots compute on
+    // zero features and are not written)
+    float y[2];
+    mlp_wave(sX, sW, sP, (t >> 6) << 6, y);
+    if (active) {
+      const float sm = ca.out_m * y[0];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) Sc[d * S + o] = sm * sN[d][t];
-    Sc[DIM * S + o] = ca.out_c * y[1];
+      for (int d = 0; d < DIM; ++d) Sc[d * S + o] = sm * sN[d][t];
+      Sc[DIM * S + o] = ca.out_c * y[1];
+    }
   }
+}
+
+// Grid of closure_kernel for nblk blocks: the workgroups that fit on the
+// current device at once (occupancy query, cached per instantiation; every
+// device of the library is a gfx950), at most nblk.
+template <int DIM, int NP>
+inline unsigned closure_grid(long long nblk) {
+  static std::atomic<int> cached{0};
+  int per_cu = cached.load(std::memory_order_relaxed);
+  if (per_cu <= 0) {
+    // a failed query gives one workgroup per CU for this launch (still
+    // correct: the blocks are walked in a loop) and is asked again next time
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, closure_kernel<DIM, NP>, kClosureThreads, 0) ==
+            hipSuccess &&
+        per_cu > 0)
+      cached.store(per_cu, std::memory_order_relaxed);
+    else
+      per_cu = 1;
+  }
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                               hipSuccess || cus <= 0)
+    cus = 1;
+  const long long g = (long long)per_cu * cus;
+  return (unsigned)(nblk < g ? nblk : g);
 }
 
 // ---- nudging step: training pairs -------------------------------------------------

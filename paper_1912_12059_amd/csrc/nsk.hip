@@ -162,10 +162,9 @@ int launch_stage_e(nsk_ctx* c, const double* Uin, double* Uout, double* dU, cons
     const bool fresh = c->cl_every_stage || c->cl_stage <= 0;
     using CS = ClosureShape<DIM, NP>;
     float* Sc = reinterpret_cast<float*>(c->work + c->off_cl);
-    const unsigned cblocks = (unsigned)((c->E + CS::EPB - 1) / CS::EPB);
     if (fresh)
-      hipLaunchKernelGGL((closure_kernel<DIM, NP>), dim3(cblocks), dim3(kClosureThreads), 0, c->stream, Uin, Sc,
-                         mesh_args(c), closure_args_of(c));
+      hipLaunchKernelGGL((closure_kernel<DIM, NP>), dim3(closure_grid<DIM, NP>((c->E + CS::EPB - 1) / CS::EPB)),
+                         dim3(kClosureThreads), 0, c->stream, Uin, Sc, mesh_args(c), closure_args_of(c));
     sta.closure = Sc;
   }
   if (ev) (void)hipEventRecord(ev[2], c->stream);
