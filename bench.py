@@ -765,6 +765,12 @@ def _timed_steps(s, dt: float, steps: int) -> float:
     return e0.elapsed_time(e1)
 
 
+def dof_stage_rate(dofs: int, steps: int, seconds: float) -> float:
+    """DOF-stage updates per second of `steps` five-stage steps over `dofs`
+    nodes taking `seconds`."""
+    return dofs * 5 * steps / seconds
+
+
 def run_small_configs(nsk, with_oracle: bool = True) -> dict:
     """The 1D slab workload (64 elements, N = 3, alpha = 500: a launch-latency
     case, 256 nodes) in microseconds per step over its 2000 steps, with the
@@ -789,7 +795,7 @@ def run_small_configs(nsk, with_oracle: bool = True) -> dict:
         res[f"us_per_step_{name}"] = 1e3 * ms / 2000
         res["dt"] = dt
         s.close()
-    res["value"] = 256 * 5 * 1e3 / res["us_per_step_graph"]
+    res["value"] = dof_stage_rate(256, 1, 1e-6 * res["us_per_step_graph"])
     res["unit"] = "DOF-stage/s"
     if with_oracle:
         O = oracle()
@@ -797,7 +803,7 @@ def run_small_configs(nsk, with_oracle: bool = True) -> dict:
         t0 = time.perf_counter()
         O.run(P, U, res["dt"], 2000)
         el = time.perf_counter() - t0
-        res["oracle"] = {"us_per_step": 1e6 * el / 2000, "value": 256 * 5 * 2000 / el,
+        res["oracle"] = {"us_per_step": 1e6 * el / 2000, "value": dof_stage_rate(256, 2000, el),
                          "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))}
     out["1d_slab"] = res
     m, U = I.droplets_2d()
@@ -813,7 +819,7 @@ def run_small_configs(nsk, with_oracle: bool = True) -> dict:
         s.set_state(U0)
         ms = _timed_steps(s, dt, 200)
         r = {"workload": f"2d-droplets 96x96 N=4 alpha={alpha:g} beta=1e-3 eps=1e-3 kappa=1e-5", "dofs": dofs,
-             "value": dofs * 5 * 200 / (ms * 1e-3), "unit": "DOF-stage/s", "ms_per_step": ms / 200, "dt": dt,
+             "value": dof_stage_rate(dofs, 200, ms * 1e-3), "unit": "DOF-stage/s", "ms_per_step": ms / 200, "dt": dt,
              "tile": {"variant": variant, "order": order}}
         s.close()
         if with_oracle:
@@ -822,7 +828,7 @@ def run_small_configs(nsk, with_oracle: bool = True) -> dict:
             t0 = time.perf_counter()
             O.run(P, U, dt, 40)
             el = time.perf_counter() - t0
-            r["oracle"] = {"value": dofs * 5 * 40 / el, "steps": 40,
+            r["oracle"] = {"value": dof_stage_rate(dofs, 40, el), "steps": 40,
                            "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))}
         out[f"2d_droplets_alpha{int(alpha)}"] = r
     return out

@@ -6,6 +6,7 @@ import subprocess
 import sys
 
 import numpy as np
+import pytest
 
 REPO = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, REPO)
@@ -67,3 +68,11 @@ def test_counter_record_only_for_its_own_shape():
     f, m = (bench.counter_traffic("3d-collision", p, (0, 3)) for p in ("fp64", "mixed"))
     if f is not None and m is not None:
         assert f["source"] != m["source"] and "fp64" in f["source"] and "mixed" in m["source"]
+
+
+def test_dof_stage_rate_units():
+    """256 nodes, five stages per step, 34.5 microseconds per step: 3.71e7
+    DOF-stage updates per second (the 1D slab workload's figures)."""
+    assert bench.dof_stage_rate(256, 1, 34.5e-6) == pytest.approx(256 * 5 / 34.5e-6, rel=1e-12)
+    assert bench.dof_stage_rate(256, 1, 34.5e-6) == pytest.approx(3.71e7, rel=1e-3)
+    assert bench.dof_stage_rate(230400, 200, 0.0352) == pytest.approx(6.545e9, rel=1e-3)
