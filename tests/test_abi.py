@@ -188,6 +188,16 @@ def test_closure_host_side_checks():
             nsk.nsk_closure_set(cl, fake, dict(norm, k2=float("inf")))
         with pytest.raises(nsk.NskError):
             nsk.nsk_closure_set(cl, fake, norm, 2)  # every_stage must be 0 or 1
+        # the parameters are staged 16 bytes at a time: a misaligned pointer
+        # is refused, an aligned one accepted (it is only stored)
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_closure_set(cl, fake + 2, norm)
+        assert e.value.code == nsk.NSK_EINVAL
+        nsk.nsk_closure_set(cl, fake, norm)
+        with pytest.raises(nsk.NskError) as e:
+            nsk.nsk_mlp_forward(fake + 8, 0, 0, 0, 0)
+        assert e.value.code == nsk.NSK_EINVAL
+        nsk.nsk_mlp_forward(fake, 0, 0, 0, 0)  # nothing to do
         with pytest.raises(nsk.NskError) as e:
             nsk.nsk_closure_nudge(cl, norm, fake, 1e-6, 1e-4, 10.0, 0, 0)
         assert e.value.code == nsk.NSK_EUNBOUND
