@@ -221,6 +221,41 @@ def test_closure_source_in_rhs(O, gpu, dim, N, nel):
     cl.close()
 
 
+def test_closure_source_persistent_walk(O, gpu):
+    """The closure kernel runs a grid of resident workgroups, each walking
+    blocks of two elements.  On 31x13x9 = 3627 elements (1814 blocks, the last
+    with one element) every workgroup takes at least two blocks: at most 4
+    workgroups fit per CU (35 KB of LDS), 1024 on the 256 CUs.  A block
+    skipped, repeated or written to the wrong place is an O(1) error in the
+    source; the network's rounding averages to a few 1e-3 over these 453k
+    nodes."""
+    from paper_1912_12059_amd import closure as CL
+    from paper_1912_12059_amd import inputs as I
+
+    dim, N, nel = 3, 4, (31, 13, 9)
+    assert (nel[0] * nel[1] * nel[2] + 1) // 2 > 4 * 256
+    _, U = I.smooth_random(dim, N, nel, seed=23)
+    w = CL.init_params(seed=4)
+    w[np.arange(NPARAM) % 7 == 0] += 0.05
+    net = _net(gpu, w)
+    phys = dict(dim=dim, N=N, nel=nel, alpha=200.0, kappa=1e-4)
+    plain = gpu.Solver(**phys)
+    cl = CL.closure_solver(net, NORM, **phys)
+    d = cl.rhs(U).cpu().numpy() - plain.rhs(U).cpu().numpy()
+    P = O.Problem(dim=dim, N=N, nel=nel, alpha=200.0, kappa=1e-4)
+    Sc = O.closure_source(P, U, net.bf16_values(), NORM)
+    assert np.all(d[0] == 0.0)
+    for v in range(1, dim + 2):
+        err = d[v] - Sc[v]
+        rel_max = np.abs(err).max() / np.abs(Sc[v]).max()
+        rel_rms = np.sqrt((err ** 2).mean() / (Sc[v] ** 2).mean())
+        record("closure source, max error / max source (persistent walk)", rel_max, 5e-2)
+        record("closure source, RMS error / RMS source (persistent walk)", rel_rms, 1e-2)
+        assert rel_max <= 5e-2 and rel_rms <= 1e-2, (v, rel_max, rel_rms)
+    plain.close()
+    cl.close()
+
+
 def test_closure_once_per_step(gpu):
     """With a source that does not depend on the state (c output only,
     constant), evaluating the closure once per step must give the bits of
