@@ -773,11 +773,13 @@ def dof_stage_rate(dofs: int, steps: int, seconds: float) -> float:
 
 def run_small_configs(nsk, with_oracle: bool = True) -> dict:
     """The 1D slab workload (64 elements, N = 3, alpha = 500: a launch-latency
-    case, 256 nodes) in microseconds per step over its 2000 steps, with the
-    steps replayed as a captured graph (non-null stream) and launched stage
-    by stage; and the 2D droplet workload (96^2, N = 4, 230,400 nodes) rate
-    at alpha = 500 and 2000 over 200 steps.  The oracle is timed beside each:
-    the full 2000 1D steps, 40 steps in 2D."""
+    case, 256 nodes) in microseconds per step over its 2000 steps: all steps
+    in one launch (the mesh fits one workgroup of the first tile variant; the
+    default), and, on the second variant (two workgroups), replayed as a
+    captured graph (non-null stream) and launched stage by stage; and the 2D
+    droplet workload (96^2, N = 4, 230,400 nodes) rate at alpha = 500 and
+    2000 over 200 steps.  The oracle is timed beside each: the full 2000 1D
+    steps, 40 steps in 2D."""
     import torch
 
     from paper_1912_12059_amd import inputs as I
@@ -785,8 +787,10 @@ def run_small_configs(nsk, with_oracle: bool = True) -> dict:
     out = {}
     m, U = I.slab_1d()
     res = {"workload": "1d-slab 64 N=3 alpha=500 beta=1e-3 eps=1e-3 kappa=1e-5, 2000 steps", "dofs": 256}
-    for name, stream in (("graph", torch.cuda.Stream()), ("stagewise", None)):
+    for name, variant, stream in (("one_launch", 0, torch.cuda.Stream()), ("graph", 1, torch.cuda.Stream()),
+                                  ("stagewise", 1, None)):
         s = nsk.Solver(dim=1, N=3, nel=(64,), alpha=500.0, beta=1e-3, eps=1e-3, kappa=1e-5, stream=stream)
+        nsk.nsk_set_tile(s.ctx, variant, 0)
         s.set_state(U)
         dt = s.dt_estimate(0.5)
         _timed_steps(s, dt, 200)
@@ -795,7 +799,7 @@ def run_small_configs(nsk, with_oracle: bool = True) -> dict:
         res[f"us_per_step_{name}"] = 1e3 * ms / 2000
         res["dt"] = dt
         s.close()
-    res["value"] = dof_stage_rate(256, 1, 1e-6 * res["us_per_step_graph"])
+    res["value"] = dof_stage_rate(256, 1, 1e-6 * res["us_per_step_one_launch"])
     res["unit"] = "DOF-stage/s"
     if with_oracle:
         O = oracle()

@@ -857,6 +857,36 @@ rhs_kernel(const double* __restrict__ U, const GT* __restrict__ G, double* __res
                                               dU, bas, msh, ph, st);
 }
 
+// Whole Runge-Kutta steps in one launch, for meshes that one workgroup tile
+// holds (grid of one workgroup): each stage's lifting and right-hand side run
+// back to back inside the workgroup, a barrier between them (the
+// workgroup's own global writes are visible to it after a barrier), the
+// state alternating between U0 and U1 from U_cur = (cur ? U1 : U0).  The
+// same device code as the stage-by-stage kernels, so the same bits; what
+// goes is the launch latency of two kernels per stage.
+struct RkCoefs {
+  double A[5], B[5];
+};
+
+template <int DIM, int NP, int EPB, typename R, typename GT, int FLUX>
+__global__ void __launch_bounds__((Tile<DIM, NP, EPB>::THREADS))
+steps_kernel(double* U0, double* U1, GT* G, double* dU, BasisArgs bas, MeshArgs msh, PhysArgs ph, RkCoefs rk,
+             double dt, int nsteps, int cur) {
+  for (int step = 0; step < nsteps; ++step) {
+#pragma nounroll
+    for (int s = 0; s < 5; ++s) {
+      const double* Uin = cur ? U1 : U0;
+      double* Uout = cur ? U0 : U1;
+      lift_block<DIM, NP, EPB, R, GT>(0, threadIdx.x, Uin, G, bas, msh, ph);
+      __syncthreads();
+      StageArgs st{rk.A[s], rk.B[s], dt, 1};
+      rhs_block<DIM, NP, EPB, R, GT, FLUX, 0>(0, threadIdx.x, Uin, G, Uout, dU, bas, msh, ph, st);
+      __syncthreads();
+      cur ^= 1;
+    }
+  }
+}
+
 // Original NSK path: the first lifting, which also writes the workgroup's
 // maximum of the global Lax-Friedrichs speed to lfpart[logical block] (when
 // lfpart is set) ...

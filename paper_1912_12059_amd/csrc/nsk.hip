@@ -289,6 +289,69 @@ bool variants_coincide(int dim, int N) {
   return dim == 1 ? variants_coincide_dim<1>(N) : dim == 2 ? variants_coincide_dim<2>(N) : variants_coincide_dim<3>(N);
 }
 
+// Whole steps in one launch of one workgroup: 1D model II meshes (FP64 or
+// mixed, Rusanov or HLLC, no closure, no sub-cells) that the first tile
+// variant holds in one workgroup, unless per-stage timing is on.
+template <int NP, typename R, typename GT>
+int launch_steps_t(nsk_ctx* c, double dt, int nsteps) {
+  constexpr int EPB = Epb<1, NP>::V0;
+  using Tl = Tile<1, NP, EPB>;
+  RkCoefs rk;
+  for (int s = 0; s < 5; ++s) {
+    rk.A[s] = kRkA[s];
+    rk.B[s] = kRkB[s];
+  }
+  GT* G = reinterpret_cast<GT*>(c->work + c->off_G);
+  if (c->par.flux == 1)
+    hipLaunchKernelGGL((steps_kernel<1, NP, EPB, R, GT, 1>), dim3(1), dim3(Tl::THREADS), 0, c->stream,
+                       state_buf(c, 0), state_buf(c, 1), G, c->dU, basis_args(c), mesh_args(c), phys_args(c), rk, dt,
+                       nsteps, c->cur);
+  else
+    hipLaunchKernelGGL((steps_kernel<1, NP, EPB, R, GT, 0>), dim3(1), dim3(Tl::THREADS), 0, c->stream,
+                       state_buf(c, 0), state_buf(c, 1), G, c->dU, basis_args(c), mesh_args(c), phys_args(c), rk, dt,
+                       nsteps, c->cur);
+  if (hipGetLastError() != hipSuccess) return NSK_EHIP;
+  if (nsteps & 1) c->cur = 1 - c->cur;  // five buffer swaps per step
+  return NSK_OK;
+}
+
+template <int NP>
+int launch_steps_np(nsk_ctx* c, double dt, int nsteps) {
+  if (c->par.precision == 0) return launch_steps_t<NP, double, double>(c, dt, nsteps);
+  return launch_steps_t<NP, float, float>(c, dt, nsteps);
+}
+
+int launch_steps(nsk_ctx* c, double dt, int nsteps) {
+  switch (c->np) {
+    case 2: return launch_steps_np<2>(c, dt, nsteps);
+    case 3: return launch_steps_np<3>(c, dt, nsteps);
+    case 4: return launch_steps_np<4>(c, dt, nsteps);
+    case 5: return launch_steps_np<5>(c, dt, nsteps);
+    case 6: return launch_steps_np<6>(c, dt, nsteps);
+    case 7: return launch_steps_np<7>(c, dt, nsteps);
+  }
+  return NSK_EUNSUPPORTED;
+}
+
+int epb_v0_1d(int np) {
+  switch (np) {
+    case 2: return Epb<1, 2>::V0;
+    case 3: return Epb<1, 3>::V0;
+    case 4: return Epb<1, 4>::V0;
+    case 5: return Epb<1, 5>::V0;
+    case 6: return Epb<1, 6>::V0;
+    case 7: return Epb<1, 7>::V0;
+  }
+  return 0;
+}
+
+bool steps_in_one_workgroup(const nsk_ctx* c) {
+  if (c->dim != 1 || c->par.model != 0 || c->par.subcell != 0 || c->par.closure != 0 || !c->events.empty())
+    return false;
+  if (c->tile != 0 && !variants_coincide(1, c->N)) return false;
+  return c->E <= epb_v0_1d(c->np);
+}
+
 // nsteps Runge-Kutta steps enqueued stage by stage on the bound stream
 int enqueue_steps(nsk_ctx* c, double dt, int nsteps) {
   for (int step = 0; step < nsteps; ++step) {
@@ -709,11 +772,17 @@ int nsk_rk_step(nsk_ctx* c, double dt, int nsteps) {
   if (!c || nsteps < 0 || !(dt > 0.0) || !std::isfinite(dt)) return NSK_EINVAL;
   if (!c->bound) return NSK_EUNBOUND;
   if (c->par.closure == 1 && !c->cl_w) return NSK_EINVAL;  // closure enabled, no network set
-  // Pairs of steps replay one captured graph (ten stages bring the state
-  // back to the buffer it started in); the null stream cannot be captured,
-  // and timed stages record events between the launches.
+  // A mesh that one workgroup holds runs all its steps in one launch.
+  // Otherwise pairs of steps replay one captured graph (ten stages bring the
+  // state back to the buffer it started in); the null stream cannot be
+  // captured, and timed stages record events between the launches.
   int left = nsteps;
-  if (nsteps >= 2 && c->stream != nullptr && c->events.empty()) {
+  if (nsteps > 0 && steps_in_one_workgroup(c)) {
+    // the whole mesh in one workgroup: all steps in one launch
+    const int rc = launch_steps(c, dt, nsteps);
+    if (rc) return rc;
+    left = 0;
+  } else if (nsteps >= 2 && c->stream != nullptr && c->events.empty()) {
     const std::vector<unsigned char> key = step_graph_key(c, dt);
     if (!c->graph_exec || key != c->graph_key) {
       int rc = build_step_graph(c, dt);

@@ -95,3 +95,37 @@ def test_graph_replay_with_closure(gpu, every_stage):
     assert bool(torch.isfinite(g.get_state()).all())
     g.close()
     e.close()
+
+
+@pytest.mark.parametrize("prec,flux", [(0, 0), (0, 1), (1, 0)])
+def test_one_launch_steps_equal_staged_steps(gpu, prec, flux):
+    """The 1D slab workload (64 elements, N = 3) fits one workgroup of the
+    first tile variant, so all its steps run in one launch (on the null
+    stream and on a side stream).  The second variant takes two workgroups
+    and runs the same steps stage by stage (launches on the null stream,
+    graph replays on a side stream).  All four agree bit for bit."""
+    import torch
+
+    m, U = I.slab_1d()
+    kw = dict(dim=1, N=3, nel=(64,), alpha=500.0, beta=1e-3, eps=1e-3, kappa=1e-5, precision=prec, flux=flux)
+    one = gpu.Solver(**kw)
+    one_side = gpu.Solver(stream=torch.cuda.Stream(), **kw)
+    staged = gpu.Solver(**kw)
+    graphed = gpu.Solver(stream=torch.cuda.Stream(), **kw)
+    for s in (staged, graphed):
+        gpu.nsk_set_tile(s.ctx, 1, 0)
+    solvers = (one, one_side, staged, graphed)
+    for s in solvers:
+        s.set_state(U)
+    dt = one.dt_estimate(0.5)
+    for n in (1, 2, 5, 40):
+        for s in solvers:
+            s.rk_step(dt, n)
+        torch.cuda.synchronize()
+        ref = staged.get_state()
+        for s in (one, one_side, graphed):
+            assert torch.equal(s.get_state(), ref), n
+    fin = ref.cpu().numpy()
+    assert np.all(np.isfinite(fin)) and not np.array_equal(fin, U.reshape(fin.shape))
+    for s in solvers:
+        s.close()
