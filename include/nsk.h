@@ -209,7 +209,11 @@ int nsk_dt_estimate(nsk_ctx* ctx, double cfl, double* dt_out);
  * fourth-order low-storage Runge-Kutta scheme of Sec. 3.1 (Carpenter-Kennedy
  * 2N-storage coefficients): per stage dU <- A_s dU + dt R(U), U <- U + B_s dU,
  * fused into the right-hand-side kernel.  Asynchronous.  On return of the
- * enqueued work the state is in d_U. */
+ * enqueued work the state is in d_U.  Launch forms (all give the same bits):
+ * a 1D model II mesh that one workgroup holds (no closure, sub-cells or
+ * stage timing) runs all nsteps in one launch; otherwise, on a non-null
+ * stream, pairs of steps replay one captured graph, and the rest is launched
+ * stage by stage. */
 int nsk_rk_step(nsk_ctx* ctx, double dt, int nsteps);
 
 /* Diagnostics of the bound state (quadrature over all elements, with the
