@@ -97,7 +97,7 @@ def test_graph_replay_with_closure(gpu, every_stage):
     e.close()
 
 
-@pytest.mark.parametrize("prec,flux", [(0, 0), (0, 1), (1, 0)])
+@pytest.mark.parametrize("prec,flux", [(0, 0), (0, 1), (1, 0), (1, 1)])
 def test_one_launch_steps_equal_staged_steps(gpu, prec, flux):
     """The 1D slab workload (64 elements, N = 3) fits one workgroup of the
     first tile variant, so all its steps run in one launch (on the null
