@@ -943,7 +943,7 @@ def main() -> int:
     if args.cpu_one_thread:
         return cpu_one_thread_child(args.cpu_one_thread)
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (sharding across GPUs is designed, not implemented)", file=sys.stderr)
         return 2
     if args.copy_calibration:
         import torch
