@@ -286,7 +286,10 @@ int or_run(const or_prob* P, double* U, double dt, int nsteps, double t0, or_for
  * Sec. 2.3 acting on the same equation for c):
  *   dt = CFL * min(dt_conv, dt_mom, dt_c)
  *   dt_conv = 1 / ((2N+1) max_e sum_d max_nodes(|v_d| + a) / h_d)
- *   dt_mom  = 1 / ((2N+1)^2 max_e sum_d eps / h_d^2)        (viscous momentum)
+ *   dt_mom  = 1 / ((2N+1)^2 (4/3) (eps / rho_min) max_e sum_d 1 / h_d^2)
+ *             (viscous momentum: the stress eps (grad v + grad v^T - (2/3) div v I)
+ *             diffuses v = m / rho, fastest in the longitudinal mode and where
+ *             the density is smallest; NaN if rho_min <= 0)
  *   dt_c    = 1 / ((2N+1)^2 max_e sum_d (kappa/beta) / h_d^2 + alpha / (beta |z_R|))
  * The screened heat equation beta c_t = kappa lap c + alpha (rho - c) has real
  * negative eigenvalues: the diffusion's and the source's, which add.  Both
@@ -298,6 +301,15 @@ double or_dt(const or_prob* P, const double* U, double cfl) {
   or_geom g;
   if (or_geom_init(&g, P)) return NAN;
   const size_t S = (size_t)g.E * g.nnode;
+  /* the momentum diffuses v = m / rho: its largest rate is that of the
+     longitudinal mode, (4/3) eps / rho, taken at the smallest density */
+  double rmin = INFINITY;
+  for (size_t o = 0; o < S; ++o) rmin = fmin(rmin, U[o]);
+  if (!(rmin > 0.0)) {
+    or_geom_free(&g);
+    return NAN;
+  }
+  const double nu = (4.0 / 3.0) * P->eps / rmin;
   double lam_c = 0.0, lam_m = 0.0, lam_k = 0.0;
   for (long e = 0; e < g.E; ++e) {
     double sc = 0.0, sm = 0.0, sk = 0.0;
@@ -309,7 +321,7 @@ double or_dt(const or_prob* P, const double* U, double cfl) {
         mx = fmax(mx, wave_speed(P, d, u));
       }
       sc += mx / h;
-      sm += P->eps / (h * h);
+      sm += nu / (h * h);
       sk += (P->kappa / P->beta) / (h * h);
     }
     lam_c = fmax(lam_c, sc);

@@ -242,7 +242,8 @@ int or_nsk_run(const or_prob* P, double* U, double dt, int nsteps, double t0, or
 
 /* Time-step rule: CFL * min(dt_conv, dt_visc, dt_disp) with
  *   dt_conv = 1 / ((2N+1) lambda max_e sum_d 1/h_d), lambda the global LF speed
- *   dt_visc = 1 / ((2N+1)^2 eps max_e sum_d 1/h_d^2)
+ *   dt_visc = 1 / ((2N+1)^2 (4/3) (eps / rho_min) max_e sum_d 1/h_d^2)
+ *             (the stress diffuses v = m / rho; NaN if rho_min <= 0)
  *   dt_disp = C_disp / ((2N+1)^2 sqrt(kappa rho_max) max_e sum_d 1/h_d^2).
  * The linearised system about a state at rest has the frequencies
  * w^2 = p' k^2 + kappa rho k^4, so the capillary modes behave like a
@@ -267,12 +268,18 @@ double or_nsk_dt(const or_prob* P, const double* U, double cfl) {
     s1 = fmax(s1, a);
     s2 = fmax(s2, b);
   }
-  for (size_t o = 0; o < S; ++o) rmax = fmax(rmax, U[o]);
+  double rmin = INFINITY;
+  for (size_t o = 0; o < S; ++o) {
+    rmax = fmax(rmax, U[o]);
+    rmin = fmin(rmin, U[o]);
+  }
+  if (!(rmin > 0.0)) return NAN;
   const double N2 = 2.0 * P->N + 1.0;
   const double lam = or_nsk_lf_speed(P, U);
   double dt = INFINITY;
   if (lam > 0.0) dt = fmin(dt, 1.0 / (N2 * lam * s1));
-  if (P->eps > 0.0) dt = fmin(dt, 1.0 / (N2 * N2 * P->eps * s2));
+  /* viscous: the longitudinal mode of v = m / rho, rate (4/3) eps / rho */
+  if (P->eps > 0.0) dt = fmin(dt, 1.0 / (N2 * N2 * (4.0 / 3.0) * (P->eps / rmin) * s2));
   if (P->kappa > 0.0) dt = fmin(dt, OR_NSK_CDISP / (N2 * N2 * sqrt(P->kappa * rmax) * s2));
   return cfl * dt;
 }

@@ -171,9 +171,15 @@ def test_dt_rule_components(O):
     a = np.sqrt(np.array([O.dpressure(T, r) for r in rho.ravel()]) + 500.0 * rho.ravel())
     lam = (np.abs(U[1] / U[0]).ravel() + a).max() * 64
     assert O.dt(P2, U, 0.5) == pytest.approx(0.5 / (7 * lam), rel=1e-12)
-    # a viscous momentum limit: large eps, weak c stiffness
+    # a viscous momentum limit: large eps, weak c stiffness; the rate is that
+    # of the longitudinal mode of v = m / rho at the smallest density
     P3 = _prob(O, m, alpha=500.0, beta=10.0, eps=5.0, kappa=1e-5)
-    assert O.dt(P3, U, 0.5) == pytest.approx(0.5 / (49 * 5.0 * 64 ** 2), rel=1e-12)
+    nu = (4.0 / 3.0) * 5.0 / U[0].min()
+    assert O.dt(P3, U, 0.5) == pytest.approx(0.5 / (49 * nu * 64 ** 2), rel=1e-12)
+    # no step for a state without positive density
+    Ubad = U.copy()
+    Ubad[0].flat[7] = -0.1
+    assert np.isnan(O.dt(P, Ubad, 0.5))
 
 
 def _jacobian(O, P, U0, h=1e-7):
@@ -194,7 +200,8 @@ def _max_amplification(O, z):
     return (np.abs(np.polyval(g[::-1], z)) / np.maximum(1.0, np.exp(z.real))).max()
 
 
-# (dim, elements per direction, N, alpha, kappa, state); beta = eps = 1e-3
+# (dim, elements per direction, N, alpha, kappa, state[, eps, beta]);
+# beta = eps = 1e-3 unless given
 DT_CASES = {
     # source and c-diffusion bounds equal to 0.5% (h = 1/73, N = 4, alpha = 200)
     "coinciding_liquid": (1, 73, 4, 200.0, 1e-4, "liquid"),
@@ -203,12 +210,16 @@ DT_CASES = {
     "source_limited_1d_workload": (1, 64, 3, 500.0, 1e-5, "liquid"),
     "source_limited_2d": (2, 6, 3, 200.0, 1e-4, "liquid"),
     "interface_moving": (1, 40, 4, 200.0, 1e-4, "interface"),
+    # the planar-interface parameters of Sec. 4.1.1 (eps = beta = 0.01,
+    # alpha = 100) in the vapour: the viscous momentum bound is the active one
+    "viscous_limited_vapour": (1, 128, 3, 100.0, 1e-4, "vapour", 0.01, 0.01),
 }
 
 
 def _dt_case(O, name):
-    dim, E, N, alpha, kappa, state = DT_CASES[name]
-    P = O.Problem(dim=dim, N=N, nel=(E, E if dim > 1 else 1, 1), alpha=alpha, beta=1e-3, eps=1e-3, kappa=kappa)
+    dim, E, N, alpha, kappa, state = DT_CASES[name][:6]
+    eps, beta = DT_CASES[name][6:] if len(DT_CASES[name]) > 6 else (1e-3, 1e-3)
+    P = O.Problem(dim=dim, N=N, nel=(E, E if dim > 1 else 1, 1), alpha=alpha, beta=beta, eps=eps, kappa=kappa)
     U = np.zeros(P.shape())
     if state == "interface":
         X = O.node_coords(P)[0]
@@ -245,6 +256,28 @@ def test_dt_separate_bounds_leave_stability_region(O):
     dt_sep = min(1.0 / (N2 ** 2 * max(P.eps, P.kappa / P.beta) / h ** 2), zr * P.beta / P.alpha)
     assert _max_amplification(O, 0.5 * dt_sep * lam) > 1.5
     assert _max_amplification(O, O.dt(P, U, 0.5) * lam) <= 1 + 1e-9
+
+
+def test_dt_viscous_bound_takes_density_and_longitudinal_mode(O):
+    """The viscous stress eps (grad v + grad v^T - (2/3) div v I) diffuses
+    v = m / rho, so the momentum's largest viscous rate is (4/3) eps / rho,
+    not eps: in the vapour (rho = 0.32) 4.2 times more.  With eps alone the
+    bound leaves the stability region even at the workloads' CFL 0.5 on the
+    planar-interface parameters (the 200-element planar interface went
+    non-finite within 200 steps that way); with (4/3) eps / rho_min the rule
+    holds."""
+    P, U = _dt_case(O, "viscous_limited_vapour")
+    lam = np.linalg.eigvals(_jacobian(O, P, U))
+    h, N2, rho0 = 1.0 / 128, 7.0, 0.32
+    a = np.sqrt(O.dpressure(T, rho0) + P.alpha * rho0)
+    dtc = 1.0 / (N2 * a / h)
+    dtk = 1.0 / (N2 ** 2 * (P.kappa / P.beta) / h ** 2 + P.alpha / (P.beta * O.lsrk_real_limit()))
+    dtm = 1.0 / (N2 ** 2 * (4.0 / 3.0) * P.eps / rho0 / h ** 2)
+    assert O.dt(P, U, 0.5) == pytest.approx(0.5 * min(dtc, dtm, dtk), rel=1e-12)
+    assert dtm < min(dtc, dtk)  # the viscous bound is the active one
+    dt_eps_only = min(dtc, 1.0 / (N2 ** 2 * P.eps / h ** 2), dtk)
+    assert _max_amplification(O, 0.5 * dt_eps_only * lam) > 2.0
+    assert _max_amplification(O, O.dt(P, U, 0.85) * lam) <= 1 + 1e-9
 
 
 # --------------------------------------------------------------------------
@@ -361,7 +394,7 @@ def test_planar_interface_relaxes_to_maxwell(O):
     reports that order at t = 2); and kappa int c_x^2 over one interface tends
     to the gradient-theory surface tension sqrt(kappa) I(T)."""
     rv, rl, _, _ = O.maxwell(T)
-    E, kap = 50, 1e-4
+    E, kap = 100, 1e-4
     P = O.Problem(dim=1, N=3, nel=(E, 1, 1), eps=0.01, kappa=kap, alpha=100.0, beta=0.01)
     X = O.node_coords(P)[0]
     w = 2 * np.sqrt(kap)
@@ -380,7 +413,9 @@ def test_planar_interface_relaxes_to_maxwell(O):
     assert d["e_kin"] < 1e-6
     vap = U[0][np.abs(X - 0.0) < 0.06].mean()
     liq = U[0][np.abs(X - 0.5) < 0.06].mean()
-    assert abs(vap - rv) < 2e-3 and abs(liq - rl) < 2e-3
+    # 100 elements: 1.7e-4 and 4.1e-4 from Maxwell at t = 2, the same to two
+    # digits as at 200 elements (measured), so resolution no longer limits it
+    assert abs(vap - rv) < 1e-3 and abs(liq - rl) < 1e-3
     _, Q = O.rhs(P, U, return_Q=True)
     b = O.basis(3)
     wq = np.tile(b.w, E) / (2 * E)

@@ -281,7 +281,7 @@ def _jacobian(O, P, U0, h=1e-7):
     return J
 
 
-@pytest.mark.parametrize("case", ["liquid_N2", "liquid_N5", "vapour_2d", "interface"])
+@pytest.mark.parametrize("case", ["liquid_N2", "liquid_N5", "vapour_2d", "interface", "viscous_vapour"])
 def test_nsk_dt_rule_inside_stability_region(O, case):
     """At CFL 1 every eigenvalue z = dt lambda of the linearised operator
     satisfies |R(z)| <= max(1, exp(Re z)) for the stability polynomial R of
@@ -295,6 +295,11 @@ def test_nsk_dt_rule_inside_stability_region(O, case):
         P = O.Problem(dim=1, N=5, nel=(10, 1, 1), model=1, eps=1e-3, kappa=1e-5)
         U = np.zeros(P.shape())
         U[0] = 1.9
+    elif case == "viscous_vapour":
+        # eps = 0.02 in the vapour: the viscous bound, (4/3) eps / rho, is active
+        P = O.Problem(dim=1, N=3, nel=(24, 1, 1), model=1, eps=0.02, kappa=1e-5)
+        U = np.zeros(P.shape())
+        U[0] = 0.32
     elif case == "vapour_2d":
         P = O.Problem(dim=2, N=3, nel=(4, 4, 1), model=1, eps=1e-3, kappa=1e-4)
         U = np.zeros(P.shape())
