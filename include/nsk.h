@@ -191,18 +191,20 @@ int nsk_rhs_noalloc(nsk_ctx* ctx, const double* d_U, double* d_R, void* hip_stre
 /* Time-step estimate for the bound state, after the parabolic bound of
  * Sec. 3.1 with the relaxation source of Sec. 2.3 on the same equation:
  *   dt = cfl * min(1/((2N+1) max_e sum_d max(|v_d|+a)/h_d),
- *                  1/((2N+1)^2 eps max_e sum_d 1/h_d^2),
+ *                  1/((2N+1)^2 nu max_e sum_d 1/h_d^2),
  *                  1/((2N+1)^2 (kappa/beta) max_e sum_d 1/h_d^2 + alpha/(beta z_R)))
- * with a = sqrt(p'(rho) + alpha rho) and z_R the negative-real-axis
- * stability limit of the Runge-Kutta scheme.  The last bound is that of the
- * equation for c: its diffusion and relaxation-source rates are both real
- * and negative, so they add.  Model 1:
+ * with a = sqrt(p'(rho) + alpha rho), nu = (4/3) eps / rho_min (the viscous
+ * stress diffuses v = m / rho, fastest in the longitudinal mode and at the
+ * smallest density) and z_R the negative-real-axis stability limit of the
+ * Runge-Kutta scheme.  The last bound is that of the equation for c: its
+ * diffusion and relaxation-source rates are both real and negative, so they
+ * add.  Model 1:
  *   dt = cfl * min(1/((2N+1) lam max_e sum_d 1/h_d),
- *                  1/((2N+1)^2 eps max_e sum_d 1/h_d^2),
+ *                  1/((2N+1)^2 nu max_e sum_d 1/h_d^2),
  *                  (1/4)/((2N+1)^2 sqrt(kappa rho_max) max_e sum_d 1/h_d^2))
  * with lam the global Lax-Friedrichs speed (the last bound is that of the
  * capillary modes, frequencies sqrt(kappa rho) k^2).  Waits for the stream.
- * NSK_ENONPHYS if the state holds non-finite values. */
+ * NSK_ENONPHYS if the state holds non-finite values or a density <= 0. */
 int nsk_dt_estimate(nsk_ctx* ctx, double cfl, double* dt_out);
 
 /* Advances the bound state by nsteps steps of size dt of the five-stage,

@@ -829,8 +829,11 @@ int nsk_dt_estimate(nsk_ctx* c, double cfl, double* dt_out) {
   double h[kDiagSlots];
   int rc = run_diag(c, h);
   if (rc) return rc;
-  if (h[11] > 0.0) return NSK_ENONPHYS;
+  if (h[11] > 0.0 || !(h[8] > 0.0)) return NSK_ENONPHYS;
   const double N2 = 2.0 * c->N + 1.0;
+  // the viscous stress diffuses v = m / rho: the longitudinal mode's rate,
+  // (4/3) eps / rho, at the smallest density
+  const double nu = (4.0 / 3.0) * c->par.eps / h[8];
   if (c->par.model == 1) {
     // original NSK: convective bound with the global LF speed, viscous bound,
     // and the bound of the capillary modes (frequencies sqrt(kappa rho) k^2)
@@ -844,7 +847,7 @@ int nsk_dt_estimate(nsk_ctx* c, double cfl, double* dt_out) {
     const double lam = h[10], rmax = h[9];
     double dt = INFINITY;
     if (lam > 0.0) dt = std::fmin(dt, 1.0 / (N2 * lam * s1));
-    if (c->par.eps > 0.0) dt = std::fmin(dt, 1.0 / (N2 * N2 * c->par.eps * s2));
+    if (c->par.eps > 0.0) dt = std::fmin(dt, 1.0 / (N2 * N2 * nu * s2));
     if (c->par.kappa > 0.0) dt = std::fmin(dt, 0.25 / (N2 * N2 * std::sqrt(c->par.kappa * rmax) * s2));
     *dt_out = cfl * dt;
     return NSK_OK;
@@ -862,7 +865,7 @@ int nsk_dt_estimate(nsk_ctx* c, double cfl, double* dt_out) {
   }
   double dt = INFINITY;
   if (lam_c > 0.0) dt = std::fmin(dt, 1.0 / (N2 * lam_c));
-  if (c->par.eps > 0.0) dt = std::fmin(dt, 1.0 / (N2 * N2 * c->par.eps * s2));
+  if (c->par.eps > 0.0) dt = std::fmin(dt, 1.0 / (N2 * N2 * nu * s2));
   dt = std::fmin(dt, 1.0 / (N2 * N2 * (c->par.kappa / c->par.beta) * s2 + c->par.alpha / (c->par.beta * c->zR)));
   *dt_out = cfl * dt;
   return NSK_OK;

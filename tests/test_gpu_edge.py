@@ -93,3 +93,38 @@ def test_zero_steps_leave_the_state(gpu):
     assert st["steps"] == 0 and st["rhs_evals"] == 0
     assert np.array_equal(s.get_state().cpu().numpy(), U)
     s.close()
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_dt_estimate_viscosity_limited(O, gpu, model):
+    """Where the viscous momentum bound is the active one (eps = 0.01 on 128
+    elements, a slab of liquid in vapour), the library's step equals the
+    oracle's: the rate (4/3) eps / rho_min on both sides, for model II and
+    the original NSK path.  A state with a non-positive density gets
+    NSK_ENONPHYS."""
+    from paper_1912_12059_amd import inputs as I
+
+    nel = (128,)
+    m, U = I.slab_1d(nel=nel[0])
+    # kappa = 1e-5 keeps the original path's capillary bound below the viscous one
+    kw = dict(eps=0.01, kappa=1e-4 if model == 0 else 1e-5)
+    if model == 0:
+        kw.update(alpha=100.0, beta=0.01)
+        s = gpu.Solver(dim=1, N=3, nel=nel, **kw)
+        P = O.Problem(dim=1, N=3, nel=(nel[0], 1, 1), **kw)
+    else:
+        U = U[:2]
+        s = gpu.Solver(dim=1, N=3, nel=nel, model=1, **kw)
+        P = O.Problem(dim=1, N=3, nel=(nel[0], 1, 1), model=1, **kw)
+    s.set_state(U)
+    dt = O.dt(P, U, 0.5)
+    assert abs(s.dt_estimate(0.5) - dt) <= 1e-12 * dt
+    h = 1.0 / nel[0]
+    assert dt == pytest.approx(0.5 / (49 * (4.0 / 3.0) * 0.01 / U[0].min() / h ** 2), rel=1e-12)
+    Ubad = U.copy()
+    Ubad[0].flat[5] = -0.1
+    s.set_state(Ubad)
+    with pytest.raises(gpu.NskError) as e:
+        s.dt_estimate(0.5)
+    assert e.value.code == gpu.NSK_ENONPHYS
+    s.close()
