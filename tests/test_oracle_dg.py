@@ -213,6 +213,9 @@ DT_CASES = {
     # the planar-interface parameters of Sec. 4.1.1 (eps = beta = 0.01,
     # alpha = 100) in the vapour: the viscous momentum bound is the active one
     "viscous_limited_vapour": (1, 128, 3, 100.0, 1e-4, "vapour", 0.01, 0.01),
+    # viscous momentum and c rates within 10% of each other: they act on
+    # different variables, so the smallest of the two bounds suffices
+    "viscous_and_c_coinciding": (1, 64, 3, 10.0, 1e-4, "vapour", 0.0024, 0.01),
 }
 
 
