@@ -122,6 +122,52 @@ def test_trajectory_1d_config(O, gpu):
     assert _relerr_per_var(got, ref) <= TRAJ_TOL
 
 
+def test_planar_interface_sec411(O, gpu):
+    """The planar interface of Sec. 4.1.1 (eps = 0.01, kappa = 1e-4,
+    alpha = 100, beta = 0.01, N = 3, 100 elements on periodic (0, 1)) from
+    off-equilibrium phase densities 0.40 / 1.70, its step limited by the
+    viscous momentum bound.  The GPU trajectory equals the oracle's over the
+    first 2000 steps; run on to t = 2 (about 65,000 steps) the energy never
+    grows, the kinetic energy falls below 1e-6 and the bulk densities come
+    within 1e-3 of the Maxwell densities, as in the oracle's own pin."""
+    import torch
+
+    rv, rl, _, _ = O.maxwell(0.85)
+    E, kap = 100, 1e-4
+    phys = dict(eps=0.01, kappa=kap, alpha=100.0, beta=0.01)
+    P = O.Problem(dim=1, N=3, nel=(E, 1, 1), **phys)
+    X = O.node_coords(P)[0]
+    w = 2 * np.sqrt(kap)
+    rho = 0.40 + 0.5 * (1.70 - 0.40) * (np.tanh((X - 0.3) / w) - np.tanh((X - 0.7) / w))
+    U = np.stack([rho, 0 * rho, rho.copy()])
+    s = gpu.Solver(dim=1, N=3, nel=(E,), stream=torch.cuda.Stream(), **phys)
+    s.set_state(U)
+    dt = O.dt(P, U, 0.5)
+    assert abs(s.dt_estimate(0.5) - dt) <= 1e-12 * dt
+    s.rk_step(dt, 2000)
+    got = s.get_state().cpu().numpy()
+    ref = O.run(P, U, dt, 2000)
+    assert _relerr_per_var(got, ref) <= TRAJ_TOL
+    nsteps = int(np.ceil(2.0 / dt))
+    e_prev = s.diagnostics()["e_total"]
+    done = 2000
+    while done < nsteps:
+        k = min(1000, nsteps - done)
+        s.rk_step(dt, k)
+        done += k
+        e = s.diagnostics()["e_total"]
+        assert e <= e_prev + 1e-12 * abs(e_prev), done
+        e_prev = e
+    d = s.diagnostics()
+    assert d["status"] == 0 and d["e_kin"] < 1e-6
+    fin = s.get_state().cpu().numpy()
+    vap = fin[0][np.abs(X - 0.0) < 0.06].mean()
+    liq = fin[0][np.abs(X - 0.5) < 0.06].mean()
+    record("planar interface, |rho - Maxwell| in the bulk", max(abs(vap - rv), abs(liq - rl)), 1e-3)
+    assert abs(vap - rv) < 1e-3 and abs(liq - rl) < 1e-3
+    s.close()
+
+
 def test_trajectory_2d_droplets_small(O, gpu):
     """2D droplet geometry on a coarser 24x24 mesh, N=4, 50 steps."""
     m, U = I.droplets_2d(nel=24)
