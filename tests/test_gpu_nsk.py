@@ -231,3 +231,39 @@ def test_nsk_full_size_3d_sampled(O, gpu):
         ulps = rhs_err_ulps(got, ref, scales)
         assert ulps <= RHS_ULPS, (e, ulps)
     s.close()
+
+
+def test_relaxation_model_approaches_nsk_on_gpu(O, gpu):
+    """The Korteweg limit of Sec. 2.3 and 4.1.1 with the library's two
+    models: a slab at rest between the Maxwell densities (eps = 0.01,
+    kappa = 1e-4, beta = 0.01, N = 3, 100 elements) run to t = 0.5.  The
+    density of model II approaches that of the original NSK path as alpha
+    grows from 10 to 100 and stays as close at 1000 (oracle on the same
+    grid: 5.3e-3, 1.8e-3, 1.7e-3 in L2)."""
+    import torch
+
+    rv, rl, _, _ = O.maxwell(0.85)
+    E, kap, tend = 100, 1e-4, 0.5
+    P1 = O.Problem(dim=1, N=3, nel=(E, 1, 1), model=1, eps=0.01, kappa=kap)
+    X = O.node_coords(P1)[0]
+    w = 2 * np.sqrt(kap)
+    rho = rv + 0.5 * (rl - rv) * (np.tanh((X - 0.3) / w) - np.tanh((X - 0.7) / w))
+    wq = np.tile(O.basis(3).w, E) / (2 * E)
+
+    def run(U, **kw):
+        s = gpu.Solver(dim=1, N=3, nel=(E,), stream=torch.cuda.Stream(), eps=0.01, kappa=kap, **kw)
+        s.set_state(U)
+        n = int(np.ceil(tend / s.dt_estimate(0.5)))
+        s.rk_step(tend / n, n)
+        r = s.get_state().cpu().numpy().reshape(U.shape)[0]
+        assert s.diagnostics()["status"] == 0
+        s.close()
+        return r
+
+    r_nsk = run(np.stack([rho, 0 * rho]), model=1)
+    gap = {}
+    for alpha in (10.0, 100.0, 1000.0):
+        r2 = run(np.stack([rho, 0 * rho, rho.copy()]), alpha=alpha, beta=0.01)
+        gap[alpha] = np.sqrt(np.sum(wq * (r2 - r_nsk).ravel() ** 2))
+    assert gap[100.0] < 0.4 * gap[10.0] and gap[1000.0] <= 1.1 * gap[100.0], gap
+    assert gap[1000.0] < 2e-3, gap

@@ -318,6 +318,42 @@ def test_nsk_dt_rule_inside_stability_region(O, case):
 
 
 # --------------------------------------------------------------------------
+# Korteweg limit of the relaxation model
+# --------------------------------------------------------------------------
+def test_relaxation_model_approaches_nsk_as_alpha_grows(O):
+    """Sec. 2.3 and 4.1.1: model II tends to the original NSK equations as
+    alpha grows (c follows rho and alpha rho grad(rho - c) becomes the
+    Korteweg force).  A slab at rest between the Maxwell densities, with the
+    parameters of Sec. 4.1.1 (eps = 0.01, kappa = 1e-4, beta = 0.01, N = 3,
+    50 elements), run to t = 0.5 with the two independently written right-hand
+    sides: the density of model II at alpha = 100 is three times closer to
+    the NSK density than at alpha = 10 (measured 1.6e-3 against 5.1e-3 in
+    L2).  Larger alpha needs finer grids here: at alpha = 1000 on 100
+    elements the gap is 1.7e-3, at alpha = 1e4 on 50 elements the relaxation
+    is unresolved and the run blows up at t = 0.051 whatever the CFL."""
+    rv, rl, _, _ = O.maxwell(0.85)
+    E, kap, tend = 50, 1e-4, 0.5
+    P1 = O.Problem(dim=1, N=3, nel=(E, 1, 1), model=1, eps=0.01, kappa=kap)
+    X = O.node_coords(P1)[0]
+    w = 2 * np.sqrt(kap)
+    rho = rv + 0.5 * (rl - rv) * (np.tanh((X - 0.3) / w) - np.tanh((X - 0.7) / w))
+    wq = np.tile(O.basis(3).w, E) / (2 * E)
+
+    def run(P, U):
+        n = int(np.ceil(tend / O.dt(P, U, 0.5)))
+        return O.run(P, U, tend / n, n)
+
+    r_nsk = run(P1, np.stack([rho, 0 * rho]))[0]
+    gap = {}
+    for alpha in (10.0, 100.0):
+        P2 = O.Problem(dim=1, N=3, nel=(E, 1, 1), alpha=alpha, beta=0.01, eps=0.01, kappa=kap)
+        r2 = run(P2, np.stack([rho, 0 * rho, rho.copy()]))[0]
+        gap[alpha] = np.sqrt(np.sum(wq * (r2 - r_nsk).ravel() ** 2))
+    assert gap[100.0] < 0.4 * gap[10.0], gap
+    assert gap[100.0] < 2e-3, gap
+
+
+# --------------------------------------------------------------------------
 # planar interface and diagnostics
 # --------------------------------------------------------------------------
 def test_nsk_planar_interface_relaxes_to_maxwell(O):
