@@ -216,6 +216,8 @@ DT_CASES = {
     # viscous momentum and c rates within 10% of each other: they act on
     # different variables, so the smallest of the two bounds suffices
     "viscous_and_c_coinciding": (1, 64, 3, 10.0, 1e-4, "vapour", 0.0024, 0.01),
+    # 2D: the viscous rate (4/3)(eps/rho) sum_d 1/h_d^2 is the active one
+    "viscous_limited_2d": (2, 6, 3, 100.0, 1e-4, "vapour", 0.2, 0.01),
 }
 
 
