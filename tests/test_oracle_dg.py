@@ -263,6 +263,21 @@ def test_dt_separate_bounds_leave_stability_region(O):
     assert _max_amplification(O, O.dt(P, U, 0.5) * lam) <= 1 + 1e-9
 
 
+def test_dt_rule_convective_and_diffusive_together(O):
+    """Where the convective bound (imaginary-axis eigenvalues) and the
+    diffusion bounds (real ones) are about equal, eigenvalues with both parts
+    near their separate limits leave the region at CFL 0.85 (2.8x
+    amplification here), but at the workloads' CFL 0.5 each part is at half
+    its limit and they stay inside."""
+    P = O.Problem(dim=1, N=3, nel=(32, 1, 1), alpha=100.0, beta=0.01, eps=0.01, kappa=1e-4)
+    U = np.zeros(P.shape())
+    U[0] = 1.8
+    U[-1] = 1.8
+    lam = np.linalg.eigvals(_jacobian(O, P, U))
+    assert _max_amplification(O, O.dt(P, U, 0.85) * lam) > 2.0
+    assert _max_amplification(O, O.dt(P, U, 0.5) * lam) <= 1 + 1e-9
+
+
 def test_dt_viscous_bound_takes_density_and_longitudinal_mode(O):
     """The viscous stress eps (grad v + grad v^T - (2/3) div v I) diffuses
     v = m / rho, so the momentum's largest viscous rate is (4/3) eps / rho,
