@@ -131,3 +131,50 @@ def test_hllc_full_size_3d_sampled(O, gpu):
         ulps = rhs_err_ulps(R[:, e, :].cpu().numpy(), Rp[:, centre, :], scales)
         assert ulps <= RHS_ULPS, (e, ulps)
 
+
+
+def test_merging_droplets_sec42(O, gpu):
+    """The first 2D case of Sec. 4.2: droplets of radii 0.2 and 0.1 centred
+    at (0.4, 0.5) and (0.7, 0.5), touching at x = 0.6, between the Maxwell
+    densities (alpha = 100, beta = 0.001, eps = 0.01, kappa = 1e-4, N = 3,
+    100^2 elements, HLLC flux).  The first 100 steps equal the oracle's; run on
+    to t = 0.1 the liquid neck at x = 0.6 widens at every check as the two
+    merge, the total energy never grows and mass stays exact."""
+    import torch
+
+    E, kap = 100, 1e-4
+    rv, rl, _, _ = O.maxwell(0.85)
+    phys = dict(alpha=100.0, beta=0.001, eps=0.01, kappa=kap, flux=1)
+    P = O.Problem(dim=2, N=3, nel=(E, E, 1), **phys)
+    x, y = O.node_coords(P)[:2]
+    w = 2 * np.sqrt(kap)
+    rho = rl + sum(0.5 * (rv - rl) * np.tanh((np.hypot(x - cx, y - cy) - r) / w)
+                   for cx, cy, r in ((0.4, 0.5, 0.2), (0.7, 0.5, 0.1)))
+    U = np.stack([rho, 0 * rho, 0 * rho, rho.copy()])
+    s = gpu.Solver(dim=2, N=3, nel=(E, E), stream=torch.cuda.Stream(), **phys)
+    s.set_state(U)
+    dt = O.dt(P, U, 0.5)
+    assert abs(s.dt_estimate(0.5) - dt) <= 1e-12 * dt
+    s.rk_step(dt, 100)
+    assert _relerr_per_var(s.get_state().cpu().numpy(), O.run(P, U, dt, 100)) <= TRAJ_TOL
+    mid = 0.5 * (rl + rv)
+    line = np.abs(x - 0.6) < 0.004
+
+    def neck(V):
+        return np.ptp(y[line][V[0][line] > mid])
+
+    m0 = s.diagnostics()["mass"][0]
+    widths, energies = [neck(U)], [s.diagnostics()["e_total"]]
+    t = 100 * dt
+    for tk in (0.02, 0.05, 0.1):
+        n = int(round((tk - t) / dt))
+        s.rk_step(dt, n)
+        t += n * dt
+        d = s.diagnostics()
+        assert d["status"] == 0 and abs(d["mass"][0] / m0 - 1) < 1e-13
+        widths.append(neck(s.get_state().cpu().numpy().reshape(U.shape)))
+        energies.append(d["e_total"])
+    assert all(b > a for a, b in zip(widths, widths[1:])), widths
+    assert widths[-1] > 1.25 * widths[0], widths
+    assert all(b <= a + 1e-12 * abs(a) for a, b in zip(energies, energies[1:])), energies
+    s.close()
