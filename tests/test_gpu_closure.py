@@ -193,8 +193,13 @@ def test_nudge_matches_oracle(O, gpu, dim, N, nel):
     s.close()
 
 
-@pytest.mark.parametrize("dim,N,nel", [(2, 4, (6, 5)), (3, 4, (3, 4, 3)), (1, 5, (11,))])
-def test_closure_source_in_rhs(O, gpu, dim, N, nel):
+@pytest.mark.parametrize("dim,N,nel,opts", [(2, 4, (6, 5), {}), (3, 4, (3, 4, 3), {}), (1, 5, (11,), {}),
+                                             (2, 4, (6, 5), {"precision": 1}), (3, 3, (3, 4, 3), {"flux": 1}),
+                                             (2, 3, (5, 4), {"precision": 1, "flux": 1})])
+def test_closure_source_in_rhs(O, gpu, dim, N, nel, opts):
+    """The closure source added by the right-hand side, in FP64 after the DG
+    terms, is the difference of the closure and plain right-hand sides, for
+    both fluxes and both precisions."""
     import torch
 
     from paper_1912_12059_amd import closure as CL
@@ -204,7 +209,7 @@ def test_closure_source_in_rhs(O, gpu, dim, N, nel):
     w = CL.init_params(seed=4)
     w[np.arange(NPARAM) % 7 == 0] += 0.05  # non-zero biases: outputs are not small differences
     net = _net(gpu, w)
-    phys = dict(dim=dim, N=N, nel=nel, alpha=200.0, kappa=1e-4)
+    phys = dict(dim=dim, N=N, nel=nel, alpha=200.0, kappa=1e-4, **opts)
     plain = gpu.Solver(**phys)
     cl = CL.closure_solver(net, NORM, **phys)
     Rp = plain.rhs(U).cpu().numpy()
