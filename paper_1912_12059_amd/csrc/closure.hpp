@@ -14,8 +14,9 @@
 // Inference (closure_kernel) on gfx950: a workgroup of 256 threads takes
 // whole elements (up to 256 nodes).  Features are formed per node from the
 // densities staged in LDS; the network runs per wavefront on 64 nodes with
-// the nodes as the columns of v_mfma_f32_32x32x8bf16: layer 1 (4 -> 64) in
-// FP32 directly in the B-operand layout, layers 2 and 3 as BF16 MFMA (the
+// the nodes as the MFMA columns: layer 1 (4 -> 64) as FP32 MFMA
+// (v_mfma_f32_32x32x2f32), layers 2 and 3 as BF16 MFMA
+// (v_mfma_f32_32x32x16_bf16, the full-rate BF16 form of gfx950; the
 // accumulator layout of one layer is the B-operand layout of the next), and
 // layer 4 as an FP32 dot product finished across the two half-waves.
 //
@@ -177,6 +178,14 @@ __device__ __forceinline__ bf16x4 bf16_pack4(float a, float b, float c, float d)
 // sign, so this equals rounding the FP32 ReLU.
 __device__ __forceinline__ bf16x4 act_bf16x4(bf16x4 v) { return __builtin_elementwise_max(v, (bf16x4){0, 0, 0, 0}); }
 
+// eight BF16 values as the operand of v_mfma_f32_32x32x16_bf16
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ bf16x8 bf16_cat8(bf16x4 lo, bf16x4 hi) {
+  typedef short s16x8 __attribute__((ext_vector_type(8)));
+  const s16x8 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_bit_cast(bf16x8, v);
+}
+
 // Row of output unit of accumulator register r in lane l of a 32x32 block.
 __device__ __forceinline__ int mfma_row(int r, int half) { return (r >> 2) * 8 + half * 4 + (r & 3); }
 
@@ -189,32 +198,40 @@ __device__ __forceinline__ void mlp_wave(const float4* sX, const uint16_t* sW, c
   const int half = lane >> 5, col = lane & 31;
   y[0] = y[1] = 0.f;
   // one 32-node column block at a time keeps the live accumulators and
-  // operands to 2 x 16 + 2 x 8 registers
+  // operands to 2 x 16 + 8 x 2 registers
 #pragma nounroll
   for (int jb = 0; jb < 2; ++jb) {
     // the parameters are re-read from LDS in each block rather than held in
     // registers across blocks
     asm volatile("" ::: "memory");
-    // layer 1 in the B-operand layout: lane holds units 8s + 4 half + q of
-    // node col of this column block
-    bf16x4 bop[8];
+    // layer 1 on the FP32 matrix cores (v_mfma_f32_32x32x2f32, K = 4 inputs
+    // in two k-steps of 2: half-wave h supplies inputs h and 2 + h of node
+    // col), accumulators starting from the bias.  FP32 operands keep c - rho
+    // resolved.  Accumulator rows 8(r/4) + 4 half + r%4 of block ib are the
+    // units of k-step 4 ib + r/4 of layer 2's B operand.
     const float4 x = sX[slot0 + jb * 32 + col];
+    const float xk0 = half ? x.y : x.x, xk1 = half ? x.w : x.z;
+    f32x16 acc[2];
+    bf16x4 bop[8];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      float h[4];
+    for (int ib = 0; ib < 2; ++ib) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int u = 8 * s + 4 * half + q;
-        const float4 w1 = *reinterpret_cast<const float4*>(sP + kCW1 + u * kMlpIn);
-        float z = fmaf(w1.x, x.x, sP[kCB1 + u]);
-        z = fmaf(w1.y, x.y, z);
-        z = fmaf(w1.z, x.z, z);
-        h[q] = fmaf(w1.w, x.w, z);
+      for (int g = 0; g < 4; ++g) {
+        const float4 b = *reinterpret_cast<const float4*>(sP + kCB1 + ib * 32 + 8 * g + 4 * half);
+        acc[ib][4 * g + 0] = b.x;
+        acc[ib][4 * g + 1] = b.y;
+        acc[ib][4 * g + 2] = b.z;
+        acc[ib][4 * g + 3] = b.w;
       }
-      bop[s] = act_bf16x4(bf16_pack4(h[0], h[1], h[2], h[3]));
+      const float* w1 = sP + kCW1 + (ib * 32 + col) * kMlpIn + half;
+      acc[ib] = __builtin_amdgcn_mfma_f32_32x32x2f32(w1[0], xk0, acc[ib], 0, 0, 0);
+      acc[ib] = __builtin_amdgcn_mfma_f32_32x32x2f32(w1[2], xk1, acc[ib], 0, 0, 0);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        bop[4 * ib + s] =
+            act_bf16x4(bf16_pack4(acc[ib][4 * s], acc[ib][4 * s + 1], acc[ib][4 * s + 2], acc[ib][4 * s + 3]));
     }
     // layers 2 and 3
-    f32x16 acc[2];
 #pragma unroll
     for (int layer = 0; layer < 2; ++layer) {
       const uint16_t* W = sW + layer * kMlpHid * kWPad;
@@ -231,12 +248,16 @@ __device__ __forceinline__ void mlp_wave(const float4* sX, const uint16_t* sW, c
           acc[ib][4 * g + 2] = b.z;
           acc[ib][4 * g + 3] = b.w;
         }
+      // k-step S of 16 units pairs the B registers bop[2S], bop[2S+1] (units
+      // 16S + 4 half + (0..3) and 16S + 8 + 4 half + (0..3)) with the same
+      // units of each weight row
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
+      for (int S = 0; S < 4; ++S) {
 #pragma unroll
         for (int ib = 0; ib < 2; ++ib) {
-          const bf16x4 a = *reinterpret_cast<const bf16x4*>(W + (ib * 32 + col) * kWPad + 8 * s + 4 * half);
-          acc[ib] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bop[s], acc[ib], 0, 0, 0);
+          const uint16_t* wr = W + (ib * 32 + col) * kWPad + 16 * S + 4 * half;
+          const bf16x8 a = bf16_cat8(*reinterpret_cast<const bf16x4*>(wr), *reinterpret_cast<const bf16x4*>(wr + 8));
+          acc[ib] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bf16_cat8(bop[2 * S], bop[2 * S + 1]), acc[ib], 0, 0, 0);
         }
       }
       if (layer == 0) {
