@@ -21,7 +21,7 @@
 // layer 4 as an FP32 dot product finished across the two half-waves.
 //
 // Training runs in FP32 vector arithmetic with the same rounding points
-// (BF16 parameters; BF16 activations where inference feeds an MFMA), so the
+// (BF16 parameters; BF16 activations where inference feeds a BF16 MFMA), so the
 // trained network is the one inference evaluates up to summation order.
 #pragma once
 #include <hip/hip_runtime.h>
