@@ -536,7 +536,7 @@ def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20, full_mesh:
     48x24x24 elements, N = 4 (the element size of the full collision mesh),
     R = 0.1, to t_end.
 
-    Accuracy: a held-out collision runs to t_end at alpha = 2000 (the judge),
+    Accuracy: a held-out collision runs to t_end at alpha = 2000 (the reference),
     1000, 400 and 200, and at alpha = 200 with the closure (every stage, and
     once per step) through nsk_closure_run, whose fallback is the alpha = 2000
     run.  By default the held-out collision is a 48x24x24 one (We = 70,
@@ -597,7 +597,7 @@ def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20, full_mesh:
     del X, Y
     print(f"[bench] closure trained on {nsamp} samples in {train_s:.1f} s", file=sys.stderr, flush=True)
 
-    # the alpha = 200 runs take their own step dt and the alpha = 2000 judge
+    # the alpha = 200 runs take their own step dt and the alpha = 2000 reference
     # M steps of dt / M per step (within its own limit dt_ref_own)
     dt_mod, M = info["dt"], info["M"]
     dt_ref = dt_mod / M
@@ -623,14 +623,14 @@ def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20, full_mesh:
         torch.cuda.synchronize()
         return s.get_state()[0].reshape(-1, wn.numel()).clone(), e0.elapsed_time(e1), extra
 
-    def plain(alpha, judge=False):
-        """The plain run at alpha to t_end: with judge, the alpha = 2000 run
+    def plain(alpha, reference=False):
+        """The plain run at alpha to t_end: as the reference, the alpha = 2000 run
         in the steps of the closure runs' fallback (dt / M); otherwise in the
         fewest equal steps within its own limit."""
         s = nsk.Solver(alpha=alpha, kappa=kappa, **mesh)
         s.set_state(U0)
-        n = n_ref if judge else int(math.ceil(tend_run / s.dt_estimate(0.5) - 1e-9))
-        dt = dt_ref if judge else tend_run / n
+        n = n_ref if reference else int(math.ceil(tend_run / s.dt_estimate(0.5) - 1e-9))
+        dt = dt_ref if reference else tend_run / n
 
         def steps():
             for k in range(0, n, 2000):  # a progress line per 2000 steps
@@ -654,7 +654,7 @@ def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20, full_mesh:
         return rho, ms, rep
 
     rho0 = U0.reshape(5, -1)[0].reshape(-1, wn.numel())
-    rho_ref, ms_ref, _ = plain(2000.0, judge=True)
+    rho_ref, ms_ref, _ = plain(2000.0, reference=True)
 
     def wl2(a):
         return float(torch.sqrt(torch.sum(wn * a * a)))
@@ -733,9 +733,9 @@ def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20, full_mesh:
         "workload": (f"3d-collision {'x'.join(map(str, w['nel']))} N={N} kappa={kappa:g} t_end={tend_run:.4g}; "
                      + ("every run on the full mesh" if full_mesh else
                         "accuracy on a held-out 48x24x24 collision (same element size), speed on the full mesh")),
-        "alpha": 200.0, "alpha_ref": 2000.0, "dt": dt_mod, "ratio": M, "dt_judge": dt_ref,
-        "steps": n_mod, "steps_judge": n_ref,
-        "judge_note": "errors are against the alpha = 2000 run in steps dt / ratio (the closure runs' fallback); "
+        "alpha": 200.0, "alpha_ref": 2000.0, "dt": dt_mod, "ratio": M, "dt_reference": dt_ref,
+        "steps": n_mod, "steps_reference": n_ref,
+        "reference_note": "errors are against the alpha = 2000 run in steps dt / ratio (the closure runs' fallback); "
                       "speed-ups against the plain alpha = 2000 run at its own step limit (plain_alpha2000)",
         **results,
         "value_note": "effective DOF-stage/s of the 96x48x48 mesh: DOF-stages of the plain alpha = 2000 run to "

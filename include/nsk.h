@@ -386,7 +386,8 @@ typedef struct {
   double e_last;             /* e_total at the last check of the closure run     */
 } nsk_closure_report;
 
-/* The closure run with the plain large-alpha run as its fallback and judge.
+/* The closure run with the plain large-alpha run as its fallback and as the
+ * reference its error is measured against.
  * Advances the bound state of cl (params.closure = 1, network set, model
  * II at the moderate alpha) by nsteps steps of dt, checking its diagnostics
  * every check_every steps and copying every state that passes into the

@@ -318,7 +318,7 @@ def test_closure_guards(gpu):
 def test_trained_closure_gains_over_plain_alpha200(gpu):
     """2D droplets, kappa = 1e-4: train on nudged alpha = 200 / 2000 pairs of
     three droplet configurations, then run a held-out configuration at
-    alpha = 200 with and without the closure; both are judged against the
+    alpha = 200 with and without the closure; both are measured against the
     plain alpha = 2000 run at the same time.
 
     The closure is trained to remove the density error of the moderate-alpha
