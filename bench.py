@@ -538,8 +538,8 @@ def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20, full_mesh:
 
     Accuracy: a held-out collision runs to t_end at alpha = 2000 (the reference),
     1000, 400 and 200, and at alpha = 200 with the closure (every stage, and
-    once per step) through nsk_closure_run, whose fallback is the alpha = 2000
-    run.  By default the held-out collision is a 48x24x24 one (We = 70,
+    once per step; FP64 and mixed-precision right-hand sides) through
+    nsk_closure_run, whose fallback is the FP64 alpha = 2000 run.  By default the held-out collision is a 48x24x24 one (We = 70,
     impact 0.03); with full_mesh it is the benchmark collision itself on
     96x48x48 (We = 100), and every run's time to t_end is measured.  Errors
     of rho against the alpha = 2000 run: the quadrature-weighted L2 over
@@ -643,8 +643,9 @@ def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20, full_mesh:
         s.close()
         return rho, ms, n
 
-    def with_closure(every_stage):
-        s = CL.closure_solver(net, norm, every_stage=every_stage, alpha=200.0, kappa=kappa, **mesh)
+    def with_closure(every_stage, precision=0):
+        s = CL.closure_solver(net, norm, every_stage=every_stage, alpha=200.0, kappa=kappa, precision=precision,
+                              **mesh)
         fb = nsk.Solver(alpha=2000.0, kappa=kappa, **mesh)
         s.set_state(U0)
         fb.set_state(U0)
@@ -680,9 +681,14 @@ def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20, full_mesh:
         rho, ms, n = plain(alpha)
         results[f"plain_alpha{int(alpha)}"] = dict(errors(rho), alpha=alpha, steps=n, ms_to_tend=ms)
         print(f"[bench] closure form: plain alpha={alpha:g} done", file=sys.stderr, flush=True)
-    for every_stage, name in ((1, "closure_alpha200"), (0, "closure_alpha200_once_per_step")):
-        rho, ms, rep = with_closure(every_stage)
-        results[name] = dict(errors(rho), alpha=200.0, steps=n_mod, ms_to_tend=ms, fallback_report=rep)
+    # the closure with FP64 and with mixed-precision right-hand sides (the
+    # alpha = 2000 fallback and reference stay FP64)
+    closure_runs = ((1, 0, "closure_alpha200"), (0, 0, "closure_alpha200_once_per_step"),
+                    (1, 1, "closure_alpha200_mixed"), (0, 1, "closure_alpha200_once_per_step_mixed"))
+    for every_stage, precision, name in closure_runs:
+        rho, ms, rep = with_closure(every_stage, precision)
+        results[name] = dict(errors(rho), alpha=200.0, steps=n_mod, ms_to_tend=ms, fallback_report=rep,
+                             precision="mixed" if precision else "fp64")
         print(f"[bench] closure form: {name} done (fell back: {rep['fell_back']})", file=sys.stderr, flush=True)
 
     # time per step on the full mesh (the speed-ups of the 48x24x24 runs)
@@ -702,11 +708,11 @@ def run_closure_form(nsk, tend: float = 0.01, timing_steps: int = 20, full_mesh:
             s = nsk.Solver(alpha=alpha, kappa=kappa, stream=torch.cuda.Stream(), **full)
             per_step[f"plain_alpha{int(alpha)}"] = ms_per_step(s, dt_mod if alpha == 200.0 else dt_ref)
             s.close()
-        for every_stage, name in ((1, "closure_alpha200"), (0, "closure_alpha200_once_per_step")):
-            s = CL.closure_solver(net, norm, every_stage=every_stage, alpha=200.0, kappa=kappa,
+        for every_stage, precision, name in closure_runs:
+            s = CL.closure_solver(net, norm, every_stage=every_stage, alpha=200.0, kappa=kappa, precision=precision,
                                   stream=torch.cuda.Stream(), **full)
             per_step[name] = ms_per_step(s, dt_mod)
-            if every_stage:
+            if every_stage and not precision:
                 s.set_state(Uf)
                 nsk.nsk_timing_enable(s.ctx, 1)
                 _timed_steps(s, dt_mod, timing_steps)
