@@ -391,10 +391,11 @@ def test_trained_closure_gains_over_plain_alpha200(gpu):
 # --------------------------------------------------------------------------
 # the closure run with the plain large-alpha run as fallback (nsk_closure_run)
 # --------------------------------------------------------------------------
-def _fallback_case(gpu, out_m, out_c=1e-3, nan_param=False, nel=16):
+def _fallback_case(gpu, out_m, out_c=1e-3, nan_param=False, nel=16, precision=0):
     """2D droplets (kappa = 1e-4, N = 3), an alpha = 200 closure context with
-    a seeded random network and output scales out_m, out_c, and the plain
-    alpha = 2000 context; returns them, the state and the step sizes."""
+    a seeded random network and output scales out_m, out_c (FP64 or mixed
+    right-hand sides), and the plain FP64 alpha = 2000 context; returns them,
+    the state and the step sizes."""
     import torch
 
     from paper_1912_12059_amd import closure as CL
@@ -409,7 +410,7 @@ def _fallback_case(gpu, out_m, out_c=1e-3, nan_param=False, nel=16):
         w[123] = np.nan
     net = CL.Network(params=w)
     norm = dict(CL.default_norm(kappa), out_m=out_m, out_c=out_c)
-    cl = CL.closure_solver(net, norm, alpha=200.0, kappa=kappa, **mesh)
+    cl = CL.closure_solver(net, norm, alpha=200.0, kappa=kappa, precision=precision, **mesh)
     ref = gpu.Solver(alpha=2000.0, kappa=kappa, **mesh)
     cl.set_state(U0)
     ref.set_state(U0)
@@ -441,22 +442,24 @@ def test_closure_run_falls_back_on_nonfinite_parameters(gpu):
     ref.close()
 
 
-def test_closure_run_falls_back_when_state_turns_nonphysical(gpu):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_closure_run_falls_back_when_state_turns_nonphysical(gpu, precision):
     """An output scale of 1e7 drives the closure run out of (0, 3); the run
-    continues on alpha = 2000 from the last state that passed a check, and
-    equals that split run done by hand."""
+    continues on FP64 alpha = 2000 from the last state that passed a check,
+    and equals that split run done by hand (closure context with FP64 or
+    mixed-precision right-hand sides)."""
     import torch
 
     from paper_1912_12059_amd import closure as CL
 
-    cl, ref, U0, dt, ratio, (net, norm, kappa, mesh) = _fallback_case(gpu, 1e7, 1e7)
+    cl, ref, U0, dt, ratio, (net, norm, kappa, mesh) = _fallback_case(gpu, 1e7, 1e7, precision=precision)
     rep = gpu.nsk_closure_run(cl.ctx, ref.ctx, dt, 40, ratio, 4)
     assert rep["fell_back"] == 1 and rep["reason"] == gpu.NSK_CLOSURE_NONPHYS
     k = rep["closure_steps"]
     assert k % 4 == 0 and k < 40 and rep["fallback_steps"] == (40 - k) * ratio
     got = cl.get_state()
     assert bool(torch.isfinite(got).all()) and cl.diagnostics()["status"] == 0
-    hand = CL.closure_solver(net, norm, alpha=200.0, kappa=kappa, **mesh)
+    hand = CL.closure_solver(net, norm, alpha=200.0, kappa=kappa, precision=precision, **mesh)
     hand.set_state(U0)
     hand.rk_step(dt, k)
     mid = hand.get_state().reshape(-1).clone()
@@ -482,17 +485,19 @@ def test_closure_run_falls_back_on_energy_growth(gpu):
     ref.close()
 
 
-def test_closure_run_keeps_a_sound_closure(gpu):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_closure_run_keeps_a_sound_closure(gpu, precision):
     """Small outputs: every check passes and the result is the closure run
-    itself, bit for bit."""
+    itself, bit for bit; with FP64 and with mixed-precision right-hand sides
+    in the closure context (the alpha = 2000 context stays FP64)."""
     import torch
 
     from paper_1912_12059_amd import closure as CL
 
-    cl, ref, U0, dt, ratio, (net, norm, kappa, mesh) = _fallback_case(gpu, 1e-3)
+    cl, ref, U0, dt, ratio, (net, norm, kappa, mesh) = _fallback_case(gpu, 1e-3, precision=precision)
     rep = gpu.nsk_closure_run(cl.ctx, ref.ctx, dt, 13, ratio, 5)
     assert rep["fell_back"] == 0 and rep["reason"] == gpu.NSK_CLOSURE_KEPT and rep["closure_steps"] == 13
-    hand = CL.closure_solver(net, norm, alpha=200.0, kappa=kappa, **mesh)
+    hand = CL.closure_solver(net, norm, alpha=200.0, kappa=kappa, precision=precision, **mesh)
     hand.set_state(U0)
     hand.rk_step(dt, 13)
     assert torch.equal(cl.get_state(), hand.get_state())
