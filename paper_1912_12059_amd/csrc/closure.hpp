@@ -80,6 +80,7 @@ struct ClosureShape {
   static constexpr int NN = ipow<NP, DIM>::v;
   static constexpr int EPB = (kClosureThreads / NN) > 0 ? kClosureThreads / NN : 1;
   static constexpr int SLOTS = EPB * NN;
+  static_assert(SLOTS <= kClosureThreads, "a workgroup takes whole elements, one thread per node");
 };
 
 // Element coordinates (x fastest).  A context holds at most 2^30 elements,
